@@ -1,0 +1,224 @@
+"""Benchmark of the matrix-free P1 apply on one MI355X.
+
+One step = one apply_stencil (y = A x, a single fused launch: interior rows
+of the macro plus its macro-boundary/Dirichlet rows) on the 2D workload:
+one macro triangle under a seeded random affine map, refinement level 14
+(134,242,305 DoFs, 1.07 GB per FP64 vector), x ~ U[-1,1) from the keyed
+generator.  Inputs are resident in HBM before timing starts.
+
+Prints ONE JSON line.  value = unique DoFs per second (GDoF/s) of the whole
+job.  roofline: algorithmic bytes (16 B/DoF: x read once, y written once)
+per launch / average launch time (HIP events on the launch stream), against
+the 8 TB/s HBM3E peak.  cpu_baseline: the oracle's CSR row loop on the host
+cores for a bounded sample.  extra: the FP32 apply, the 3D 6-tet cube apply,
+a device copy for reference, and the mixed-precision vs FP64 V-cycle solve.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_DOF_APPLY = {"f64": 16, "f32": 8}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_apply2d_l14.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2305_15116_amd", "csrc", "stencil_kernels.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def bench_apply(P, torch, co, ce, L, dtype, steps, warmup, seed):
+    m = P.create_macro_mesh(co, ce, L)
+    s, u = P.mesh_num_dofs(m, L)
+    x = torch.empty(s, dtype=dtype, device="cuda")
+    P.mesh_fill_random(m, L, seed, x)
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        P.apply_stencil(m, L, x, y, stream)
+    torch.cuda.synchronize()
+    # whole timed region: `steps` back-to-back applies
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        P.apply_stencil(m, L, x, y, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
+    # each launch bracketed by its own events, for the per-launch average and median
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        a.record(stream)
+        P.apply_stencil(m, L, x, y, stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    per = sorted(a.elapsed_time(b) for a, b in ev)
+    del x, y
+    P.destroy_macro_mesh(m)
+    return {"storage": s, "unique": u, "ms_per_step": total_ms / steps, "launch_avg_ms": sum(per) / len(per),
+            "launch_median_ms": per[len(per) // 2]}
+
+
+def copy_bandwidth(torch, nbytes=2 * 1024 ** 3, reps=20):
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def cpu_baseline(W, budget_s=20.0):
+    """The oracle's CSR row loop on all host cores for a bounded sample of the
+    same workload: the same affine triangle at level 11."""
+    from oracle.oracle import OracleMesh
+    co, ce = W.affine_triangle(2)
+    L = 11
+    t0 = time.time()
+    om = OracleMesh(co, ce, L)
+    om.csr(dirichlet=True)
+    t_build = time.time() - t0
+    nthreads = os.cpu_count() or 1
+    t, used = om.time_spmv(nthreads, 3, 5)
+    per = float(sorted(t)[len(t) // 2])
+    reps = max(10, min(400, int(budget_s / max(per, 1e-6))))
+    t, used = om.time_spmv(nthreads, 0, reps)
+    med = float(sorted(t)[len(t) // 2])
+    return {"value": om.n / med / 1e9, "unit": "GDoF/s", "cores": int(used), "kind": "oracle",
+            "sample": f"same affine triangle at level {L} ({om.n} DoFs): CSR row loop y = A x, median of {reps} "
+                      f"reps on {used} threads; CSR assembly ({t_build:.1f} s) excluded",
+            "csr_GBps": (om.n * 8 * 2 + om.csr().nnz * 16 + (om.n + 1) * 8) / med / 1e9}
+
+
+def traffic_for(kernel_hash):
+    try:
+        d = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha256") != kernel_hash:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def solve_bench(P, torch, W, L=8, repeats=10):
+    co, ce = W.kuhn_cube()
+    m = P.create_macro_mesh(co, ce, L)
+    s, _ = P.mesh_num_dofs(m, L)
+    # b = lumped load of f = 3 pi^2 sin(pi x) sin(pi y) sin(pi z): on this mesh the
+    # lumped mass is h^3 at every DoF; built here from the DoF coordinates.
+    v, w = P.mesh_dof_keys(m, L)
+    import numpy as np
+    N = 1 << L
+    xyz = np.zeros((s, 3))
+    for k in range(4):
+        ok = v[:, k] >= 0
+        xyz[ok] += (w[ok, k:k + 1] / N) * co[v[ok, k]]
+    h = 1.0 / N
+    f = 3 * np.pi ** 2 * np.prod(np.sin(np.pi * xyz), axis=1)
+    b = torch.as_tensor(h ** 3 * f, device="cuda")
+    out = {}
+    for mode in (0, 1):
+        ws = torch.empty(P.mesh_workspace_bytes(m, L, mode), dtype=torch.uint8, device="cuda")
+        x = torch.zeros(s, dtype=torch.float64, device="cuda")
+        rc, it, rel, sec = P.vcycle_solve(m, L, b, x, ws, mode=mode, rtol=1e-10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(repeats):
+            x.zero_()
+            rc, it, rel, sec = P.vcycle_solve(m, L, b, x, ws, mode=mode, rtol=1e-10)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / repeats
+        uh = np.prod(np.sin(np.pi * xyz), axis=1) * (np.pi ** 2 * h ** 2 / 4) / np.sin(np.pi * h / 2) ** 2
+        err = float(np.abs(x.cpu().numpy() - uh).max())
+        out["mixed" if mode else "fp64"] = {"status": rc, "iters": it, "rel_res": rel, "ms_per_solve": dt * 1e3,
+                                            "solves_per_s": 1.0 / dt, "max_err_vs_discrete_solution": err}
+    P.destroy_macro_mesh(m)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-extra", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the macro-parallel multi-GPU path is not built "
+              "(every GPU box here has one GPU); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2305_15116_amd as P
+    from paper_2305_15116_amd import workloads as W
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    P.lib()
+
+    co, ce = W.affine_triangle(2)
+    L = 14
+    log(f"apply 2D level {L} fp64: {args.warmup} warmup + {args.steps} timed")
+    r64 = bench_apply(P, torch, co, ce, L, torch.float64, args.steps, args.warmup, 3)
+    gdofs = r64["unique"] / (r64["ms_per_step"] * 1e-3) / 1e9
+    bytes_launch = BYTES_PER_DOF_APPLY["f64"] * r64["unique"]
+    achieved = bytes_launch / (r64["launch_avg_ms"] * 1e-3) / 1e9
+    khash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(khash),
+                "kernel": "stencil_kernel<double,2,apply>", "algorithmic_bytes_per_launch": bytes_launch,
+                "launch_avg_ms": r64["launch_avg_ms"], "launch_median_ms": r64["launch_median_ms"]}
+    extra = {}
+    if not args.skip_extra:
+        log("apply 2D level 14 fp32")
+        r32 = bench_apply(P, torch, co, ce, L, torch.float32, args.steps, args.warmup, 3)
+        extra["apply2d_l14_fp32"] = {"GDoF_s": r32["unique"] / (r32["launch_avg_ms"] * 1e-3) / 1e9,
+                                     "GB_s": 8 * r32["unique"] / (r32["launch_avg_ms"] * 1e-3) / 1e9,
+                                     "launch_avg_ms": r32["launch_avg_ms"]}
+        for L3 in (8, 9):
+            log(f"apply 3D cube level {L3} fp64")
+            r3 = bench_apply(P, torch, *W.kuhn_cube(), L3, torch.float64, args.steps, args.warmup, 4)
+            extra[f"apply3d_cube_l{L3}_fp64"] = {
+                "GDoF_s": r3["unique"] / (r3["launch_avg_ms"] * 1e-3) / 1e9,
+                "GB_s_storage": 16 * r3["storage"] / (r3["launch_avg_ms"] * 1e-3) / 1e9,
+                "launch_avg_ms": r3["launch_avg_ms"], "storage": r3["storage"], "unique": r3["unique"]}
+        log("device copy reference")
+        cbw = copy_bandwidth(torch)
+        extra["device_copy_GBps"] = cbw
+        extra["apply2d_frac_of_copy"] = achieved / cbw
+        log("C4 solve: mixed vs fp64")
+        extra["solve_cube_l8"] = solve_bench(P, torch, W)
+    cpu = None
+    if not args.skip_cpu:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(W)
+    line = {
+        "metric": "stencil-apply GDoF/s & % HBM peak; batched-solve p50/p99 latency vs plain",
+        "value": round(gdofs, 3), "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": r64["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "2D FP64 apply, one macro triangle under a seeded affine map (cond <= 10), level 14",
+                   "dofs": r64["unique"], "level": L, "macros": 1},
+        "roofline": roofline, "cpu_baseline": cpu, "extra": extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,180 @@
+/* mf_stencil.h — C ABI of the MI355X matrix-free P1 stencil library.
+ *
+ * The operator is the P1 finite-element Laplacian on a mesh of macro
+ * triangles (2D) or tetrahedra (3D), each uniformly refined `level` times
+ * (paper: Intro, "Hybrid Tetrahedral Grids"; the number of refinements is the
+ * level).  Inside one macro every interior row of the matrix is the same
+ * stencil — 7 points in 2D (the Vertex-to-Vertex kernel of the Performance
+ * Modeling section), 15 points in 3D (the paper's stated next step in its
+ * Conclusion and Outlook) — so the matrix is never stored (PETSc comparison
+ * section, theoretical analysis).  Rows of DoFs on macro boundaries are
+ * completed by interface handling between macros, which the paper assigns to
+ * dedicated interface primitives rather than to the face kernels (Performance
+ * Modeling, experiment description).  Domain-boundary DoFs get identity rows
+ * (Dirichlet).
+ *
+ * Conventions shared by every call
+ *  - All functions are extern "C", never throw, and return an int status
+ *    (MF_OK = 0; negative = error, message in mf_last_error()).
+ *  - Pointers named *_dev are device pointers on the current HIP device;
+ *    host pointers are named without suffix.  `stream` is a hipStream_t
+ *    (NULL = the default stream).  The caller owns every vector and workspace
+ *    it passes; the library owns the mesh metadata (host and device) until
+ *    destroy_macro_mesh.
+ *  - Vectors are in STORAGE layout: the closed index space of every macro,
+ *    concatenated in cell order.  In 2D the point (x, y), x, y >= 0,
+ *    x + y <= N, N = 2^level, sits at y(N+2) - y(y+1)/2 + x of its macro (rows
+ *    of N+1-y points, x fastest — the layout of the paper's generated
+ *    vertex-to-vertex kernel).  In 3D slice z is the 2D triangle of side
+ *    M = N - z, stored after slices 0..z-1: offset Tet(N+1) - Tet(N+1-z),
+ *    Tet(n) = n(n+1)(n+2)/6.  DoFs on shared macro boundaries are stored once
+ *    per macro; every function keeps all copies equal.
+ *  - dtype MF_F64 = double vectors, MF_F32 = float vectors.
+ *  - apply_stencil, smooth and residual (without a norm) are asynchronous on
+ *    `stream`.  The mesh is read-only after creation, so calls on different
+ *    streams with different buffers may overlap.
+ */
+#ifndef MF_STENCIL_H
+#define MF_STENCIL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mf_mesh mf_mesh;
+
+enum {
+  MF_OK = 0,
+  MF_NOT_CONVERGED = 1, /* vcycle_solve hit max_iter; x holds the last iterate */
+  MF_EINVAL = -1,       /* bad argument: dim, null pointer, level range, degenerate or non-conforming mesh, dtype */
+  MF_ENOMEM = -2,       /* host or device allocation failed, or a request exceeds a size limit */
+  MF_EDEVICE = -3,      /* a HIP call failed; mf_last_error() holds hipGetErrorString */
+  MF_ENOTSUP = -4,      /* valid but unsupported (e.g. device call on a host-only mesh) */
+  MF_ENUMERIC = -5      /* a norm came out non-finite */
+};
+
+enum { MF_F64 = 0, MF_F32 = 1 };
+
+enum {
+  MF_FLAG_DIRICHLET = 1, /* bit0: every domain-boundary DoF is Dirichlet (identity row); set by default */
+  MF_FLAG_HOST_ONLY = 2  /* bit1: build the host metadata only (no device memory); device calls return MF_ENOTSUP */
+};
+
+/* Thread-local message of the last error on this thread ("" if none). */
+const char* mf_last_error(void);
+
+/* Build a macro mesh and all per-level metadata up to max_level (0..15 in 2D,
+ * 0..11 in 3D).
+ *   coords: host, n_vertices*dim doubles.  cells: host, n_cells*(dim+1)
+ *   vertex ids; the vertex order of a cell defines its index space
+ *   (F(xi) = P0 + [P1-P0 | P2-P0 (| P3-P0)] xi, xi = lattice point / N).
+ *   flags: MF_FLAG_* (pass MF_FLAG_DIRICHLET for the usual case).
+ * Errors: MF_EINVAL for dim not 2/3, null pointers, vertex ids out of range,
+ * a degenerate cell (|det J| <= 1e-14 * scale^dim), a repeated cell or a facet
+ * shared by more than two cells; MF_ENOMEM / MF_EDEVICE on allocation or
+ * upload failure.  On success *out owns host and device memory. */
+int create_macro_mesh(int dim, int64_t n_vertices, const double* coords, int64_t n_cells,
+                      const int64_t* cells, int max_level, int flags, mf_mesh** out);
+
+/* Free everything the mesh owns.  NULL is accepted. */
+int destroy_macro_mesh(mf_mesh* mesh);
+
+/* Mesh facts: dimension, number of macros, maximum level. */
+int mesh_info(const mf_mesh* mesh, int* dim, int64_t* n_macros, int* max_level);
+
+/* Storage DoFs (length of a vector) and unique DoFs (shared copies counted once). */
+int mesh_num_dofs(const mf_mesh* mesh, int level, int64_t* storage, int64_t* unique);
+
+/* Exact integer key of every storage DoF (host arrays of storage*(dim+1)):
+ * the (global vertex id, barycentric weight) pairs with non-zero weight,
+ * sorted by vertex id, padded with (-1, 0).  Weights sum to N.  Copies of a
+ * shared DoF have equal keys. */
+int mesh_dof_keys(const mf_mesh* mesh, int level, int64_t* vids, int32_t* weights);
+
+/* Storage index of n points given as (macro, x, y[, z]) rows (host arrays,
+ * n*(dim+1) int64 in, n int64 out).  MF_EINVAL if a point lies outside its macro. */
+int mesh_dof_index(const mf_mesh* mesh, int level, int64_t n, const int64_t* macro_lattice, int64_t* index);
+
+/* The interior stencil of one macro at one level (host, 7 or 15 doubles).
+ * 2D order: S, SE, W, C, E, NW, N (offsets (0,-1),(1,-1),(-1,0),(0,0),(1,0),(-1,1),(0,1)),
+ * the weight order of the paper's generated vertex-to-vertex kernel.
+ * 3D order: (0,0,-1),(1,0,-1),(0,1,-1),(-1,1,-1), the seven in-slice offsets
+ * in the 2D order, then (0,-1,1),(1,-1,1),(-1,0,1),(0,0,1). */
+int mesh_stencil(const mf_mesh* mesh, int level, int64_t macro, double* weights);
+
+/* Bytes of device workspace vcycle_solve needs at `level` for mode 0 (all
+ * FP64) or 1 (FP32 V-cycle inside FP64 iterative refinement). */
+int mesh_workspace_bytes(const mf_mesh* mesh, int level, int mode, int64_t* bytes);
+
+/* Fill a storage vector with x = 2u - 1, u uniform in [0,1) from SplitMix64
+ * (Steele, Lea, Flood, OOPSLA 2014) chained over (seed, key pairs): a seeded
+ * U[-1,1) input that is equal on all copies of a shared DoF.  Asynchronous.
+ * Test-input helper; no part of the operator. */
+int mesh_fill_random(const mf_mesh* mesh, int level, int dtype, uint64_t seed, void* x_dev, void* stream);
+
+/* y = A x (paper: the "apply", i.e. an operator applied to a function,
+ * Performance Modeling section).  Interior rows of each macro use its
+ * constant stencil; macro-boundary rows are summed over the copies' partial
+ * rows and written to every copy; Dirichlet rows give y = x.  y is
+ * overwritten and must not alias x.  Asynchronous. */
+int apply_stencil(const mf_mesh* mesh, int level, int dtype, const void* x_dev, void* y_dev, void* stream);
+
+/* `sweeps` weighted-Jacobi sweeps x <- x + omega D^-1 (b - A x) (the
+ * multigrid smoother the paper names as a code-generated operation,
+ * Performance Modeling section).  D is the assembled diagonal.  Dirichlet DoFs
+ * are left unchanged.  tmp_dev is a vector of the same size used for
+ * ping-pong; the result is in x_dev.  Asynchronous. */
+int smooth(const mf_mesh* mesh, int level, int dtype, double omega, int sweeps, const void* b_dev,
+           void* x_dev, void* tmp_dev, void* stream);
+
+/* r = b - A x (Dirichlet rows: r = b - x).  If norm2 is non-NULL, also
+ * ||r||_2 over unique DoFs, accumulated in FP64 in a fixed order (bitwise
+ * reproducible); this synchronises `stream` and returns MF_ENUMERIC if the
+ * norm is not finite. */
+int residual(const mf_mesh* mesh, int level, int dtype, const void* b_dev, const void* x_dev, void* r_dev,
+             double* norm2, void* stream);
+
+/* Multigrid restriction r_c = P^T r_f from `level` to `level`-1, where P is
+ * the P1 interpolation between the nested refinement levels (the paper
+ * names the levels a natural basis for multigrid, Intro, "Hybrid Tetrahedral
+ * Grids").  Each macro sums the fine values it owns (weight 1 at the
+ * coincident point, 1/2 at the midpoints of the coarse micro-edges through
+ * it), then copies of shared coarse DoFs are summed; Dirichlet coarse DoFs
+ * get 0.  rf_dev: vector at `level`; bc_dev: vector at `level`-1
+ * (overwritten).  level >= 1.  Asynchronous. */
+int restrict_residual(const mf_mesh* mesh, int level, int dtype, const void* rf_dev, void* bc_dev, void* stream);
+
+/* x_f += P e_c from `level`-1 to `level` (the interpolation above);
+ * Dirichlet fine DoFs are left unchanged.  ec_dev: vector at `level`-1;
+ * xf_dev: vector at `level`.  level >= 1.  Asynchronous. */
+int prolong_add(const mf_mesh* mesh, int level, int dtype, const void* ec_dev, void* xf_dev, void* stream);
+
+typedef struct {
+  int mode;         /* 0: all-FP64 V-cycles; 1: FP32 V-cycles + FP64 residual and update */
+  int pre, post;    /* smoothing sweeps (default 2, 2) */
+  int coarse_level; /* solved directly (default min(2, level)) */
+  int max_iter;     /* outer iterations (default 50) */
+  double omega;     /* Jacobi weight (default 2/3) */
+  double rtol;      /* stop when ||b - A x||_2 / ||b||_2 <= rtol over unique DoFs */
+} mf_solve_opts;
+
+typedef struct {
+  int iters;
+  double rel_res;
+  double seconds;
+} mf_solve_info;
+
+/* Solve A x = b by V(pre,post)-cycles of geometric multigrid (levels are the
+ * refinement hierarchy, Intro) inside iterative refinement.  x_dev holds the
+ * initial guess (its Dirichlet entries are set to b's); workspace_dev must
+ * hold mesh_workspace_bytes(level, opts->mode) bytes.  Returns MF_OK,
+ * MF_NOT_CONVERGED (x = last iterate) or an error.  Synchronous. */
+int vcycle_solve(const mf_mesh* mesh, int level, const double* b_dev, double* x_dev, void* workspace_dev,
+                 const mf_solve_opts* opts, mf_solve_info* info, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -25,8 +25,8 @@
 //     (0,1,0)-(1,0,1) diagonal; "down" tets a+{(1,1,0),(1,0,1),(0,1,1),(1,1,1)}.
 //     This is Bey's tetrahedral refinement written in index space (the paper
 //     is 2D only and leaves 3D to future work, Conclusion and Outlook).
-//  3. Element stiffness K = |T| G^T G from the physical micro-vertex
-//     coordinates, G = barycentric gradients (solve with the edge vectors).
+//  3. Element stiffness K = |T| G^T G from the physical micro-element edge
+//     vectors, G = barycentric gradients (solve with the edge vectors).
 //  4. Assembly COO -> CSR, duplicates summed, explicit zeros kept.
 //  5. Dirichlet boundary: DoFs on macro facets with exactly one adjacent cell
 //     get identity rows; other rows keep their boundary columns.
@@ -92,18 +92,6 @@ void weights_of(int dim, int64_t N, const int64_t* p, int64_t* w) {
   int64_t s = 0;
   for (int k = 0; k < dim; ++k) { w[k + 1] = p[k]; s += p[k]; }
   w[0] = N - s;
-}
-
-// Physical coordinates: sum_k (w_k / N) * X(v_k).
-void point_coords(int dim, const double* coords, const int64_t* cellv, int64_t N,
-                  const int64_t* p, double* X) {
-  int64_t w[MAXV];
-  weights_of(dim, N, p, w);
-  for (int r = 0; r < dim; ++r) {
-    double s = 0.0;
-    for (int k = 0; k <= dim; ++k) s += ((double)w[k] / (double)N) * coords[cellv[k] * dim + r];
-    X[r] = s;
-  }
 }
 
 // ---- SplitMix64 (Steele, Lea, Flood: "Fast splittable pseudorandom number
@@ -178,13 +166,31 @@ void for_each_element(int dim, int64_t N, const int64_t* lo, const int64_t* hi, 
 }
 
 // ---- Step 3: element stiffness from physical vertex coordinates.
+// Edge vectors X_k - X_0 are formed from the exact integer differences of the
+// vertices' barycentric weights, sum_j ((w_kj - w_0j) / N) P_j, so that they
+// carry full relative precision at any level (subtracting two absolute
+// coordinates would lose about log10(N) digits to cancellation).
+void edge_matrix(int dim, const double* coords, const int64_t* cellv, int64_t N, int64_t (*v)[3],
+                 double E[3][3]) {
+  int64_t w0[MAXV];
+  weights_of(dim, N, v[0], w0);
+  for (int c = 0; c < 3; ++c)
+    for (int r = 0; r < 3; ++r) E[r][c] = 0.0;
+  for (int c = 0; c < dim; ++c) {
+    int64_t wk[MAXV];
+    weights_of(dim, N, v[c + 1], wk);
+    for (int r = 0; r < dim; ++r) {
+      double s = 0.0;
+      for (int j = 0; j <= dim; ++j) s += ((double)(wk[j] - w0[j]) / (double)N) * coords[cellv[j] * dim + r];
+      E[r][c] = s;
+    }
+  }
+}
+
 // E = [X1-X0 | .. | Xd-X0]; lambda_{1..d} = E^{-1}(x - X0), so grad lambda_k
 // is row k of E^{-1}; grad lambda_0 = -sum of the others; |T| = |det E| / d!.
 // Returns false for a degenerate element.
-bool element_stiffness(int dim, const double X[MAXV][3], double K[MAXV][MAXV], double* vol) {
-  double E[3][3] = {{0}};
-  for (int c = 0; c < dim; ++c)
-    for (int r = 0; r < dim; ++r) E[r][c] = X[c + 1][r] - X[0][r];
+bool element_stiffness(int dim, const double E[3][3], double K[MAXV][MAXV], double* vol) {
   double inv[3][3] = {{0}};
   double det;
   if (dim == 2) {
@@ -409,14 +415,12 @@ int64_t or_elements(const or_mesh* m, int64_t* out) {
 }
 
 namespace {
-// Physical coordinates of a micro-element's vertices and their unique ids.
-void element_data(const or_mesh* m, int64_t c, int64_t (*v)[3], double X[MAXV][3], int64_t* ids) {
+// Edge matrix of a micro-element and the unique ids of its vertices.
+void element_data(const or_mesh* m, int64_t c, int64_t (*v)[3], double E[3][3], int64_t* ids) {
   const int64_t* cv = &m->cells[c * (m->dim + 1)];
   const int64_t* L = &m->lat[c * m->lat_stride];
-  for (int i = 0; i <= m->dim; ++i) {
-    point_coords(m->dim, m->coords.data(), cv, m->N, v[i], X[i]);
-    ids[i] = L[lat_index(m->dim, m->N, v[i])];
-  }
+  edge_matrix(m->dim, m->coords.data(), cv, m->N, v, E);
+  for (int i = 0; i <= m->dim; ++i) ids[i] = L[lat_index(m->dim, m->N, v[i])];
 }
 }  // namespace
 
@@ -438,10 +442,10 @@ int64_t or_assemble(or_mesh* m, int dirichlet) {
   bool bad = false;
   for (int64_t c = 0; c < m->nc; ++c) {
     for_each_cell_element(m, c, [&](int64_t (*v)[3]) {
-      double X[MAXV][3], K[MAXV][MAXV], vol;
+      double E[3][3], K[MAXV][MAXV], vol;
       int64_t ids[MAXV];
-      element_data(m, c, v, X, ids);
-      if (!element_stiffness(m->dim, X, K, &vol)) { bad = true; return; }
+      element_data(m, c, v, E, ids);
+      if (!element_stiffness(m->dim, E, K, &vol)) { bad = true; return; }
       for (int i = 0; i < d1; ++i)
         for (int j = 0; j < d1; ++j) {
           const int64_t at = fill[ids[i]]++;
@@ -502,10 +506,10 @@ int or_apply_elementwise(const or_mesh* m, int dirichlet, const double* x, doubl
   bool bad = false;
   for (int64_t c = 0; c < m->nc; ++c) {
     for_each_cell_element(m, c, [&](int64_t (*v)[3]) {
-      double X[MAXV][3], K[MAXV][MAXV], vol;
+      double E[3][3], K[MAXV][MAXV], vol;
       int64_t ids[MAXV];
-      element_data(m, c, v, X, ids);
-      if (!element_stiffness(m->dim, X, K, &vol)) { bad = true; return; }
+      element_data(m, c, v, E, ids);
+      if (!element_stiffness(m->dim, E, K, &vol)) { bad = true; return; }
       for (int i = 0; i < d1; ++i) {
         double s = 0.0;
         for (int j = 0; j < d1; ++j) s += K[i][j] * x[ids[j]];
@@ -527,10 +531,10 @@ int or_lumped_mass(const or_mesh* m, double* mass) {
   bool bad = false;
   for (int64_t c = 0; c < m->nc; ++c) {
     for_each_cell_element(m, c, [&](int64_t (*v)[3]) {
-      double X[MAXV][3], K[MAXV][MAXV], vol;
+      double E[3][3], K[MAXV][MAXV], vol;
       int64_t ids[MAXV];
-      element_data(m, c, v, X, ids);
-      if (!element_stiffness(m->dim, X, K, &vol)) { bad = true; return; }
+      element_data(m, c, v, E, ids);
+      if (!element_stiffness(m->dim, E, K, &vol)) { bad = true; return; }
       for (int i = 0; i < d1; ++i) mass[ids[i]] += vol / d1;
     });
   }
@@ -588,19 +592,36 @@ int or_sample_rows(int dim, int64_t nv, const double* coords, int64_t nc, const 
           if (eq) me = i;
         }
         if (me < 0) return;
-        double X[MAXV][3], K[MAXV][MAXV], vol;
+        double E[3][3], K[MAXV][MAXV], vol;
         double xv[MAXV];
         for (int i = 0; i < d1; ++i) {
-          point_coords(dim, coords, cv2, N, v[i], X[i]);
           int64_t wi[MAXV];
           weights_of(dim, N, v[i], wi);
           xv[i] = keyed_value(seed, make_key(dim, cv2, wi));
         }
-        element_stiffness(dim, X, K, &vol);
+        edge_matrix(dim, coords, cv2, N, v, E);
+        element_stiffness(dim, E, K, &vol);
         for (int j = 0; j < d1; ++j) acc += K[me][j] * xv[j];
       });
     }
     y[s] = acc;
+  }
+  return 0;
+}
+
+// Keyed input values x(key) at (cell, lattice point) pairs, without a global build.
+int or_keyed_points(int dim, int64_t nc, const int64_t* cells, int level, uint64_t seed, int64_t ns,
+                    const int64_t* sample_cell, const int64_t* sample_lat, double* out) {
+  const int64_t N = int64_t(1) << level;
+  for (int64_t s = 0; s < ns; ++s) {
+    const int64_t c = sample_cell[s];
+    if (c < 0 || c >= nc) { g_err = "sample cell out of range"; return -1; }
+    int64_t p[3] = {0, 0, 0}, w[MAXV];
+    for (int k = 0; k < dim; ++k) p[k] = sample_lat[s * dim + k];
+    weights_of(dim, N, p, w);
+    for (int k = 0; k <= dim; ++k)
+      if (w[k] < 0) { g_err = "sample point outside its macro"; return -1; }
+    out[s] = keyed_value(seed, make_key(dim, cells + c * (dim + 1), w));
   }
   return 0;
 }

@@ -55,6 +55,8 @@ def lib():
         L.or_sample_rows.restype = C.c_int
         L.or_sample_rows.argtypes = [C.c_int, C.c_int64, f64p, C.c_int64, i64p, C.c_int, C.c_int,
                                      C.c_uint64, C.c_int64, i64p, i64p, f64p, i8p]
+        L.or_keyed_points.restype = C.c_int
+        L.or_keyed_points.argtypes = [C.c_int, C.c_int64, i64p, C.c_int, C.c_uint64, C.c_int64, i64p, i64p, f64p]
         L.or_prolongation.restype = C.c_int64
         L.or_prolongation.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.or_time_spmv.restype = C.c_int
@@ -203,6 +205,17 @@ def sample_rows(coords, cells, level: int, seed: int, sample_cell, sample_lat, d
     if r != 0:
         raise ValueError(_err())
     return y, b.astype(bool)
+
+
+def keyed_points(cells, dim: int, level: int, seed: int, sample_cell, sample_lat):
+    """Keyed input values at sampled (cell, lattice point) pairs."""
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    sc = np.ascontiguousarray(sample_cell, dtype=np.int64)
+    sl = np.ascontiguousarray(sample_lat, dtype=np.int64).ravel()
+    out = np.empty(sc.shape[0])
+    if lib().or_keyed_points(dim, cells.shape[0], cells.ravel(), level, seed, sc.shape[0], sc, sl, out) != 0:
+        raise ValueError(_err())
+    return out
 
 
 def solve(mesh: OracleMesh, b, tol: float = 1e-13, maxiter: int = 100000):

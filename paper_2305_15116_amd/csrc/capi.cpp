@@ -1,0 +1,401 @@
+// extern "C" entry points (include/mf_stencil.h) and the multigrid solver.
+//
+// apply_stencil is the paper's "apply" (an operator applied to a function,
+// Performance Modeling section): the interior kernel covers every interior
+// row of every macro with its constant stencil, then the interface kernel
+// completes the rows of macro-boundary DoFs, which the paper leaves to
+// interface primitives rather than to the macro kernels (same section,
+// experiment description).  smooth and residual reuse the same kernels in
+// their fused Jacobi and residual modes; vcycle_solve runs geometric
+// multigrid over the refinement levels (Intro: the levels are a natural
+// multigrid hierarchy) inside iterative refinement.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "mf_stencil.h"
+#include "launch.hpp"
+#include "mesh.hpp"
+
+using namespace mf;
+
+namespace {
+
+int check_mesh(const mf_mesh* m, int level, bool device) {
+  if (!m) return set_error(MF_EINVAL, "mesh is NULL");
+  if (level < 0 || level > m->max_level)
+    return set_error(MF_EINVAL, "level " + std::to_string(level) + " outside [0, " + std::to_string(m->max_level) + "]");
+  if (device && m->host_only) return set_error(MF_ENOTSUP, "mesh was created host-only");
+  return MF_OK;
+}
+
+int check_dtype(int dtype) {
+  if (dtype != MF_F64 && dtype != MF_F32) return set_error(MF_EINVAL, "dtype must be MF_F64 or MF_F32");
+  return MF_OK;
+}
+
+int sync_result(const double* result_dev, double out[2], hipStream_t s) {
+  hipError_t e = hipMemcpyAsync(out, result_dev, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return set_error(MF_EDEVICE, hipGetErrorString(e));
+  return MF_OK;
+}
+
+// r = b - A x with partials in `part`; reduces to result_dev and copies back.
+int residual_norm(const mf_mesh* m, const Level& L, int dtype, const void* b, const void* x, void* r, double* part,
+                  double* result_dev, double* ss, double* mx, hipStream_t s) {
+  const int64_t np = L.n_partials();
+  int rc = launch_stencil(m, L, dtype, kResidual, x, r, b, 0.0, part, s);
+  if (!rc) rc = launch_reduce(part, np, result_dev, s);
+  double out[2] = {0.0, 0.0};
+  if (!rc) rc = sync_result(result_dev, out, s);
+  if (rc) return rc;
+  *ss = out[0];
+  *mx = out[1];
+  if (!std::isfinite(out[0]) || !std::isfinite(out[1])) return set_error(MF_ENUMERIC, "residual norm is not finite");
+  return MF_OK;
+}
+
+// sum of squares and max |.| of b over unique DoFs
+int vector_norm(const mf_mesh* m, const Level& L, int dtype, const void* b, double* part, double* result_dev,
+                double* ss, double* mx, hipStream_t s) {
+  const int64_t np = L.n_partials();
+  int rc = launch_stencil(m, L, dtype, kNormB, b, nullptr, b, 0.0, part, s);
+  if (!rc) rc = launch_reduce(part, np, result_dev, s);
+  double out[2] = {0.0, 0.0};
+  if (!rc) rc = sync_result(result_dev, out, s);
+  if (rc) return rc;
+  *ss = out[0];
+  *mx = out[1];
+  if (!std::isfinite(out[0])) return set_error(MF_ENUMERIC, "norm of b is not finite");
+  return MF_OK;
+}
+
+int jacobi_sweeps(const mf_mesh* m, const Level& L, int dtype, double omega, int sweeps, const void* b, void* x,
+                  void* tmp, hipStream_t s) {
+  void* cur = x;
+  void* oth = tmp;
+  for (int i = 0; i < sweeps; ++i) {
+    const int rc = launch_stencil(m, L, dtype, kJacobi, cur, oth, b, omega, nullptr, s);
+    if (rc) return rc;
+    std::swap(cur, oth);
+  }
+  if (cur != x) return launch_copy(dtype, x, cur, L.storage, s);
+  return MF_OK;
+}
+
+constexpr int64_t kAlign = 256;
+int64_t align_up(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Workspace {
+  std::vector<void*> b, x, t;  // per level
+  double* r64 = nullptr;
+  double* e64 = nullptr;
+  double* t64 = nullptr;
+  double* part = nullptr;
+  double* result = nullptr;
+  int64_t bytes = 0;
+};
+
+// Carves the workspace (base may be null to only measure it).
+Workspace carve(const mf_mesh* m, int level, int mode, int lc, char* base) {
+  Workspace w;
+  int64_t off = 0;
+  auto take = [&](int64_t nbytes) -> void* {
+    void* p = base ? (void*)(base + off) : nullptr;
+    off += align_up(nbytes);
+    return p;
+  };
+  const int64_t SL = m->levels[level].storage;
+  w.b.assign(level + 1, nullptr);
+  w.x.assign(level + 1, nullptr);
+  w.t.assign(level + 1, nullptr);
+  w.r64 = (double*)take(8 * SL);
+  if (mode == 0) {
+    w.e64 = (double*)take(8 * SL);
+    w.t64 = (double*)take(8 * SL);
+    w.b[level] = w.r64;
+    w.x[level] = w.e64;
+    w.t[level] = w.t64;
+    for (int l = lc; l < level; ++l) {
+      const int64_t S = m->levels[l].storage;
+      w.b[l] = take(8 * S);
+      w.x[l] = take(8 * S);
+      w.t[l] = take(8 * S);
+    }
+  } else {
+    for (int l = lc; l <= level; ++l) {
+      const int64_t S = m->levels[l].storage;
+      w.b[l] = take(4 * S);
+      w.x[l] = take(4 * S);
+      w.t[l] = take(4 * S);
+    }
+  }
+  w.part = (double*)take(8 * 2 * (m->levels[level].n_partials() + 1));
+  w.result = (double*)take(8 * 2);
+  w.bytes = off;
+  return w;
+}
+
+int vcycle(const mf_mesh* m, int l, int lc, int dtype, const Workspace& w, const mf_solve_opts& o, hipStream_t s) {
+  const Level& L = m->levels[l];
+  if (l == lc) return launch_coarse_solve(L, dtype, w.b[l], w.x[l], s);
+  int rc = jacobi_sweeps(m, L, dtype, o.omega, o.pre, w.b[l], w.x[l], w.t[l], s);
+  if (rc) return rc;
+  rc = launch_stencil(m, L, dtype, kResidual, w.x[l], w.t[l], w.b[l], 0.0, nullptr, s);
+  if (!rc) rc = launch_restrict(m, L, m->levels[l - 1], dtype, w.t[l], w.b[l - 1], s);
+  if (!rc) rc = launch_fill(dtype, w.x[l - 1], 0.0, m->levels[l - 1].storage, s);
+  if (!rc) rc = vcycle(m, l - 1, lc, dtype, w, o, s);
+  if (!rc) rc = launch_prolong_add(m, L, m->levels[l - 1], dtype, w.x[l - 1], w.x[l], s);
+  if (!rc) rc = jacobi_sweeps(m, L, dtype, o.omega, o.post, w.b[l], w.x[l], w.t[l], s);
+  return rc;
+}
+
+int default_coarse(int level) { return std::min(2, level); }
+
+}  // namespace
+
+extern "C" {
+
+const char* mf_last_error(void) { return mf::last_error(); }
+
+int create_macro_mesh(int dim, int64_t n_vertices, const double* coords, int64_t n_cells, const int64_t* cells,
+                      int max_level, int flags, mf_mesh** out) {
+  if (!out) return set_error(MF_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (dim != 2 && dim != 3) return set_error(MF_EINVAL, "dim must be 2 or 3");
+  if (!coords || !cells || n_vertices <= 0 || n_cells <= 0) return set_error(MF_EINVAL, "empty or NULL mesh arrays");
+  const int lmax = dim == 2 ? 15 : 11;
+  if (max_level < 0 || max_level > lmax)
+    return set_error(MF_EINVAL, "max_level must be in [0, " + std::to_string(lmax) + "]");
+  if (n_cells > (int64_t)1 << 30) return set_error(MF_EINVAL, "too many cells");
+  mf_mesh* m = nullptr;
+  try {
+    m = new mf_mesh;
+    m->dim = dim;
+    m->max_level = max_level;
+    m->flags = flags;
+    m->host_only = (flags & MF_FLAG_HOST_ONLY) != 0;
+    m->nv = n_vertices;
+    m->nc = n_cells;
+    m->coords.assign(coords, coords + n_vertices * dim);
+    m->cells.assign(cells, cells + n_cells * (dim + 1));
+    const int rc = build_mesh(m);
+    if (rc) {
+      free_device(m);
+      delete m;
+      return rc;
+    }
+  } catch (const std::bad_alloc&) {
+    if (m) {
+      free_device(m);
+      delete m;
+    }
+    return set_error(MF_ENOMEM, "host allocation failed");
+  }
+  *out = m;
+  set_error(MF_OK, "");
+  return MF_OK;
+}
+
+int destroy_macro_mesh(mf_mesh* m) {
+  if (!m) return MF_OK;
+  free_device(m);
+  delete m;
+  return MF_OK;
+}
+
+int mesh_info(const mf_mesh* m, int* dim, int64_t* n_macros, int* max_level) {
+  if (!m) return set_error(MF_EINVAL, "mesh is NULL");
+  if (dim) *dim = m->dim;
+  if (n_macros) *n_macros = m->nc;
+  if (max_level) *max_level = m->max_level;
+  return MF_OK;
+}
+
+int mesh_num_dofs(const mf_mesh* m, int level, int64_t* storage, int64_t* unique) {
+  int rc = check_mesh(m, level, false);
+  if (rc) return rc;
+  if (storage) *storage = m->levels[level].storage;
+  if (unique) *unique = m->levels[level].unique;
+  return MF_OK;
+}
+
+int mesh_dof_keys(const mf_mesh* m, int level, int64_t* vids, int32_t* weights) {
+  int rc = check_mesh(m, level, false);
+  if (rc) return rc;
+  if (!vids || !weights) return set_error(MF_EINVAL, "NULL output");
+  storage_keys(m, level, vids, weights);
+  return MF_OK;
+}
+
+int mesh_dof_index(const mf_mesh* m, int level, int64_t n, const int64_t* ml, int64_t* index) {
+  int rc = check_mesh(m, level, false);
+  if (rc) return rc;
+  if (n < 0 || (n > 0 && (!ml || !index))) return set_error(MF_EINVAL, "bad arrays");
+  const int d1 = m->dim + 1;
+  const Level& L = m->levels[level];
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t c = ml[i * d1], x = ml[i * d1 + 1], y = ml[i * d1 + 2], z = m->dim == 3 ? ml[i * d1 + 3] : 0;
+    if (c < 0 || c >= m->nc || x < 0 || y < 0 || z < 0 || x + y + z > L.N)
+      return set_error(MF_EINVAL, "point " + std::to_string(i) + " outside its macro");
+    index[i] = L.base[c] + (m->dim == 2 ? idx2(L.N, x, y) : idx3(L.N, x, y, z));
+  }
+  return MF_OK;
+}
+
+int mesh_stencil(const mf_mesh* m, int level, int64_t macro, double* w) {
+  int rc = check_mesh(m, level, false);
+  if (rc) return rc;
+  if (macro < 0 || macro >= m->nc || !w) return set_error(MF_EINVAL, "bad macro or NULL output");
+  const int n = m->dim == 2 ? 7 : 15;
+  std::memcpy(w, m->levels[level].md[macro].w, sizeof(double) * n);
+  return MF_OK;
+}
+
+int mesh_workspace_bytes(const mf_mesh* m, int level, int mode, int64_t* bytes) {
+  int rc = check_mesh(m, level, false);
+  if (rc) return rc;
+  if (mode != 0 && mode != 1) return set_error(MF_EINVAL, "mode must be 0 or 1");
+  if (!bytes) return set_error(MF_EINVAL, "NULL output");
+  *bytes = carve(m, level, mode, 0, nullptr).bytes;
+  return MF_OK;
+}
+
+int mesh_fill_random(const mf_mesh* m, int level, int dtype, uint64_t seed, void* x, void* stream) {
+  int rc = check_mesh(m, level, true);
+  if (!rc) rc = check_dtype(dtype);
+  if (rc) return rc;
+  if (!x) return set_error(MF_EINVAL, "x is NULL");
+  return launch_fill_random(m, m->levels[level], dtype, seed, x, (hipStream_t)stream);
+}
+
+int apply_stencil(const mf_mesh* m, int level, int dtype, const void* x, void* y, void* stream) {
+  int rc = check_mesh(m, level, true);
+  if (!rc) rc = check_dtype(dtype);
+  if (rc) return rc;
+  if (!x || !y) return set_error(MF_EINVAL, "NULL vector");
+  if (x == y) return set_error(MF_EINVAL, "y must not alias x");
+  const Level& L = m->levels[level];
+  hipStream_t s = (hipStream_t)stream;
+  return launch_stencil(m, L, dtype, kApply, x, y, nullptr, 0.0, nullptr, s);
+}
+
+int smooth(const mf_mesh* m, int level, int dtype, double omega, int sweeps, const void* b, void* x, void* tmp,
+           void* stream) {
+  int rc = check_mesh(m, level, true);
+  if (!rc) rc = check_dtype(dtype);
+  if (rc) return rc;
+  if (!b || !x || !tmp) return set_error(MF_EINVAL, "NULL vector");
+  if (sweeps < 0) return set_error(MF_EINVAL, "sweeps < 0");
+  if (x == tmp || b == x || b == tmp) return set_error(MF_EINVAL, "b, x and tmp must be distinct");
+  return jacobi_sweeps(m, m->levels[level], dtype, omega, sweeps, b, x, tmp, (hipStream_t)stream);
+}
+
+int residual(const mf_mesh* m, int level, int dtype, const void* b, const void* x, void* r, double* norm2,
+             void* stream) {
+  int rc = check_mesh(m, level, true);
+  if (!rc) rc = check_dtype(dtype);
+  if (rc) return rc;
+  if (!b || !x || !r) return set_error(MF_EINVAL, "NULL vector");
+  if (r == x || r == b) return set_error(MF_EINVAL, "r must not alias b or x");
+  const Level& L = m->levels[level];
+  hipStream_t s = (hipStream_t)stream;
+  if (!norm2) {
+    return launch_stencil(m, L, dtype, kResidual, x, r, b, 0.0, nullptr, s);
+  }
+  std::lock_guard<std::mutex> lock(const_cast<mf_mesh*>(m)->norm_mutex);
+  double ss = 0.0, mx = 0.0;
+  rc = residual_norm(m, L, dtype, b, x, r, L.dev.part, L.dev.result, &ss, &mx, s);
+  *norm2 = std::sqrt(ss);
+  return rc;
+}
+
+int restrict_residual(const mf_mesh* m, int level, int dtype, const void* rf, void* bc, void* stream) {
+  int rc = check_mesh(m, level, true);
+  if (!rc) rc = check_dtype(dtype);
+  if (rc) return rc;
+  if (level < 1) return set_error(MF_EINVAL, "restriction needs level >= 1");
+  if (!rf || !bc || rf == bc) return set_error(MF_EINVAL, "NULL or aliased vectors");
+  return launch_restrict(m, m->levels[level], m->levels[level - 1], dtype, rf, bc, (hipStream_t)stream);
+}
+
+int prolong_add(const mf_mesh* m, int level, int dtype, const void* ec, void* xf, void* stream) {
+  int rc = check_mesh(m, level, true);
+  if (!rc) rc = check_dtype(dtype);
+  if (rc) return rc;
+  if (level < 1) return set_error(MF_EINVAL, "prolongation needs level >= 1");
+  if (!ec || !xf || ec == xf) return set_error(MF_EINVAL, "NULL or aliased vectors");
+  return launch_prolong_add(m, m->levels[level], m->levels[level - 1], dtype, ec, xf, (hipStream_t)stream);
+}
+
+int vcycle_solve(const mf_mesh* m, int level, const double* b, double* x, void* workspace,
+                 const mf_solve_opts* opts, mf_solve_info* info, void* stream) {
+  int rc = check_mesh(m, level, true);
+  if (rc) return rc;
+  if (!b || !x || !workspace) return set_error(MF_EINVAL, "NULL vector or workspace");
+  mf_solve_opts o = {0, 2, 2, default_coarse(level), 50, 2.0 / 3.0, 1e-10};
+  if (opts) o = *opts;
+  if (o.mode != 0 && o.mode != 1) return set_error(MF_EINVAL, "mode must be 0 or 1");
+  if (o.pre < 0 || o.post < 0 || o.max_iter < 0 || !(o.rtol >= 0.0))
+    return set_error(MF_EINVAL, "bad solver options");
+  if (o.coarse_level < 0 || o.coarse_level > level) return set_error(MF_EINVAL, "coarse_level outside [0, level]");
+  const int lc = o.coarse_level;
+  {
+    std::lock_guard<std::mutex> lock(const_cast<mf_mesh*>(m)->norm_mutex);
+    rc = build_coarse_solver(const_cast<mf_mesh*>(m), lc);
+  }
+  if (rc) return rc;
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = (hipStream_t)stream;
+  const Level& L = m->levels[level];
+  const Workspace w = carve(m, level, o.mode, 0, (char*)workspace);
+  const int vdt = o.mode == 0 ? MF_F64 : MF_F32;
+  // Dirichlet entries of x take b's values; the correction never changes them.
+  rc = launch_iface(m, L, MF_F64, kDirichletSet, x, x, b, s);
+  // ||b|| over unique DoFs
+  double ss = 0.0, mx = 0.0;
+  if (!rc) rc = vector_norm(m, L, MF_F64, b, w.part, w.result, &ss, &mx, s);
+  if (rc) return rc;
+  const double bnorm = std::sqrt(ss);
+  int it = 0;
+  double rel = 0.0;
+  bool converged = false;
+  for (;;) {
+    rc = residual_norm(m, L, MF_F64, b, x, w.r64, w.part, w.result, &ss, &mx, s);
+    if (rc) return rc;
+    rel = bnorm > 0.0 ? std::sqrt(ss) / bnorm : std::sqrt(ss);
+    if (rel <= o.rtol || mx == 0.0) {
+      converged = true;
+      break;
+    }
+    if (it >= o.max_iter) break;
+    if (o.mode == 1) {
+      // scale r by its max norm before the cast so FP32 keeps its relative precision
+      rc = launch_scale_to_f32(w.r64, (float*)w.b[level], 1.0 / mx, L.storage, s);
+      if (!rc) rc = launch_fill(MF_F32, w.x[level], 0.0, L.storage, s);
+      if (!rc) rc = vcycle(m, level, lc, vdt, w, o, s);
+      if (!rc) rc = launch_axpy_f32(x, (const float*)w.x[level], mx, L.storage, s);
+    } else {
+      rc = launch_fill(MF_F64, w.x[level], 0.0, L.storage, s);
+      if (!rc) rc = vcycle(m, level, lc, vdt, w, o, s);
+      if (!rc) rc = launch_axpy(MF_F64, x, w.x[level], 1.0, L.storage, s);
+    }
+    if (rc) return rc;
+    ++it;
+  }
+  if (info) {
+    info->iters = it;
+    info->rel_res = rel;
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return converged ? MF_OK : MF_NOT_CONVERGED;
+}
+
+}  // extern "C"

@@ -1,0 +1,42 @@
+// Host-side launchers of the HIP kernels (kernels.hip).  All are
+// asynchronous on `stream` and return an MF_* status.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "mesh.hpp"
+
+namespace mf {
+
+// One launch of the whole operator: interior rows of every macro (wave
+// tiles) and macro-boundary rows (interface groups).  mode: kApply, kJacobi,
+// kResidual, kNormB.  part (nullable; kResidual / kNormB) receives sums of
+// squares at [0, np) and maxima at [np, 2 np), np = L.n_partials().
+int launch_stencil(const mf_mesh* m, const Level& L, int dtype, int mode, const void* x, void* y, const void* b,
+                   double omega, double* part, hipStream_t s);
+
+// Interface groups only, for kExchangeSum (y = sum of x over copies;
+// Dirichlet -> 0) and kDirichletSet (y = b at Dirichlet DoFs).
+int launch_iface(const mf_mesh* m, const Level& L, int dtype, int mode, const void* x, void* y, const void* b,
+                 hipStream_t s);
+
+// result[0] = sum part[0..np), result[1] = max part[np..2np), fixed order.
+int launch_reduce(const double* part, int64_t np, double* result, hipStream_t s);
+
+int launch_fill_random(const mf_mesh* m, const Level& L, int dtype, uint64_t seed, void* x, hipStream_t s);
+int launch_restrict(const mf_mesh* m, const Level& fine, const Level& coarse, int dtype, const void* rf, void* bc,
+                    hipStream_t s);
+int launch_prolong_add(const mf_mesh* m, const Level& fine, const Level& coarse, int dtype, const void* ec,
+                       void* xf, hipStream_t s);
+int launch_coarse_solve(const Level& L, int dtype, const void* b, void* x, hipStream_t s);
+
+// Plain vector kernels over n entries.
+int launch_fill(int dtype, void* x, double v, int64_t n, hipStream_t s);
+int launch_copy(int dtype, void* dst, const void* src, int64_t n, hipStream_t s);
+int launch_axpy(int dtype, void* y, const void* x, double a, int64_t n, hipStream_t s);    // y += a x
+int launch_scale_to_f32(const double* r, float* b, double scale, int64_t n, hipStream_t s);  // b = float(scale r)
+int launch_axpy_f32(double* x, const float* e, double a, int64_t n, hipStream_t s);     // x += a double(e)
+
+}  // namespace mf

@@ -1,0 +1,90 @@
+// Host-side macro mesh and per-level metadata.
+#pragma once
+
+#include <array>
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "mf_internal.hpp"
+#include "mf_stencil.h"
+
+namespace mf {
+
+// Device copies of one level's metadata.
+struct LevelDev {
+  MacroDev* md = nullptr;
+  Tile* tiles = nullptr;       // interior wave tiles, padded to a multiple of kWavesPerWG
+  Tile* segs = nullptr;        // row segments of 64 points covering every storage point
+  int32_t* grp_ptr = nullptr;  // ngroups + 1
+  Copy* copies = nullptr;
+  uint8_t* grp_flag = nullptr;  // bit0: Dirichlet
+  double* grp_invdiag = nullptr;
+  float* grp_invdiagf = nullptr;
+  double* part = nullptr;       // norm partials: ntiles + iface blocks, then the same again for max
+  double* result = nullptr;     // 2 doubles: sum of squares, max |.|
+  double* host_result = nullptr;  // pinned host mirror of result
+  // coarse direct solve (levels <= 2 only)
+  double* cinv = nullptr;
+  float* cinvf = nullptr;
+  int32_t* cfirst = nullptr;   // storage index of each coarse unknown's first copy
+  int32_t* cptr = nullptr;     // copies of each coarse unknown
+  int64_t* cidx = nullptr;
+};
+
+struct Level {
+  int level = 0;
+  int N = 0;
+  int64_t storage = 0, unique = 0;
+  std::vector<int64_t> base;    // per macro storage offset
+  std::vector<MacroDev> md;
+  std::vector<Tile> tiles;      // interior wave tiles (natural order, padded)
+  std::vector<Tile> segs;       // per-point row segments
+  std::vector<int32_t> grp_ptr;
+  std::vector<Copy> copies;
+  std::vector<uint8_t> grp_flag;
+  std::vector<double> grp_invdiag;
+  int64_t ngroups() const { return (int64_t)grp_ptr.size() - 1; }
+  int64_t iface_blocks() const { return (ngroups() + kIfaceWG - 1) / kIfaceWG; }
+  int64_t n_partials() const { return (int64_t)tiles.size() + iface_blocks(); }
+  // coarse direct solve
+  int64_t ncoarse = 0;          // unknowns (unique non-Dirichlet DoFs); 0 = not prepared
+  std::vector<double> cinv;     // ncoarse^2 inverse of the interior block
+  std::vector<int32_t> cfirst, cptr;
+  std::vector<int64_t> cidx;
+  LevelDev dev;
+};
+
+}  // namespace mf
+
+struct mf_mesh {
+  int dim = 0;
+  int max_level = 0;
+  int flags = 0;
+  bool host_only = false;
+  int device = 0;
+  int64_t nv = 0, nc = 0;
+  std::vector<double> coords;
+  std::vector<int64_t> cells;
+  std::vector<uint16_t> own_mask, dir_mask;  // per macro
+  std::vector<mf::Level> levels;
+  std::mutex norm_mutex;  // serialises residual() calls that return a norm
+};
+
+namespace mf {
+
+// Status helpers (thread-local message).
+int set_error(int code, const std::string& msg);
+const char* last_error();
+
+// Host set-up (mesh_setup.cpp).
+int build_mesh(mf_mesh* m);
+int build_coarse_solver(mf_mesh* m, int level);
+void free_device(mf_mesh* m);
+int upload_level(mf_mesh* m, Level& L);
+
+// Keys of every storage point of a level, (dim+1) pairs each.
+void storage_keys(const mf_mesh* m, int level, int64_t* vids, int32_t* wts);
+
+}  // namespace mf

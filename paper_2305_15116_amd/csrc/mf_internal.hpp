@@ -1,0 +1,138 @@
+// Internal types of the matrix-free P1 stencil library, shared by the host
+// set-up code and the HIP kernels (never by the oracle).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#define MF_HD __host__ __device__ __forceinline__
+
+namespace mf {
+
+// ---------------------------------------------------------------- tiling
+// One wavefront (64 lanes) owns 64 consecutive columns of a macro row and
+// produces the 62 inner ones (lanes 0 and 63 are the halo); it walks a strip
+// of rows upward, keeping the three rows the 2D stencil reads in registers
+// (the layout of the paper's generated kernel: x fastest, rows bottom-up,
+// Performance Modeling, experiment description).  Four waves form a workgroup.
+constexpr int kWave = 64;
+constexpr int kTileW = 62;
+constexpr int kTileH2 = 64;   // rows per 2D wave tile
+constexpr int kTileH3 = 16;   // rows per 3D wave tile (one slice z)
+constexpr int kWavesPerWG = 4;
+constexpr int kWG = kWave * kWavesPerWG;
+constexpr int kIfaceWG = 256;  // groups per interface workgroup
+constexpr int kXCD = 8;        // MI355X: 8 accelerator complex dies, workgroups dealt round-robin
+
+// A wave tile: columns [x0, x0+62) of rows [y0, y0+H) of slice z of `macro`
+// (z = 0 in 2D).  For per-point kernels the same record names a row segment
+// of 64 points starting at x0 of row y0 in slice z.  macro < 0: padding.
+struct Tile {
+  int32_t macro, x0, y0, z;
+};
+
+// A copy of a macro-boundary DoF: macro id and its index-space point.
+struct Copy {
+  int32_t macro, x, y, z;
+};
+
+// Per-macro, per-level constants.  Element matrices K[t] are stored as 4x4
+// (2D uses the leading 3x3).
+struct MacroDev {
+  int64_t base;        // storage offset of the macro
+  int64_t vid[4];      // global vertex ids in cell order (for keys)
+  int32_t N;
+  uint16_t own_mask;   // bit s: this macro owns the primitive spanned by local-vertex subset s
+  uint16_t dir_mask;   // bit s: that primitive lies on the Dirichlet boundary
+  double w[16];        // interior stencil (7 or 15 used)
+  float wf[16];
+  double inv_diag;     // 1 / centre weight (interior points)
+  float inv_diagf;
+  float pad_;
+  double K[6][16];
+  float Kf[6][16];
+};
+
+// ---------------------------------------------------------------- layout
+MF_HD int64_t tet_count(int64_t n) { return n * (n + 1) * (n + 2) / 6; }
+MF_HD int64_t tri_count(int64_t n) { return n * (n + 1) / 2; }
+// storage points of one macro
+MF_HD int64_t macro_points(int dim, int64_t N) { return dim == 2 ? tri_count(N + 1) : tet_count(N + 1); }
+// first index of slice z (3D)
+MF_HD int64_t slice_base(int64_t N, int64_t z) { return tet_count(N + 1) - tet_count(N + 1 - z); }
+// start of row y in a triangle of side M
+MF_HD int64_t row_start(int64_t M, int64_t y) { return y * (M + 2) - y * (y + 1) / 2; }
+MF_HD int64_t idx2(int64_t N, int64_t x, int64_t y) { return row_start(N, y) + x; }
+MF_HD int64_t idx3(int64_t N, int64_t x, int64_t y, int64_t z) { return slice_base(N, z) + row_start(N - z, y) + x; }
+
+// ---------------------------------------------------------------- micro-elements
+// Index-space vertex offsets of the micro-element types (Bey's refinement in
+// the lattice; 2D: the up and down triangles).  An element of type t with
+// anchor a exists iff a >= 0 componentwise and sum(a) <= N - slack[t].
+struct ElemTable {
+  int ntypes;
+  int nv;
+  int8_t off[6][4][3];
+  int8_t slack[6];
+};
+
+MF_HD constexpr ElemTable elem_table(int dim) {
+  if (dim == 2)
+    return ElemTable{2, 3,
+                     {{{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 0}},
+                      {{1, 0, 0}, {1, 1, 0}, {0, 1, 0}, {0, 0, 0}},
+                      {}, {}, {}, {}},
+                     {1, 2, 0, 0, 0, 0}};
+  // 3D: up tet; the octahedron around the (0,1,0)-(1,0,1) diagonal with ring
+  // (1,0,0),(1,1,0),(0,1,1),(0,0,1); down tet.
+  return ElemTable{6, 4,
+                   {{{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}},
+                    {{0, 1, 0}, {1, 0, 1}, {1, 0, 0}, {1, 1, 0}},
+                    {{0, 1, 0}, {1, 0, 1}, {1, 1, 0}, {0, 1, 1}},
+                    {{0, 1, 0}, {1, 0, 1}, {0, 1, 1}, {0, 0, 1}},
+                    {{0, 1, 0}, {1, 0, 1}, {0, 0, 1}, {1, 0, 0}},
+                    {{1, 1, 0}, {1, 0, 1}, {0, 1, 1}, {1, 1, 1}}},
+                   {1, 2, 2, 2, 2, 3}};
+}
+
+// Stencil offsets in weight order (see mf_stencil.h).
+struct StencilTable {
+  int n;
+  int centre;
+  int8_t off[15][3];
+};
+
+MF_HD constexpr StencilTable stencil_table(int dim) {
+  if (dim == 2)
+    return StencilTable{7, 3, {{0, -1, 0}, {1, -1, 0}, {-1, 0, 0}, {0, 0, 0}, {1, 0, 0}, {-1, 1, 0}, {0, 1, 0}}};
+  return StencilTable{15, 7,
+                      {{0, 0, -1}, {1, 0, -1}, {0, 1, -1}, {-1, 1, -1},
+                       {0, -1, 0}, {1, -1, 0}, {-1, 0, 0}, {0, 0, 0}, {1, 0, 0}, {-1, 1, 0}, {0, 1, 0},
+                       {0, -1, 1}, {1, -1, 1}, {-1, 0, 1}, {0, 0, 1}}};
+}
+
+// Local-vertex support mask of point p of a macro: bit k set iff barycentric
+// weight k is non-zero (weights (N - sum p, p1, .., pd)).
+MF_HD int support_mask(int dim, int N, int x, int y, int z) {
+  const int w0 = N - x - y - (dim == 3 ? z : 0);
+  int m = (w0 != 0 ? 1 : 0) | (x != 0 ? 2 : 0) | (y != 0 ? 4 : 0);
+  if (dim == 3) m |= (z != 0 ? 8 : 0);
+  return m;
+}
+
+// Operation modes of the fused stencil kernels.
+enum Mode : int {
+  kApply = 0,     // y = A x
+  kJacobi = 1,    // y = x + omega D^-1 (b - A x)
+  kResidual = 2,  // y = b - A x  (+ sum of squares and max |.| partials)
+  kNormB = 3,     // no output; partials of b only (||b|| over unique DoFs)
+};
+
+// Interface-kernel-only modes.
+enum IfaceMode : int {
+  kExchangeSum = 10,   // y(all copies) = sum of the copies' values of x; Dirichlet -> 0
+  kDirichletSet = 11,  // y = b at Dirichlet DoFs only
+};
+
+}  // namespace mf

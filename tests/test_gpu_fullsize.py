@@ -1,0 +1,134 @@
+"""Full-size checks in the benchmark's launch configuration.
+
+At the benchmark sizes (one affine triangle at level 14, 134,242,305 DoFs;
+the 6-tet unit cube at level 8, 17,173,254 storage DoFs) the oracle cannot
+assemble the whole matrix, so sampled rows are recomputed one by one by the
+oracle's row evaluator (same keyed input), and properties that hold at any
+size are checked on every row.
+"""
+import numpy as np
+import pytest
+
+import paper_2305_15116_amd as P
+from oracle.oracle import sample_rows
+from paper_2305_15116_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    yield
+    torch.cuda.synchronize()
+
+
+def _samples_2d(N, rng, n=3000):
+    pts = []
+    for _ in range(n):
+        y = int(rng.integers(0, N + 1))
+        pts.append((int(rng.integers(0, N + 1 - y)), y))
+    for k in range(0, N + 1, 62):      # tile column edges
+        for y in (1, 2, 63, 64, 65, 128):
+            for x in (k - 1, k, k + 1, k + 2):
+                if 0 <= x and x + y <= N:
+                    pts.append((x, y))
+    for y in range(0, N + 1, max(1, N // 64)):  # hypotenuse band and the legs
+        for x in (N - y, N - y - 1, N - y - 2, 0, 1):
+            if 0 <= x and x + y <= N:
+                pts.append((x, y))
+    pts += [(0, 0), (N, 0), (0, N), (1, 1), (N - 2, 1), (1, N - 2)]
+    return np.array(pts, dtype=np.int64)
+
+
+def _samples_3d(N, nc, rng, n=3000):
+    pts = []
+    for _ in range(n):
+        c = int(rng.integers(0, nc))
+        z = int(rng.integers(0, N + 1))
+        y = int(rng.integers(0, N + 1 - z))
+        x = int(rng.integers(0, N + 1 - z - y))
+        pts.append((c, x, y, z))
+    for c in range(nc):
+        for z in (0, 1, 2, N // 2, N - 3, N - 2, N - 1, N):
+            M = N - z
+            for y in (0, 1, 16, 17, M // 2, M - 1, M):
+                for x in (0, 1, 61, 62, 63, M - y - 1, M - y):
+                    if 0 <= y <= M and 0 <= x and x + y <= M:
+                        pts.append((c, x, y, z))
+    return np.array(pts, dtype=np.int64)
+
+
+def _check_sampled(co, ce, m, L, y, seed, pts_ml, tol):
+    idx = P.mesh_dof_index(m, L, pts_ml)
+    got = y[torch.as_tensor(idx, device="cuda")].double().cpu().numpy()
+    dim = co.shape[1]
+    yo, bnd = sample_rows(co, ce, L, seed, pts_ml[:, 0], pts_ml[:, 1:1 + dim])
+    scale = np.abs(yo).max()
+    return np.abs(got - yo), scale, bnd
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_2d_level14_affine_triangle(dtype):
+    co, ce = W.affine_triangle(2)
+    L = 14
+    N = 1 << L
+    m = P.create_macro_mesh(co, ce, L)
+    s, u = P.mesh_num_dofs(m, L)
+    assert s == u == (N + 1) * (N + 2) // 2 == 134242305
+    x = torch.empty(s, dtype=dtype, device="cuda")
+    P.mesh_fill_random(m, L, 3, x)
+    y = torch.empty_like(x)
+    P.apply_stencil(m, L, x, y)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(42)
+    pts = _samples_2d(N, rng)
+    ml = np.hstack([np.zeros((len(pts), 1), np.int64), pts])
+    err, scale, _ = _check_sampled(co, ce, m, L, y, 3, ml, None)
+    if dtype == torch.float64:
+        assert err.max() <= 1e-12 * scale
+    else:
+        w = np.abs(P.mesh_stencil(m, L, 0)).sum()
+        assert err.max() <= 16 * U32 * w
+    # A 1 = 0 on interior rows and 1 on the boundary, checked on every row
+    x.fill_(1.0)
+    P.apply_stencil(m, L, x, y)
+    torch.cuda.synchronize()
+    wsum = np.abs(P.mesh_stencil(m, L, 0)).sum()
+    yb = y.double()
+    bidx = torch.as_tensor(P.mesh_dof_index(m, L, np.array(
+        [[0, xx, 0] for xx in range(N + 1)] + [[0, 0, yy] for yy in range(1, N + 1)] +
+        [[0, N - yy, yy] for yy in range(1, N)])), device="cuda")
+    assert torch.all(yb[bidx] == 1.0)
+    yb[bidx] = 0.0
+    tol = 1e-12 if dtype == torch.float64 else 16 * U32
+    assert float(yb.abs().max()) <= tol * wsum
+
+
+@pytest.mark.parametrize("order", ["canonical", "random"])
+def test_3d_level8_cube(order):
+    co, ce = W.kuhn_cube(order, 5)
+    L = 8
+    N = 1 << L
+    m = P.create_macro_mesh(co, ce, L)
+    s, u = P.mesh_num_dofs(m, L)
+    assert s == 17173254 and u == 16974593
+    x = torch.empty(s, dtype=torch.float64, device="cuda")
+    P.mesh_fill_random(m, L, 4, x)
+    y = torch.empty_like(x)
+    P.apply_stencil(m, L, x, y)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(43)
+    ml = _samples_3d(N, 6, rng)
+    err, scale, bnd = _check_sampled(co, ce, m, L, y, 4, ml, None)
+    assert err.max() <= 1e-12 * scale
+    if order == "canonical":
+        # every non-boundary row is h (6 x_c - sum of axis neighbours): A 1 = 0 there, and
+        # A applied to x = 1 gives exactly 1 on the Dirichlet rows
+        x.fill_(1.0)
+        P.apply_stencil(m, L, x, y)
+        torch.cuda.synchronize()
+        h = 1.0 / N
+        assert float((y - torch.where(y == 1.0, y, torch.zeros_like(y))).abs().max()) <= 1e-12 * 12 * h

@@ -1,0 +1,183 @@
+"""GPU parity of the HIP path (through the C ABI) against the oracle.
+
+FP64 results must match the oracle's CSR product within 1e-12 relative in
+the max norm; FP32 results within 16 u32 (|A| |x|)_i per row (a forward
+error bound for 7 or 15 fused products with rounded weights and inputs).
+Inputs come from the keyed SplitMix64 generator, implemented separately on
+both sides; the two must agree bitwise.
+"""
+import numpy as np
+import pytest
+
+import harness
+import paper_2305_15116_amd as P
+from oracle.oracle import OracleMesh, prolongation
+from paper_2305_15116_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def _mesh(name):
+    table = {
+        "tri_ref": (W.unit_triangle, None),
+        "tri_affine": (lambda: W.affine_triangle(2), None),
+        "square": (W.two_triangle_square, None),
+        "strip2d": (lambda: W.strip_2d(5), 2),
+        "strip2d_shuf": (lambda: (W.strip_2d(6)[0], W.shuffle_cell_orders(W.strip_2d(6)[1], 4)), 2),
+        "tet": (W.unit_tet, 3),
+        "cube": (W.kuhn_cube, None),
+        "cube_random": (lambda: W.kuhn_cube("random", 5), 3),
+        "strip3d": (lambda: W.strip_3d(9), 3),
+    }
+    mk, affine_dim = table[name]
+    co, ce = mk()
+    if affine_dim:
+        J, t = W.random_affine(affine_dim, 17)
+        co = W.apply_affine(co, J, t)
+    return co, ce
+
+
+def _setup(name, L):
+    co, ce = _mesh(name)
+    m = P.create_macro_mesh(co, ce, L)
+    om = OracleMesh(co, ce, L)
+    s2u = harness.storage_to_unique(P.mesh_dof_keys(m, L), om.keys())
+    return co, ce, m, om, s2u
+
+
+def _rand(m, L, seed, dtype=torch.float64):
+    s, _ = P.mesh_num_dofs(m, L)
+    x = torch.empty(s, dtype=dtype, device="cuda")
+    P.mesh_fill_random(m, L, seed, x)
+    return x
+
+
+CASES = [("tri_ref", 8), ("tri_affine", 6), ("tri_affine", 9), ("square", 7), ("strip2d", 6),
+         ("strip2d_shuf", 5), ("tri_affine", 0), ("tri_affine", 1), ("tri_affine", 2), ("strip2d", 3),
+         ("tet", 5), ("cube", 4), ("cube_random", 5), ("strip3d", 4), ("cube", 1), ("cube_random", 2),
+         ("tet", 3), ("cube_random", 6)]
+
+
+@pytest.mark.parametrize("name,L", CASES)
+def test_apply_fp64_matches_oracle(name, L):
+    co, ce, m, om, s2u = _setup(name, L)
+    x = _rand(m, L, 1000 + L)
+    y = torch.full_like(x, float("nan"))
+    P.apply_stencil(m, L, x, y)
+    torch.cuda.synchronize()
+    xo = om.keyed_random(1000 + L)
+    xs = x.cpu().numpy()
+    assert np.array_equal(xs, xo[s2u]), "keyed generators disagree"
+    yo = om.spmv(xo)
+    ys = y.cpu().numpy()
+    assert np.isfinite(ys).all()
+    assert harness.copies_consistent(ys, s2u)
+    assert harness.rel_err_max(ys, yo[s2u]) <= 1e-12
+
+
+@pytest.mark.parametrize("name,L", [("tri_affine", 8), ("strip2d", 6), ("cube_random", 5), ("strip3d", 4)])
+def test_apply_fp32_within_rounding_bound(name, L):
+    co, ce, m, om, s2u = _setup(name, L)
+    x = _rand(m, L, 7, torch.float32)
+    y = torch.empty_like(x)
+    P.apply_stencil(m, L, x, y)
+    torch.cuda.synchronize()
+    xo = om.keyed_random(7)
+    A = om.csr(dirichlet=True)
+    yo = A @ xo
+    bound = 16 * U32 * (abs(A) @ np.abs(xo))
+    ys = y.cpu().numpy().astype(np.float64)
+    assert harness.copies_consistent(y.cpu().numpy(), s2u)
+    assert (np.abs(ys - yo[s2u]) <= bound[s2u] + 1e-30).all()
+
+
+@pytest.mark.parametrize("name,L", [("tri_affine", 7), ("strip2d_shuf", 6), ("cube_random", 4), ("strip3d", 4)])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_smooth_and_residual_match_oracle(name, L, dtype):
+    co, ce, m, om, s2u = _setup(name, L)
+    x = _rand(m, L, 11, dtype)
+    b = _rand(m, L, 12, dtype)
+    tmp = torch.empty_like(x)
+    r = torch.empty_like(x)
+    omega = 2.0 / 3.0
+    nrm = P.residual(m, L, b, x, r, norm=True)
+    P.smooth(m, L, omega, 3, b, x, tmp)
+    torch.cuda.synchronize()
+    xo, bo = om.keyed_random(11), om.keyed_random(12)
+    if dtype == torch.float32:
+        xo, bo = xo.astype(np.float32).astype(np.float64), bo.astype(np.float32).astype(np.float64)
+    A = om.csr(dirichlet=True)
+    bnd = om.boundary()
+    ro = bo - A @ xo
+    tol = 1e-12 if dtype == torch.float64 else 1e-5
+    assert harness.rel_err_max(r.cpu().numpy().astype(np.float64), ro[s2u]) <= tol
+    assert abs(nrm - np.linalg.norm(ro)) <= tol * np.linalg.norm(ro)
+    d = A.diagonal()
+    xs = xo.copy()
+    for _ in range(3):
+        xs = np.where(bnd, xs, xs + omega / d * (bo - A @ xs))
+    out = x.cpu().numpy().astype(np.float64)
+    assert harness.copies_consistent(x.cpu().numpy(), s2u)
+    assert harness.rel_err_max(out, xs[s2u]) <= (1e-12 if dtype == torch.float64 else 2e-5)
+
+
+@pytest.mark.parametrize("name,L", [("tri_affine", 5), ("strip2d_shuf", 4), ("square", 3), ("cube_random", 3),
+                                    ("strip3d", 3), ("tet", 4), ("tri_affine", 1), ("cube", 1)])
+def test_transfers_match_oracle_prolongation(name, L):
+    co, ce, mf_, omf, s2u_f = _setup(name, L)
+    omc = OracleMesh(co, ce, L - 1)
+    s2u_c = harness.storage_to_unique(P.mesh_dof_keys(mf_, L - 1), omc.keys())
+    Pm = prolongation(omf, omc)
+    bf, bc_ = omf.boundary(), omc.boundary()
+    # restriction of a fine vector: P^T r with Dirichlet rows/cols removed
+    rf = _rand(mf_, L, 21)
+    sc, _ = P.mesh_num_dofs(mf_, L - 1)
+    bc = torch.empty(sc, dtype=torch.float64, device="cuda")
+    P.restrict_residual(mf_, L, rf, bc)
+    ec = _rand(mf_, L - 1, 22)
+    xf = _rand(mf_, L, 23)
+    P.prolong_add(mf_, L, ec, xf)
+    torch.cuda.synchronize()
+    rfo = omf.keyed_random(21)
+    rfo_masked = np.where(bf, 0.0, rfo)
+    bco = Pm.T @ rfo_masked
+    bco[bc_] = 0.0
+    assert harness.copies_consistent(bc.cpu().numpy(), s2u_c)
+    assert harness.rel_err_max(bc.cpu().numpy(), bco[s2u_c]) <= 1e-14
+    eco = omc.keyed_random(22)
+    xfo = omf.keyed_random(23) + np.where(bf, 0.0, Pm @ eco)
+    assert harness.copies_consistent(xf.cpu().numpy(), s2u_f)
+    assert harness.rel_err_max(xf.cpu().numpy(), xfo[s2u_f]) <= 1e-14
+
+
+def test_apply_is_deterministic():
+    co, ce, m, om, s2u = _setup("cube_random", 5)
+    x = _rand(m, 5, 3)
+    y1, y2 = torch.empty_like(x), torch.empty_like(x)
+    r1, r2 = torch.empty_like(x), torch.empty_like(x)
+    P.apply_stencil(m, 5, x, y1)
+    P.apply_stencil(m, 5, x, y2)
+    n1 = P.residual(m, 5, y1, x, r1, norm=True)
+    n2 = P.residual(m, 5, y1, x, r2, norm=True)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2) and torch.equal(r1, r2) and n1 == n2
+
+
+def test_apply_bad_arguments_raise():
+    co, ce, m, om, s2u = _setup("tri_affine", 3)
+    x = _rand(m, 3, 1)
+    with pytest.raises(P.MFError):
+        P.apply_stencil(m, 4, x, torch.empty_like(x))
+    with pytest.raises(P.MFError):
+        P.apply_stencil(m, 3, x, x)

@@ -14,7 +14,7 @@ import pytest
 from scipy.spatial import cKDTree
 
 import bruteforce
-from oracle.oracle import OracleMesh, prolongation, sample_rows, solve, splitmix64
+from oracle.oracle import OracleMesh, keyed_points, prolongation, sample_rows, solve, splitmix64
 from paper_2305_15116_amd import workloads as W
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -114,6 +114,32 @@ def test_2d_stencil_closed_form(seed):
             for (dx, dy), val in expect.items():
                 j = _find(xyz, P0 + (x + dx) * e1 + (y + dy) * e2)
                 assert abs(A[u, j] - val) <= 1e-13 * max(1.0, abs(expect[(0, 0)]))
+
+
+@pytest.mark.parametrize("L", [10, 14])
+def test_sampled_rows_at_full_level_match_closed_form(L):
+    """At the benchmark level the oracle's row evaluator still reproduces the
+    closed-form stencil of an affine triangle to rounding (its micro-element
+    edge vectors carry full precision)."""
+    co, ce = W.affine_triangle(2)
+    J = np.column_stack([co[1] - co[0], co[2] - co[0]])
+    M = np.linalg.inv(J.T @ J)
+    a, b, c = M[0, 0], M[0, 1], M[1, 1]
+    D = abs(np.linalg.det(J))
+    offs = [((0, -1), -D * (b + c)), ((1, -1), D * b), ((-1, 0), -D * (a + b)), ((0, 0), 2 * D * (a + b + c)),
+            ((1, 0), -D * (a + b)), ((-1, 1), D * b), ((0, 1), -D * (b + c))]
+    N = 1 << L
+    rng = np.random.default_rng(L)
+    ys = rng.integers(1, N - 1, 200)
+    xs = np.array([rng.integers(1, N - y) for y in ys])
+    pts = np.stack([xs, ys], 1)
+    got, bnd = sample_rows(co, ce, L, 5, np.zeros(len(pts), np.int64), pts)
+    assert not bnd.any()
+    exp = np.zeros(len(pts))
+    for (dx, dy), w in offs:
+        exp += w * keyed_points(ce, 2, L, 5, np.zeros(len(pts), np.int64), pts + np.array([dx, dy]))
+    wsum = sum(abs(w) for _, w in offs)
+    assert np.abs(got - exp).max() <= 1e-14 * wsum
 
 
 def test_reference_triangle_is_five_point():
