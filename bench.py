@@ -159,6 +159,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-extra", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one device copy of 1 GiB (counter calibration for profiles)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the macro-parallel multi-GPU path is not built "
@@ -185,6 +187,14 @@ def main():
                 "kernel": "stencil_kernel<double,2,apply>", "algorithmic_bytes_per_launch": bytes_launch,
                 "launch_avg_ms": r64["launch_avg_ms"], "launch_median_ms": r64["launch_median_ms"]}
     extra = {}
+    if args.copy_calibration:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        extra["copy_calibration_bytes"] = {"read": a.numel() * 8, "write": b.numel() * 8}
+        del a, b
     if not args.skip_extra:
         log("apply 2D level 14 fp32")
         r32 = bench_apply(P, torch, co, ce, L, torch.float32, args.steps, args.warmup, 3)

@@ -50,7 +50,7 @@ int sync_result(const double* result_dev, double out[2], hipStream_t s) {
 // r = b - A x with partials in `part`; reduces to result_dev and copies back.
 int residual_norm(const mf_mesh* m, const Level& L, int dtype, const void* b, const void* x, void* r, double* part,
                   double* result_dev, double* ss, double* mx, hipStream_t s) {
-  const int64_t np = L.n_partials();
+  const int64_t np = stencil_partials(L);
   int rc = launch_stencil(m, L, dtype, kResidual, x, r, b, 0.0, part, s);
   if (!rc) rc = launch_reduce(part, np, result_dev, s);
   double out[2] = {0.0, 0.0};
@@ -65,7 +65,7 @@ int residual_norm(const mf_mesh* m, const Level& L, int dtype, const void* b, co
 // sum of squares and max |.| of b over unique DoFs
 int vector_norm(const mf_mesh* m, const Level& L, int dtype, const void* b, double* part, double* result_dev,
                 double* ss, double* mx, hipStream_t s) {
-  const int64_t np = L.n_partials();
+  const int64_t np = stencil_partials(L);
   int rc = launch_stencil(m, L, dtype, kNormB, b, nullptr, b, 0.0, part, s);
   if (!rc) rc = launch_reduce(part, np, result_dev, s);
   double out[2] = {0.0, 0.0};
@@ -255,7 +255,7 @@ int mesh_stencil(const mf_mesh* m, int level, int64_t macro, double* w) {
   if (rc) return rc;
   if (macro < 0 || macro >= m->nc || !w) return set_error(MF_EINVAL, "bad macro or NULL output");
   const int n = m->dim == 2 ? 7 : 15;
-  std::memcpy(w, m->levels[level].md[macro].w, sizeof(double) * n);
+  std::memcpy(w, m->levels[level].md[macro].wm[full_mask(m->dim)], sizeof(double) * n);
   return MF_OK;
 }
 

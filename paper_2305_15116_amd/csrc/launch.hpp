@@ -13,7 +13,9 @@ namespace mf {
 // One launch of the whole operator: interior rows of every macro (wave
 // tiles) and macro-boundary rows (interface groups).  mode: kApply, kJacobi,
 // kResidual, kNormB.  part (nullable; kResidual / kNormB) receives sums of
-// squares at [0, np) and maxima at [np, 2 np), np = L.n_partials().
+// squares at [0, np) and maxima at [np, 2 np), np = stencil_partials(L)
+// (at most L.n_partials(), which sizes the buffers).
+int64_t stencil_partials(const Level& L);
 int launch_stencil(const mf_mesh* m, const Level& L, int dtype, int mode, const void* x, void* y, const void* b,
                    double omega, double* part, hipStream_t s);
 

@@ -20,8 +20,10 @@ struct LevelDev {
   int32_t* grp_ptr = nullptr;  // ngroups + 1
   Copy* copies = nullptr;
   uint8_t* grp_flag = nullptr;  // bit0: Dirichlet
-  double* grp_invdiag = nullptr;
-  float* grp_invdiagf = nullptr;
+  int32_t* xgrp_ptr = nullptr;  // exchange groups: shared, non-Dirichlet DoFs
+  Copy* xcopies = nullptr;
+  double* xgrp_invdiag = nullptr;
+  float* xgrp_invdiagf = nullptr;
   double* part = nullptr;       // norm partials: ntiles + iface blocks, then the same again for max
   double* result = nullptr;     // 2 doubles: sum of squares, max |.|
   double* host_result = nullptr;  // pinned host mirror of result
@@ -44,10 +46,15 @@ struct Level {
   std::vector<int32_t> grp_ptr;
   std::vector<Copy> copies;
   std::vector<uint8_t> grp_flag;
-  std::vector<double> grp_invdiag;
+  // exchange groups: DoFs shared by several macros and not Dirichlet
+  std::vector<int32_t> xgrp_ptr;
+  std::vector<Copy> xcopies;
+  std::vector<double> xgrp_invdiag;
   int64_t ngroups() const { return (int64_t)grp_ptr.size() - 1; }
+  int64_t nxgroups() const { return (int64_t)xgrp_ptr.size() - 1; }
   int64_t iface_blocks() const { return (ngroups() + kIfaceWG - 1) / kIfaceWG; }
-  int64_t n_partials() const { return (int64_t)tiles.size() + iface_blocks(); }
+  int64_t xgroup_blocks() const { return (nxgroups() + kIfaceWG - 1) / kIfaceWG; }
+  int64_t n_partials() const { return (int64_t)tiles.size() + xgroup_blocks(); }
   // coarse direct solve
   int64_t ncoarse = 0;          // unknowns (unique non-Dirichlet DoFs); 0 = not prepared
   std::vector<double> cinv;     // ncoarse^2 inverse of the interior block
@@ -67,7 +74,7 @@ struct mf_mesh {
   int64_t nv = 0, nc = 0;
   std::vector<double> coords;
   std::vector<int64_t> cells;
-  std::vector<uint16_t> own_mask, dir_mask;  // per macro
+  std::vector<uint16_t> own_mask, dir_mask, shared_mask;  // per macro
   std::vector<mf::Level> levels;
   std::mutex norm_mutex;  // serialises residual() calls that return a norm
 };

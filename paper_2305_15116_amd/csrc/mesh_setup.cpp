@@ -118,26 +118,6 @@ PointKey point_key(int dim, const int64_t* cellv, int N, int x, int y, int z) {
   return k;
 }
 
-// Partial diagonal at point p of a macro: sum of K_t[v][v] over the
-// micro-elements of that macro containing p.
-double partial_diag(int dim, const MacroDev& M, int x, int y, int z) {
-  const ElemTable T = elem_table(dim);
-  const int p[3] = {x, y, z};
-  double s = 0.0;
-  for (int t = 0; t < T.ntypes; ++t)
-    for (int v = 0; v < T.nv; ++v) {
-      int a[3], sum = 0;
-      bool ok = true;
-      for (int k = 0; k < dim; ++k) {
-        a[k] = p[k] - T.off[t][v][k];
-        ok = ok && a[k] >= 0;
-        sum += a[k];
-      }
-      if (ok && sum <= M.N - T.slack[t]) s += M.K[t][v * 4 + v];
-    }
-  return s;
-}
-
 template <class F>
 void for_each_boundary_point(int dim, int N, F&& fn) {
   if (dim == 2) {
@@ -196,8 +176,9 @@ static int build_topology(mf_mesh* m) {
       if (++facet_count[f] > 2) return set_error(MF_EINVAL, "non-conforming mesh: a facet has more than two cells");
     }
   }
-  // lowest macro containing each primitive (vertex subset of a cell)
+  // lowest macro containing each primitive (vertex subset of a cell), and how many contain it
   std::map<std::vector<int64_t>, int64_t> owner;
+  std::map<std::vector<int64_t>, int> containing;
   for (int64_t c = 0; c < m->nc; ++c)
     for (int s = 1; s < (1 << d1); ++s) {
       std::vector<int64_t> prim;
@@ -206,6 +187,7 @@ static int build_topology(mf_mesh* m) {
       std::sort(prim.begin(), prim.end());
       auto it = owner.find(prim);
       if (it == owner.end() || it->second > c) owner[prim] = c;
+      containing[prim] += 1;
     }
   // primitives lying in a boundary facet
   std::map<std::vector<int64_t>, bool> on_boundary;
@@ -223,6 +205,7 @@ static int build_topology(mf_mesh* m) {
   const bool dirichlet = (m->flags & MF_FLAG_DIRICHLET) != 0;
   m->own_mask.assign(m->nc, 0);
   m->dir_mask.assign(m->nc, 0);
+  m->shared_mask.assign(m->nc, 0);
   for (int64_t c = 0; c < m->nc; ++c)
     for (int s = 1; s < (1 << d1); ++s) {
       std::vector<int64_t> prim;
@@ -230,6 +213,7 @@ static int build_topology(mf_mesh* m) {
         if (s & (1 << k)) prim.push_back(m->cells[c * d1 + k]);
       std::sort(prim.begin(), prim.end());
       if (owner[prim] == c) m->own_mask[c] |= (uint16_t)(1u << s);
+      if (containing[prim] >= 2) m->shared_mask[c] |= (uint16_t)(1u << s);
       if (dirichlet && on_boundary.count(prim)) m->dir_mask[c] |= (uint16_t)(1u << s);
     }
   return MF_OK;
@@ -258,6 +242,7 @@ static int build_level(mf_mesh* m, int level, Level& L) {
     M.N = N;
     M.own_mask = m->own_mask[c];
     M.dir_mask = m->dir_mask[c];
+    M.shared_mask = m->shared_mask[c];
     // macro Jacobian columns P_k - P_0
     const double* P0 = &m->coords[m->cells[c * d1] * dim];
     double J[3][3] = {{0}};
@@ -276,25 +261,39 @@ static int build_level(mf_mesh* m, int level, Level& L) {
       double K[4][4];
       if (!metric_stiffness(dim, E, K)) return set_error(MF_EINVAL, "degenerate macro " + std::to_string(c));
       for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 4; ++j) {
-          M.K[t][i * 4 + j] = K[i][j];
-          M.Kf[t][i * 4 + j] = (float)K[i][j];
-        }
+        for (int j = 0; j < 4; ++j) M.K[t][i * 4 + j] = K[i][j];
     }
-    // interior stencil: sum over every (type, local vertex v) incidence of row v of K_t
-    for (int t = 0; t < ET.ntypes; ++t)
-      for (int v = 0; v < ET.nv; ++v)
-        for (int u = 0; u < ET.nv; ++u) {
-          int d[3] = {0, 0, 0};
-          for (int k = 0; k < 3; ++k) d[k] = ET.off[t][u][k] - ET.off[t][v][k];
-          int hit = -1;
-          for (int s = 0; s < ST.n; ++s)
-            if (ST.off[s][0] == d[0] && ST.off[s][1] == d[1] && ST.off[s][2] == d[2]) hit = s;
-          if (hit < 0) return set_error(MF_EINVAL, "internal: stencil offset not found");
-          M.w[hit] += M.K[t][v * 4 + u];
+    // Partial stencil of every support mask: sum, over the (type, local vertex v)
+    // incidences of the micro-elements inside the macro that contain a point
+    // with that support, of row v of K_t.  An incidence is present iff the
+    // element's vertex offset o_v is zero in every coordinate that vanishes
+    // at the point, and, on the far face (weight w0 = 0), iff o_v has the
+    // largest coordinate sum of its type; the full mask gives the interior stencil.
+    const int fm = full_mask(dim);
+    for (int mask = 1; mask <= fm; ++mask) {
+      for (int t = 0; t < ET.ntypes; ++t)
+        for (int v = 0; v < ET.nv; ++v) {
+          bool ok = true;
+          int osum = 0;
+          for (int k = 0; k < dim; ++k) {
+            osum += ET.off[t][v][k];
+            if (!((mask >> (k + 1)) & 1) && ET.off[t][v][k] != 0) ok = false;
+          }
+          if (!(mask & 1) && osum != ET.slack[t]) ok = false;
+          if (!ok) continue;
+          for (int u = 0; u < ET.nv; ++u) {
+            int d[3] = {0, 0, 0};
+            for (int k = 0; k < 3; ++k) d[k] = ET.off[t][u][k] - ET.off[t][v][k];
+            int hit = -1;
+            for (int q = 0; q < ST.n; ++q)
+              if (ST.off[q][0] == d[0] && ST.off[q][1] == d[1] && ST.off[q][2] == d[2]) hit = q;
+            if (hit < 0) return set_error(MF_EINVAL, "internal: stencil offset not found");
+            M.wm[mask][hit] += M.K[t][v * 4 + u];
+          }
         }
-    for (int s = 0; s < ST.n; ++s) M.wf[s] = (float)M.w[s];
-    M.inv_diag = 1.0 / M.w[ST.centre];
+      for (int q = 0; q < ST.n; ++q) M.wmf[mask][q] = (float)M.wm[mask][q];
+    }
+    M.inv_diag = 1.0 / M.wm[fm][ST.centre];
     M.inv_diagf = (float)M.inv_diag;
   }
   L.storage = off;
@@ -316,20 +315,37 @@ static int build_level(mf_mesh* m, int level, Level& L) {
   L.grp_ptr.clear();
   L.copies.clear();
   L.grp_flag.clear();
-  L.grp_invdiag.clear();
-  for (size_t i = 0; i < ent.size(); ++i) {
-    if (i == 0 || !(ent[i].k == ent[i - 1].k)) {
-      L.grp_ptr.push_back((int32_t)L.copies.size());
-      const int s = support_mask(dim, N, ent[i].x, ent[i].y, ent[i].z);
-      L.grp_flag.push_back((m->dir_mask[ent[i].macro] >> s) & 1);
-      L.grp_invdiag.push_back(0.0);
+  L.xgrp_ptr.clear();
+  L.xcopies.clear();
+  L.xgrp_invdiag.clear();
+  const int fmask = full_mask(dim);
+  for (size_t i = 0; i < ent.size();) {
+    size_t j = i;
+    while (j < ent.size() && ent[j].k == ent[i].k) ++j;
+    const int s0 = support_mask(dim, N, ent[i].x, ent[i].y, ent[i].z);
+    const bool dir = (m->dir_mask[ent[i].macro] >> s0) & 1;
+    L.grp_ptr.push_back((int32_t)L.copies.size());
+    L.grp_flag.push_back(dir ? 1 : 0);
+    for (size_t k = i; k < j; ++k) L.copies.push_back({ent[k].macro, ent[k].x, ent[k].y, ent[k].z});
+    if (!dir && j - i >= 2) {
+      // shared, not Dirichlet: the stencil kernel leaves partial rows in every
+      // copy and the exchange sums them; the assembled diagonal is the sum
+      // of the copies' partial centre weights
+      L.xgrp_ptr.push_back((int32_t)L.xcopies.size());
+      double diag = 0.0;
+      for (size_t k = i; k < j; ++k) {
+        L.xcopies.push_back({ent[k].macro, ent[k].x, ent[k].y, ent[k].z});
+        const int sk = support_mask(dim, N, ent[k].x, ent[k].y, ent[k].z);
+        diag += L.md[ent[k].macro].wm[sk][ST.centre];
+      }
+      L.xgrp_invdiag.push_back(diag != 0.0 ? 1.0 / diag : 0.0);
     }
-    L.copies.push_back({ent[i].macro, ent[i].x, ent[i].y, ent[i].z});
-    L.grp_invdiag.back() += partial_diag(dim, L.md[ent[i].macro], ent[i].x, ent[i].y, ent[i].z);
+    (void)fmask;
+    i = j;
   }
   if (L.copies.size() > (size_t)INT32_MAX) return set_error(MF_ENOMEM, "too many interface copies");
   L.grp_ptr.push_back((int32_t)L.copies.size());
-  for (auto& d : L.grp_invdiag) d = d != 0.0 ? 1.0 / d : 0.0;
+  L.xgrp_ptr.push_back((int32_t)L.xcopies.size());
   const int64_t ngroups = L.ngroups();
   // unique DoFs: interior points of every macro + groups
   int64_t interior = 0;
@@ -337,18 +353,17 @@ static int build_level(mf_mesh* m, int level, Level& L) {
   else interior = N >= 4 ? tet_count(N - 3) : 0;
   L.unique = interior * m->nc + ngroups;
 
-  // interior wave tiles, natural order: macro, slice, strip, band
+  // wave tiles over every point of every macro, natural order: macro,
+  // (slice chunk,) strip, band
   L.tiles.clear();
   for (int64_t c = 0; c < m->nc; ++c) {
     if (dim == 2) {
-      for (int y0 = 1; y0 <= N - 2; y0 += kTileH2)
-        for (int x0 = 1; x0 + y0 <= N - 1; x0 += kTileW) L.tiles.push_back({(int32_t)c, x0, y0, 0});
+      for (int y0 = 0; y0 <= N; y0 += kTileH2)
+        for (int x0 = 0; x0 + y0 <= N; x0 += kTileW) L.tiles.push_back({(int32_t)c, x0, y0, 0});
     } else {
-      for (int z = 1; z <= N - 2; ++z) {
-        const int M = N - z;
-        for (int y0 = 1; y0 <= M - 2; y0 += kTileH3)
-          for (int x0 = 1; x0 + y0 <= M - 1; x0 += kTileW) L.tiles.push_back({(int32_t)c, x0, y0, z});
-      }
+      for (int z0 = 0; z0 <= N; z0 += kPenZ)
+        for (int y0 = 0; y0 + z0 <= N; y0 += kPenR)
+          for (int x0 = 0; x0 + y0 + z0 <= N; x0 += kTileW) L.tiles.push_back({(int32_t)c, x0, y0, z0});
     }
   }
   while (L.tiles.size() % kWavesPerWG) L.tiles.push_back({-1, 0, 0, 0});
@@ -376,9 +391,11 @@ int upload_level(mf_mesh* m, Level& L) {
   if ((rc = dev_upload(&D.grp_ptr, L.grp_ptr))) return rc;
   if ((rc = dev_upload(&D.copies, L.copies))) return rc;
   if ((rc = dev_upload(&D.grp_flag, L.grp_flag))) return rc;
-  if ((rc = dev_upload(&D.grp_invdiag, L.grp_invdiag))) return rc;
-  std::vector<float> f(L.grp_invdiag.begin(), L.grp_invdiag.end());
-  if ((rc = dev_upload(&D.grp_invdiagf, f))) return rc;
+  if ((rc = dev_upload(&D.xgrp_ptr, L.xgrp_ptr))) return rc;
+  if ((rc = dev_upload(&D.xcopies, L.xcopies))) return rc;
+  if ((rc = dev_upload(&D.xgrp_invdiag, L.xgrp_invdiag))) return rc;
+  std::vector<float> f(L.xgrp_invdiag.begin(), L.xgrp_invdiag.end());
+  if ((rc = dev_upload(&D.xgrp_invdiagf, f))) return rc;
   std::vector<double> zeros(2 * (L.n_partials() + 1), 0.0);
   if ((rc = dev_upload(&D.part, zeros))) return rc;
   std::vector<double> z2(2, 0.0);
@@ -545,7 +562,8 @@ int build_mesh(mf_mesh* m) {
 void free_device(mf_mesh* m) {
   for (auto& L : m->levels) {
     LevelDev& D = L.dev;
-    void* ptrs[] = {D.md, D.tiles, D.segs, D.grp_ptr, D.copies, D.grp_flag, D.grp_invdiag, D.grp_invdiagf,
+    void* ptrs[] = {D.md, D.tiles, D.segs, D.grp_ptr, D.copies, D.grp_flag, D.xgrp_ptr, D.xcopies, D.xgrp_invdiag,
+                    D.xgrp_invdiagf,
                     D.part, D.result, D.cinv, D.cinvf, D.cfirst, D.cptr, D.cidx};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);

@@ -18,15 +18,23 @@ namespace mf {
 // Performance Modeling, experiment description).  Four waves form a workgroup.
 constexpr int kWave = 64;
 constexpr int kTileW = 62;
-constexpr int kTileH2 = 64;   // rows per 2D wave tile
-constexpr int kTileH3 = 16;   // rows per 3D wave tile (one slice z)
+// Short strips keep the rows written at any moment within a few MB, so the
+// partial cache lines at wave boundaries are completed in L2 before write-back.
+#ifndef MF_TILE_H2
+#define MF_TILE_H2 8
+#endif
+constexpr int kTileH2 = MF_TILE_H2;   // rows per 2D wave tile
+// 3D: a wave walks a "pencil" of kPenR rows upward through kPenZ slices,
+// keeping the rows of slices z-1, z, z+1 in registers.
+constexpr int kPenR = 4;
+constexpr int kPenZ = 8;
 constexpr int kWavesPerWG = 4;
 constexpr int kWG = kWave * kWavesPerWG;
 constexpr int kIfaceWG = 256;  // groups per interface workgroup
 constexpr int kXCD = 8;        // MI355X: 8 accelerator complex dies, workgroups dealt round-robin
 
-// A wave tile: columns [x0, x0+62) of rows [y0, y0+H) of slice z of `macro`
-// (z = 0 in 2D).  For per-point kernels the same record names a row segment
+// A wave tile: columns [x0, x0+62) of rows [y0, y0+H) of `macro` (2D), or of
+// rows [y0, y0+kPenR) in slices [z, z+kPenZ) (3D).  For per-point kernels the same record names a row segment
 // of 64 points starting at x0 of row y0 in slice z.  macro < 0: padding.
 struct Tile {
   int32_t macro, x0, y0, z;
@@ -37,21 +45,26 @@ struct Copy {
   int32_t macro, x, y, z;
 };
 
-// Per-macro, per-level constants.  Element matrices K[t] are stored as 4x4
-// (2D uses the leading 3x3).
+// Per-macro, per-level constants.  wm[s] is the (partial) stencil of a point
+// whose non-zero barycentric weights are the local vertices in mask s: the
+// sum, over the micro-elements of this macro containing the point, of its
+// rows of the element matrices.  s = full (7 in 2D, 15 in 3D) is the
+// interior stencil; faces, edges and vertices of the macro get the rows of
+// the elements on their side only, which copies of a shared DoF then sum.
+// Element matrices K[t] are stored as 4x4 (2D uses the leading 3x3).
 struct MacroDev {
-  int64_t base;        // storage offset of the macro
-  int64_t vid[4];      // global vertex ids in cell order (for keys)
+  int64_t base;         // storage offset of the macro
+  int64_t vid[4];       // global vertex ids in cell order (for keys)
   int32_t N;
-  uint16_t own_mask;   // bit s: this macro owns the primitive spanned by local-vertex subset s
-  uint16_t dir_mask;   // bit s: that primitive lies on the Dirichlet boundary
-  double w[16];        // interior stencil (7 or 15 used)
-  float wf[16];
-  double inv_diag;     // 1 / centre weight (interior points)
+  uint16_t own_mask;    // bit s: this macro owns the primitive spanned by local-vertex subset s
+  uint16_t dir_mask;    // bit s: that primitive lies on the Dirichlet boundary
+  uint16_t shared_mask; // bit s: that primitive belongs to more than one macro
+  uint16_t pad0_;
   float inv_diagf;
-  float pad_;
+  double inv_diag;      // 1 / interior centre weight
+  double wm[16][16];
+  float wmf[16][16];
   double K[6][16];
-  float Kf[6][16];
 };
 
 // ---------------------------------------------------------------- layout
@@ -111,6 +124,8 @@ MF_HD constexpr StencilTable stencil_table(int dim) {
                        {0, -1, 0}, {1, -1, 0}, {-1, 0, 0}, {0, 0, 0}, {1, 0, 0}, {-1, 1, 0}, {0, 1, 0},
                        {0, -1, 1}, {1, -1, 1}, {-1, 0, 1}, {0, 0, 1}}};
 }
+
+MF_HD constexpr int full_mask(int dim) { return dim == 2 ? 7 : 15; }
 
 // Local-vertex support mask of point p of a macro: bit k set iff barycentric
 // weight k is non-zero (weights (N - sum p, p1, .., pd)).

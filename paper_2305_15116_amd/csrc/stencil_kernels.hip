@@ -1,17 +1,27 @@
-// Fused constant-stencil kernels for CDNA4 (gfx950): interior rows of every
-// macro (apply, weighted Jacobi, residual + norm partials) and the interface
-// kernel that completes macro-boundary rows.
+// Constant-stencil kernels for CDNA4 (gfx950): the operator's rows for every
+// point of every macro (apply, weighted Jacobi, residual + norm partials),
+// the exchange that completes rows of DoFs shared by several macros, and the
+// deterministic norm reduction.
 //
 // The paper's vertex-to-vertex kernel (Performance Modeling section) walks
 // one triangle row by row, x fastest, reading seven neighbours with constant
 // weights; on a CPU its speed depends on whether three source rows plus the
 // destination row fit in a cache level (the layer condition).  Here the same
-// reuse is kept in registers: one 64-lane wavefront owns 64 consecutive
-// columns and walks a strip of rows upward, holding rows y-1, y, y+1 (2D) or
-// the five rows of slices z-1, z, z+1 (3D) and exchanging the x+-1
-// neighbours through cross-lane shuffles, so every source value is read from
-// memory once per tile.  Future rows are loaded U rows ahead to keep enough
-// bytes in flight for HBM3E.  No matrix cores: the path is HBM-bound.
+// reuse is kept in registers: a 64-lane wavefront owns 64 consecutive
+// columns and walks rows upward (2D), or walks a pencil of rows upward
+// through the slices (3D), holding the rows the stencil needs and taking the
+// x+-1 neighbours from adjacent lanes through DPP shifts, so each source
+// value is read from memory once per tile; future rows are loaded ahead to
+// keep enough bytes in flight for HBM3E.  No matrix cores: the path is
+// HBM-bound.
+//
+// Macro-boundary DoFs are handled in the same walk (the paper leaves them to
+// interface primitives, Performance Modeling, experiment description): a
+// point on a face, edge or vertex of its macro uses the partial stencil of
+// its support mask — only the micro-elements on its side — and a DoF shared
+// by several macros is finished by the exchange kernel, which sums the
+// copies' partial rows in fixed macro order and writes the result to every
+// copy.
 
 #include <hip/hip_runtime.h>
 
@@ -22,33 +32,47 @@ namespace mf {
 namespace {
 
 template <typename T>
-__device__ __forceinline__ T wgt(const MacroDev& M, int i);
+struct Prec;
 template <>
-__device__ __forceinline__ double wgt<double>(const MacroDev& M, int i) { return M.w[i]; }
+struct Prec<double> {
+  static __device__ __forceinline__ double w(const MacroDev& M, int mask, int i) { return M.wm[mask][i]; }
+  static __device__ __forceinline__ double invd(const MacroDev& M) { return M.inv_diag; }
+  static __device__ __forceinline__ double ginv(const double* d, const float*, int g) { return d[g]; }
+};
 template <>
-__device__ __forceinline__ float wgt<float>(const MacroDev& M, int i) { return M.wf[i]; }
+struct Prec<float> {
+  static __device__ __forceinline__ float w(const MacroDev& M, int mask, int i) { return M.wmf[mask][i]; }
+  static __device__ __forceinline__ float invd(const MacroDev& M) { return M.inv_diagf; }
+  static __device__ __forceinline__ float ginv(const double*, const float* f, int g) { return f[g]; }
+};
 
-template <typename T>
-__device__ __forceinline__ T kel(const MacroDev& M, int t, int i);
-template <>
-__device__ __forceinline__ double kel<double>(const MacroDev& M, int t, int i) { return M.K[t][i]; }
-template <>
-__device__ __forceinline__ float kel<float>(const MacroDev& M, int t, int i) { return M.Kf[t][i]; }
+// Cross-lane neighbours through DPP wavefront shifts (a VALU op, no LDS
+// traffic): wave_shr:1 gives each lane the value of lane - 1, wave_shl:1 that
+// of lane + 1 (lanes 0 and 63 receive their own value; they are halo lanes).
+constexpr int kDppWaveShl1 = 0x130;
+constexpr int kDppWaveShr1 = 0x138;
 
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+  const int i = __builtin_bit_cast(int, v);
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(i, i, CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long l = __builtin_bit_cast(long long, v);
+  const int lo = (int)(l & 0xffffffffLL), hi = (int)(l >> 32);
+  const int rlo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
+  const int rhi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)rhi << 32) | (long long)(unsigned)rlo);
+}
 template <typename T>
-__device__ __forceinline__ T invd(const MacroDev& M);
-template <>
-__device__ __forceinline__ double invd<double>(const MacroDev& M) { return M.inv_diag; }
-template <>
-__device__ __forceinline__ float invd<float>(const MacroDev& M) { return M.inv_diagf; }
+__device__ __forceinline__ T up1(T v) { return dpp_move<kDppWaveShr1>(v); }  // value of lane - 1
+template <typename T>
+__device__ __forceinline__ T dn1(T v) { return dpp_move<kDppWaveShl1>(v); }  // value of lane + 1
 
+// Ordinary (write-back) stores: partial lines at wave boundaries merge in L2.
 template <typename T>
-__device__ __forceinline__ T up1(T v) { return __shfl_up(v, 1, kWave); }      // value of lane - 1
-template <typename T>
-__device__ __forceinline__ T dn1(T v) { return __shfl_down(v, 1, kWave); }    // value of lane + 1
-
-template <typename T>
-__device__ __forceinline__ void st(T* p, T v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void st(T* p, T v) { *p = v; }
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -72,352 +96,358 @@ __device__ __forceinline__ int xcd_wg(int nwg) {
   return n < nwg ? n : -1;
 }
 
-constexpr int kU2 = 8;  // rows loaded ahead (2D)
-constexpr int kU3 = 4;  // rows loaded ahead per slice (3D)
+#ifndef MF_RING_U2
+#define MF_RING_U2 4
+#endif
+constexpr int kU2 = MF_RING_U2;  // rows loaded ahead (2D)
+static_assert(kTileH2 % kU2 == 0, "ring depth must divide the tile height");
 
-// ------------------------------------------------------------------ 2D tile
-template <typename T, int MODE>
-__device__ __forceinline__ void tile2d(const Tile t, const MacroDev& M, const T* __restrict__ X,
-                                       T* __restrict__ Y, const T* __restrict__ B, T omega, double& ss,
-                                       double& mx) {
+// The wave's copy of its macro's partial stencils lives in LDS, so that the
+// per-lane lookups of boundary lanes are LDS reads and never wait on the
+// vector-memory counter that paces the row loads in flight.
+template <typename T>
+using WTab = T (*)[16];
+
+template <typename T>
+__device__ __forceinline__ void load_wtab(const MacroDev& M, WTab<T> W) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int N = M.N;
-  const int x = t.x0 - 1 + lane;
-  const int y0 = t.y0;
-  const int y1 = min(y0 + kTileH2, N - t.x0);  // rows with x0 + y <= N - 1
-  X += M.base;
-  Y += M.base;
-  if (MODE != kApply) B += M.base;
-  const T wS = wgt<T>(M, 0), wSE = wgt<T>(M, 1), wW = wgt<T>(M, 2), wC = wgt<T>(M, 3);
-  const T wE = wgt<T>(M, 4), wNW = wgt<T>(M, 5), wN = wgt<T>(M, 6);
-  const T id = invd<T>(M);
-
-  int r = y0 - 1;
-  int rs = (int)row_start(N, r);
-  T am = (x + r <= N) ? X[rs + x] : T(0);
-  rs += N + 1 - r;
-  ++r;
-  T a0 = (x + r <= N) ? X[rs + x] : T(0);
-  T am_r = dn1(am), a0_l = up1(a0), a0_r = dn1(a0);
-  int rs_c = rs;                   // start of output row y
-  int rp = r + 1;                  // next row to prefetch
-  int rs_p = rs + N + 1 - r;       // its start
-  T q[kU2];
-  T qb[kU2];
 #pragma unroll
-  for (int k = 0; k < kU2; ++k) {
-    q[k] = (rp <= y1 && x + rp <= N) ? X[rs_p + x] : T(0);
-    if (MODE != kApply) qb[k] = (rp - 1 < y1 && x + rp - 1 <= N) ? B[rs_p - (N + 2 - rp) + x] : T(0);
-    rs_p += N + 1 - rp;
-    ++rp;
-  }
-  for (int y = y0; y < y1; y += kU2) {
-#pragma unroll
-    for (int k = 0; k < kU2; ++k) {
-      const int yy = y + k;
-      const T ap = q[k];
-      const T bv = MODE != kApply ? qb[k] : T(0);
-      q[k] = (rp <= y1 && x + rp <= N) ? X[rs_p + x] : T(0);
-      if (MODE != kApply) qb[k] = (rp - 1 < y1 && x + rp - 1 <= N) ? B[rs_p - (N + 2 - rp) + x] : T(0);
-      rs_p += N + 1 - rp;
-      ++rp;
-      if (yy < y1) {
-        const T ap_l = up1(ap), ap_r = dn1(ap);
-        T acc = wS * am;
-        acc = fma(wSE, am_r, acc);
-        acc = fma(wW, a0_l, acc);
-        acc = fma(wC, a0, acc);
-        acc = fma(wE, a0_r, acc);
-        acc = fma(wNW, ap_l, acc);
-        acc = fma(wN, ap, acc);
-        const bool ok = lane >= 1 && lane <= kTileW && x + yy <= N - 1;
-        if (ok) {
-          const int o = rs_c + x;
-          if (MODE == kApply) {
-            st(Y + o, acc);
-          } else if (MODE == kJacobi) {
-            st(Y + o, fma(omega * id, bv - acc, a0));
-          } else {
-            const T rv = MODE == kNormB ? bv : bv - acc;
-            if (MODE == kResidual) st(Y + o, rv);
-            ss += (double)rv * (double)rv;
-            mx = fmax(mx, fabs((double)rv));
-          }
-        }
-        am = a0;
-        am_r = a0_r;
-        a0 = ap;
-        a0_l = ap_l;
-        a0_r = ap_r;
-        rs_c += N + 1 - yy;
-      }
-    }
-  }
+  for (int i = lane; i < 256; i += kWave) W[i >> 4][i & 15] = Prec<T>::w(M, i >> 4, i & 15);
+  __builtin_amdgcn_wave_barrier();
 }
 
-// ------------------------------------------------------------------ 3D tile
-// Slice z of a tetrahedral macro is a triangle of side M = N - z; the output
-// row y of slice z reads rows y, y+1 of slice z-1, rows y-1..y+1 of slice z
-// and rows y-1, y of slice z+1.
-template <typename T, int MODE>
-__device__ __forceinline__ void tile3d(const Tile t, const MacroDev& M, const T* __restrict__ X,
-                                       T* __restrict__ Y, const T* __restrict__ B, T omega, double& ss,
-                                       double& mx) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int N = M.N;
-  const int z = t.z;
-  const int S0 = N - z, Sm = S0 + 1, Sp = S0 - 1;
-  const int x = t.x0 - 1 + lane;
-  const int y0 = t.y0;
-  const int y1 = min(y0 + kTileH3, S0 - t.x0);
-  const T* Xm = X + M.base + slice_base(N, z - 1);
-  const T* X0 = X + M.base + slice_base(N, z);
-  const T* Xp = X + M.base + slice_base(N, z + 1);
-  T* Y0 = Y + M.base + slice_base(N, z);
-  const T* B0 = MODE != kApply ? B + M.base + slice_base(N, z) : nullptr;
-  T w[15];
-#pragma unroll
-  for (int i = 0; i < 15; ++i) w[i] = wgt<T>(M, i);
-  const T id = invd<T>(M);
-
-  // preloads: slice z-1 row y0; slice z rows y0-1, y0; slice z+1 row y0-1
-  int rsm = (int)row_start(Sm, y0);
-  T dm0 = (x + y0 <= Sm) ? Xm[rsm + x] : T(0);
-  rsm += Sm + 1 - y0;  // row y0+1 of slice z-1
-  int rs0 = (int)row_start(S0, y0 - 1);
-  T am = (x + y0 - 1 <= S0) ? X0[rs0 + x] : T(0);
-  rs0 += S0 + 1 - (y0 - 1);
-  T a0 = (x + y0 <= S0) ? X0[rs0 + x] : T(0);
-  int rs_c = rs0;                 // output row y in slice z
-  rs0 += S0 + 1 - y0;             // row y0+1 of slice z
-  int rsp = (int)row_start(Sp, y0 - 1);
-  T pm = (x + y0 - 1 <= Sp) ? Xp[rsp + x] : T(0);
-  rsp += Sp + 1 - (y0 - 1);       // row y0 of slice z+1
-  T dm0_r = dn1(dm0), am_r = dn1(am), a0_l = up1(a0), a0_r = dn1(a0), pm_r = dn1(pm);
-
-  // prefetch rings: slice z-1 row y+1, slice z row y+1, slice z+1 row y, b row y
-  T qm[kU3], q0[kU3], qp[kU3], qb[kU3];
-  int rm_next = y0 + 1, r0_next = y0 + 1, rp_next = y0, rb_next = y0;
-  int rsb = rs_c;
-#pragma unroll
-  for (int k = 0; k < kU3; ++k) {
-    qm[k] = (rm_next <= y1 && x + rm_next <= Sm) ? Xm[rsm + x] : T(0);
-    rsm += Sm + 1 - rm_next;
-    ++rm_next;
-    q0[k] = (r0_next <= y1 && x + r0_next <= S0) ? X0[rs0 + x] : T(0);
-    rs0 += S0 + 1 - r0_next;
-    ++r0_next;
-    qp[k] = (rp_next < y1 && x + rp_next <= Sp) ? Xp[rsp + x] : T(0);
-    rsp += Sp + 1 - rp_next;
-    ++rp_next;
-    if (MODE != kApply) qb[k] = (rb_next < y1 && x + rb_next <= S0) ? B0[rsb + x] : T(0);
-    rsb += S0 + 1 - rb_next;
-    ++rb_next;
-  }
-  for (int y = y0; y < y1; y += kU3) {
-#pragma unroll
-    for (int k = 0; k < kU3; ++k) {
-      const int yy = y + k;
-      const T dm1 = qm[k], ap = q0[k], p0 = qp[k];
-      const T bv = MODE != kApply ? qb[k] : T(0);
-      qm[k] = (rm_next <= y1 && x + rm_next <= Sm) ? Xm[rsm + x] : T(0);
-      rsm += Sm + 1 - rm_next;
-      ++rm_next;
-      q0[k] = (r0_next <= y1 && x + r0_next <= S0) ? X0[rs0 + x] : T(0);
-      rs0 += S0 + 1 - r0_next;
-      ++r0_next;
-      qp[k] = (rp_next < y1 && x + rp_next <= Sp) ? Xp[rsp + x] : T(0);
-      rsp += Sp + 1 - rp_next;
-      ++rp_next;
-      if (MODE != kApply) qb[k] = (rb_next < y1 && x + rb_next <= S0) ? B0[rsb + x] : T(0);
-      rsb += S0 + 1 - rb_next;
-      ++rb_next;
-      if (yy < y1) {
-        const T dm1_l = up1(dm1), dm1_r = dn1(dm1);
-        const T ap_l = up1(ap), ap_r = dn1(ap);
-        const T p0_l = up1(p0), p0_r = dn1(p0);
-        T acc = w[0] * dm0;
-        acc = fma(w[1], dm0_r, acc);
-        acc = fma(w[2], dm1, acc);
-        acc = fma(w[3], dm1_l, acc);
-        acc = fma(w[4], am, acc);
-        acc = fma(w[5], am_r, acc);
-        acc = fma(w[6], a0_l, acc);
-        acc = fma(w[7], a0, acc);
-        acc = fma(w[8], a0_r, acc);
-        acc = fma(w[9], ap_l, acc);
-        acc = fma(w[10], ap, acc);
-        acc = fma(w[11], pm, acc);
-        acc = fma(w[12], pm_r, acc);
-        acc = fma(w[13], p0_l, acc);
-        acc = fma(w[14], p0, acc);
-        const bool ok = lane >= 1 && lane <= kTileW && x + yy <= S0 - 1;
-        if (ok) {
-          const int o = rs_c + x;
-          if (MODE == kApply) {
-            st(Y0 + o, acc);
-          } else if (MODE == kJacobi) {
-            st(Y0 + o, fma(omega * id, bv - acc, a0));
-          } else {
-            const T rv = MODE == kNormB ? bv : bv - acc;
-            if (MODE == kResidual) st(Y0 + o, rv);
-            ss += (double)rv * (double)rv;
-            mx = fmax(mx, fabs((double)rv));
-          }
-        }
-        dm0 = dm1;
-        dm0_r = dm1_r;
-        am = a0;
-        am_r = a0_r;
-        a0 = ap;
-        a0_l = ap_l;
-        a0_r = ap_r;
-        pm = p0;
-        pm_r = p0_r;
-        rs_c += S0 + 1 - yy;
-      }
-    }
-  }
-}
-
+// Partial stencil sum for a point with support `mask`: neighbours outside
+// the macro (whose values in v are clamped stand-ins) are dropped by
+// selects, so the code is branch-free.
 template <typename T, int DIM>
-__device__ __forceinline__ T partial_row(const MacroDev& M, const T* __restrict__ X, int x, int y, int z) {
-  constexpr ElemTable ET = elem_table(DIM);
-  const int N = M.N;
+__device__ __forceinline__ T partial_sum(const WTab<T> W, int mask, int N, int x, int y, int z, const T* v) {
+  constexpr StencilTable ST = stencil_table(DIM);
   T acc = T(0);
 #pragma unroll
-  for (int t = 0; t < ET.ntypes; ++t) {
-#pragma unroll
-    for (int v = 0; v < ET.nv; ++v) {
-      const int ax = x - ET.off[t][v][0], ay = y - ET.off[t][v][1], az = DIM == 3 ? z - ET.off[t][v][2] : 0;
-      if (ax >= 0 && ay >= 0 && az >= 0 && ax + ay + az <= N - ET.slack[t]) {
-#pragma unroll
-        for (int u = 0; u < ET.nv; ++u) {
-          const int qx = ax + ET.off[t][u][0], qy = ay + ET.off[t][u][1], qz = az + ET.off[t][u][2];
-          const int64_t qi = M.base + (DIM == 2 ? idx2(N, qx, qy) : idx3(N, qx, qy, qz));
-          acc = fma(kel<T>(M, t, v * 4 + u), X[qi], acc);
-        }
-      }
-    }
+  for (int o = 0; o < ST.n; ++o) {
+    const int nx = x + ST.off[o][0], ny = y + ST.off[o][1], nz = z + ST.off[o][2];
+    const bool in = nx >= 0 && ny >= 0 && nz >= 0 && nx + ny + nz <= N;
+    acc = fma(W[mask][o], in ? v[o] : T(0), acc);
   }
   return acc;
 }
 
-template <typename T>
-__device__ __forceinline__ T ginvd(const double* d, const float* f, int g);
-template <>
-__device__ __forceinline__ double ginvd<double>(const double* d, const float*, int g) { return d[g]; }
-template <>
-__device__ __forceinline__ float ginvd<float>(const double*, const float* f, int g) { return f[g]; }
+// Finish the row of one point.  acc is its (partial) stencil value, xc and bv
+// its x and b entries.  Interior points, Dirichlet points (identity rows) and
+// points no other macro shares are finished here; shared non-Dirichlet points
+// get their partial row for the exchange.  Norm partials count each unique
+// DoF once (Dirichlet DoFs on shared primitives only in their owner).
+template <typename T, int DIM, int MODE>
+__device__ __forceinline__ void finish(const MacroDev& M, const WTab<T> W, int mask, T acc, T xc, T bv, T omega,
+                                       T* yp, double& ss, double& mx) {
+  constexpr int FM = full_mask(DIM);
+  constexpr StencilTable ST = stencil_table(DIM);
+  const bool full = mask == FM;
+  const bool dir = !full && ((M.dir_mask >> mask) & 1);
+  const bool shared = !full && ((M.shared_mask >> mask) & 1);
+  if (dir) {
+    const T out = MODE == kResidual ? bv - xc : (MODE == kNormB ? bv : xc);
+    if (MODE != kNormB) st(yp, out);
+    if ((MODE == kResidual || MODE == kNormB) && ((M.own_mask >> mask) & 1)) {
+      ss += (double)out * (double)out;
+      mx = fmax(mx, fabs((double)out));
+    }
+  } else if (full || !shared) {
+    T out;
+    if (MODE == kApply) out = acc;
+    else if (MODE == kJacobi) out = fma(omega * (full ? Prec<T>::invd(M) : T(1) / W[mask][ST.centre]), bv - acc, xc);
+    else if (MODE == kResidual) out = bv - acc;
+    else out = bv;
+    if (MODE != kNormB) st(yp, out);
+    if (MODE == kResidual || MODE == kNormB) {
+      ss += (double)out * (double)out;
+      mx = fmax(mx, fabs((double)out));
+    }
+  } else if (MODE != kNormB) {
+    st(yp, acc);
+  }
+}
+
+// Row of one point from its neighbour values v: the interior stencil for
+// every lane, then — only when some lane of the wave lies on a face, edge or
+// vertex of the macro (a uniform branch) — the partial stencils of those lanes.
+template <typename T, int DIM, int MODE>
+__device__ __forceinline__ void point_row(const MacroDev& M, const WTab<T> W, const T* wi, bool inside, int N, int x,
+                                          int y, int z, const T* v, T xc, T bv, T omega, T* yp, double& ss,
+                                          double& mx) {
+  constexpr int FM = full_mask(DIM);
+  constexpr int NO = DIM == 2 ? 7 : 15;
+  T acc = wi[0] * v[0];
+#pragma unroll
+  for (int o = 1; o < NO; ++o) acc = fma(wi[o], v[o], acc);
+  const int mask = support_mask(DIM, N, x, y, z);
+  const bool special = inside && mask != FM;
+  if (__builtin_amdgcn_ballot_w64(special)) {
+    const T pacc = partial_sum<T, DIM>(W, special ? mask : FM, N, x, y, z, v);
+    if (special) acc = pacc;
+    if (inside) finish<T, DIM, MODE>(M, W, mask, acc, xc, bv, omega, yp, ss, mx);
+  } else if (inside) {
+    T out;
+    if (MODE == kApply) out = acc;
+    else if (MODE == kJacobi) out = fma(omega * Prec<T>::invd(M), bv - acc, xc);
+    else if (MODE == kResidual) out = bv - acc;
+    else out = bv;
+    if (MODE != kNormB) st(yp, out);
+    if (MODE == kResidual || MODE == kNormB) {
+      ss += (double)out * (double)out;
+      mx = fmax(mx, fabs((double)out));
+    }
+  }
+}
+
+// ------------------------------------------------------------------ row cursors
+// Walks the rows of one triangle (side S) upward, yielding for row r the
+// storage offset of column x clamped into that row (row -1 reads row 0, rows
+// past `last` repeat row `last`): a valid point for every lane, so loads need
+// no predicate and the unrolled loop stays straight-line code.  Clamped
+// values are never used.
+struct RowCursor {
+  int r, rs, last, rs_last, S;
+  __device__ __forceinline__ void init(int S_, int r0, int last_) {
+    S = S_;
+    r = r0;
+    rs = r0 >= 0 ? (int)row_start(S_, r0) : 0;
+    last = last_;
+    rs_last = (int)row_start(S_, last_);
+  }
+  __device__ __forceinline__ int next(int x) {
+    const int xc = max(x, 0);
+    int o;
+    if (r < 0) o = min(xc, S);
+    else if (r <= last) o = rs + min(xc, S - r);
+    else o = rs_last + min(xc, S - last);
+    if (r >= 0) rs += S + 1 - r;
+    ++r;
+    return o;
+  }
+};
+
+// ------------------------------------------------------------------ 2D tile
+template <typename T, int MODE>
+__device__ __forceinline__ void tile2d(const int x0, const int y0, const MacroDev& M, WTab<T> W,
+                                       const T* __restrict__ X, T* __restrict__ Y, const T* __restrict__ B,
+                                       T omega, double& ss, double& mx) {
+  constexpr int FM = full_mask(2);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int N = M.N;
+  const int x = x0 - 1 + lane;
+  const int y1 = min(y0 + kTileH2, N - x0 + 1);  // rows y0 .. y1-1 (x0 + y <= N)
+  X += M.base;
+  Y += M.base;
+  if (MODE != kApply) B += M.base;
+  T wi[7];
+#pragma unroll
+  for (int o = 0; o < 7; ++o) wi[o] = Prec<T>::w(M, FM, o);
+
+  RowCursor cx, cb;
+  cx.init(N, y0 - 1, y1);
+  T am = X[cx.next(x)];
+  T a0 = X[cx.next(x)];
+  T am_r = dn1(am), a0_l = up1(a0), a0_r = dn1(a0);
+  cb.init(N, y0, y1 - 1);  // right-hand side rows = output rows
+  T q[kU2], qb[kU2];
+#pragma unroll
+  for (int k = 0; k < kU2; ++k) {
+    q[k] = X[cx.next(x)];
+    if (MODE != kApply) qb[k] = B[cb.next(x)];
+  }
+  load_wtab<T>(M, W);
+  // The tile's rows are fully unrolled so that the load ring needs no
+  // register copies at a loop back-edge (which would wait for every load in
+  // flight).  Loads are unconditional; rows past the tile's end only skip
+  // the arithmetic (a uniform branch).
+  int rs_c = (int)row_start(N, y0);  // start of output row y
+  const int nrows = y1 - y0;
+#pragma unroll
+  for (int k = 0; k < kTileH2; ++k) {
+    const int yy = y0 + k;
+    const T ap = q[k % kU2];
+    const T bv = MODE != kApply ? qb[k % kU2] : T(0);
+    q[k % kU2] = X[cx.next(x)];
+    if (MODE != kApply) qb[k % kU2] = B[cb.next(x)];
+    if (k >= nrows) continue;
+    const T ap_l = up1(ap), ap_r = dn1(ap);
+    const T v[7] = {am, am_r, a0_l, a0, a0_r, ap_l, ap};
+    const bool inside = lane >= 1 && lane <= kTileW && x + yy <= N;
+    point_row<T, 2, MODE>(M, W, wi, inside, N, x, yy, 0, v, a0, bv, omega, Y + rs_c + x, ss, mx);
+    am = a0;
+    am_r = a0_r;
+    a0 = ap;
+    a0_l = ap_l;
+    a0_r = ap_r;
+    rs_c += N + 1 - yy;
+  }
+}
+
+// ------------------------------------------------------------------ 3D pencil
+// Slice z of a tetrahedral macro is a triangle of side S = N - z.  Output row
+// y of slice z reads rows y, y+1 of slice z-1, rows y-1..y+1 of slice z and
+// rows y-1, y of slice z+1.  A wave keeps rows y0-1 .. y0+kPenR of five
+// consecutive slices in registers (z-1, z, z+1 and two in flight) and walks
+// z upward, so each value is loaded once per pencil.  Rows, columns and
+// slices outside the macro are clamped to a valid point (values never used).
+template <typename T, int MODE>
+__device__ __forceinline__ void pencil3d(const int x0, const int y0, const int z0, const MacroDev& M, WTab<T> W,
+                                         const T* __restrict__ X, T* __restrict__ Y, const T* __restrict__ B,
+                                         T omega, double& ss, double& mx) {
+  constexpr int FM = full_mask(3);
+  constexpr int NS = 5;
+  constexpr int NR = kPenR + 2;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int N = M.N;
+  const int x = x0 - 1 + lane;
+  const int nz = min(kPenZ, N + 1 - x0 - y0 - z0);  // output slices z0 .. z0+nz-1
+  X += M.base;
+  Y += M.base;
+  if (MODE != kApply) B += M.base;
+  T wi[15];
+#pragma unroll
+  for (int o = 0; o < 15; ++o) wi[o] = Prec<T>::w(M, FM, o);
+  auto off = [&](int zp, int y) -> int64_t {
+    zp = min(max(zp, 0), N);
+    const int S = N - zp;
+    const int yc = min(max(y, 0), S);
+    return slice_base(N, zp) + row_start(S, yc) + min(max(x, 0), S - yc);
+  };
+  T s[NS][NR];
+#pragma unroll
+  for (int i = 0; i < NS; ++i)
+#pragma unroll
+    for (int j = 0; j < NR; ++j) s[i][j] = X[off(z0 - 1 + i, y0 - 1 + j)];
+  T bq[2][kPenR];
+  if (MODE != kApply) {
+#pragma unroll
+    for (int j = 0; j < kPenR; ++j) bq[0][j] = B[off(z0, y0 + j)];
+  }
+  load_wtab<T>(M, W);
+#pragma unroll
+  for (int k = 0; k < kPenZ; ++k) {
+    const int z = z0 + k;
+    if (MODE != kApply && k + 1 < kPenZ) {
+#pragma unroll
+      for (int j = 0; j < kPenR; ++j) bq[(k + 1) % 2][j] = B[off(z + 1, y0 + j)];
+    }
+    const T* A = s[k % NS];
+    const T* Bs = s[(k + 1) % NS];
+    const T* C = s[(k + 2) % NS];
+    if (k < nz) {
+      const int S = N - z;
+      const int64_t zb = slice_base(N, z);
+#pragma unroll
+      for (int j = 1; j <= kPenR; ++j) {
+        const int y = y0 + j - 1;
+        const T v[15] = {A[j],      dn1(A[j]),  A[j + 1],      up1(A[j + 1]), Bs[j - 1],
+                         dn1(Bs[j - 1]), up1(Bs[j]), Bs[j],     dn1(Bs[j]),    up1(Bs[j + 1]),
+                         Bs[j + 1], C[j - 1],   dn1(C[j - 1]), up1(C[j]),     C[j]};
+        const bool inside = lane >= 1 && lane <= kTileW && x + y + z <= N;
+        const T bv = MODE != kApply ? bq[k % 2][j - 1] : T(0);
+        point_row<T, 3, MODE>(M, W, wi, inside, N, x, y, z, v, Bs[j], bv, omega, Y + zb + row_start(S, y) + x, ss,
+                              mx);
+      }
+    }
+    // slice z-1 is done: its slot takes slice z+4
+#pragma unroll
+    for (int j = 0; j < NR; ++j) s[k % NS][j] = X[off(z + NS - 1, y0 - 1 + j)];
+  }
+}
 
 // Arguments of one stencil launch (passed by value).
 template <typename T>
 struct StencilArgs {
   const Tile* tiles;
-  int ntiles;
-  int grid_int;  // blocks [0, grid_int) do interior tiles, the rest interface groups
+  int ntiles;   // wave tiles (one partial slot each)
+  int nwg;      // workgroups of tiles (natural order)
+  const MacroDev* md;
+  const T* X;
+  T* Y;
+  const T* B;
+  T omega;
+  double* part;  // sums at [0, np), maxima at [np, 2 np)
+  int np;
+};
+
+template <typename T, int DIM, int MODE>
+__global__ __launch_bounds__(kWG) void stencil_kernel(const StencilArgs<T> a) {
+  constexpr bool kPart = MODE == kResidual || MODE == kNormB;
+  const int n = xcd_wg(a.nwg);
+  if (n < 0) return;
+  // wave-uniform tile index: the tile and its macro constants load into scalar registers
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int ti = n * kWavesPerWG + wv;
+  const Tile t = a.tiles[ti];
+  __shared__ T wtab[kWavesPerWG][16][16];
+  double ss = 0.0, mx = 0.0;
+  if (t.macro >= 0) {
+    const MacroDev& M = a.md[t.macro];
+    if (DIM == 2)
+      tile2d<T, MODE>(t.x0, t.y0, M, wtab[wv], a.X, a.Y, a.B, a.omega, ss, mx);
+    else
+      pencil3d<T, MODE>(t.x0, t.y0, t.z, M, wtab[wv], a.X, a.Y, a.B, a.omega, ss, mx);
+  }
+  if (kPart && a.part != nullptr) {
+    ss = wave_sum(ss);
+    mx = wave_max(mx);
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+      a.part[ti] = ss;
+      a.part[a.np + ti] = mx;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ exchange
+template <typename T>
+struct GroupArgs {
   int ngroups;
   const int32_t* gptr;
   const Copy* copies;
-  const uint8_t* gflag;
-  const double* ginv;
+  const uint8_t* gflag;     // all-groups list only
+  const double* ginv;       // exchange list only
   const float* ginvf;
   const MacroDev* md;
   const T* X;
   T* Y;
   const T* B;
   T omega;
-  double* part;   // sums at [0, np), maxima at [np, 2 np); interface slots start at ntiles
+  double* part;  // block partials at [0, nblk), maxima at [np, ...)
   int np;
 };
 
-// One interface group (unique macro-boundary DoF): sum the partial rows of
-// its copies in fixed macro order, finish the row for MODE, write all copies.
+template <int DIM>
+__device__ __forceinline__ int64_t copy_index(const MacroDev& M, const Copy& c) {
+  return M.base + (DIM == 2 ? idx2(M.N, c.x, c.y) : idx3(M.N, c.x, c.y, c.z));
+}
+
+// One DoF shared by several macros and not Dirichlet: its copies hold
+// partial rows (written by stencil_kernel); sum them in fixed macro order,
+// finish the row, and write it to every copy.
 template <typename T, int DIM, int MODE>
-__device__ __forceinline__ void iface_group(const StencilArgs<T>& a, int g, double& ss, double& mx) {
-  const int c0 = a.gptr[g], c1 = a.gptr[g + 1];
-  const bool dir = a.gflag[g] & 1;
-  const Copy cp0 = a.copies[c0];
-  const MacroDev& M0 = a.md[cp0.macro];
-  const int64_t i0 = M0.base + (DIM == 2 ? idx2(M0.N, cp0.x, cp0.y) : idx3(M0.N, cp0.x, cp0.y, cp0.z));
-  bool write = true;
-  T out = T(0);
-  if (MODE == kExchangeSum) {
-    if (!dir) {
-      for (int c = c0; c < c1; ++c) {
-        const Copy cp = a.copies[c];
-        const MacroDev& Mc = a.md[cp.macro];
-        out += a.X[Mc.base + (DIM == 2 ? idx2(Mc.N, cp.x, cp.y) : idx3(Mc.N, cp.x, cp.y, cp.z))];
-      }
+__global__ __launch_bounds__(kIfaceWG) void exchange_kernel(const GroupArgs<T> a) {
+  const int g = blockIdx.x * kIfaceWG + threadIdx.x;
+  double ss = 0.0, mx = 0.0;
+  if (g < a.ngroups) {
+    const int c0 = a.gptr[g], c1 = a.gptr[g + 1];
+    const int64_t i0 = copy_index<DIM>(a.md[a.copies[c0].macro], a.copies[c0]);
+    T out;
+    if (MODE == kNormB) {
+      out = a.B[i0];
+    } else {
+      T acc = T(0);
+      for (int c = c0; c < c1; ++c) acc += a.Y[copy_index<DIM>(a.md[a.copies[c].macro], a.copies[c])];
+      if (MODE == kApply) out = acc;
+      else if (MODE == kJacobi) out = fma(a.omega * Prec<T>::ginv(a.ginv, a.ginvf, g), a.B[i0] - acc, a.X[i0]);
+      else out = a.B[i0] - acc;
+      for (int c = c0; c < c1; ++c) a.Y[copy_index<DIM>(a.md[a.copies[c].macro], a.copies[c])] = out;
     }
-  } else if (MODE == kDirichletSet) {
-    write = dir;
-    if (dir) out = a.B[i0];
-  } else if (MODE == kNormB) {
-    write = false;
-    out = a.B[i0];
-  } else if (dir) {
-    const T xv = a.X[i0];
-    if (MODE == kApply || MODE == kJacobi) out = xv;
-    else out = a.B[i0] - xv;
-  } else {
-    T acc = T(0);
-    for (int c = c0; c < c1; ++c) {
-      const Copy cp = a.copies[c];
-      acc += partial_row<T, DIM>(a.md[cp.macro], a.X, cp.x, cp.y, cp.z);
-    }
-    if (MODE == kApply) out = acc;
-    else if (MODE == kJacobi) out = fma(a.omega * ginvd<T>(a.ginv, a.ginvf, g), a.B[i0] - acc, a.X[i0]);
-    else out = a.B[i0] - acc;
-  }
-  if (MODE == kResidual || MODE == kNormB) {
     ss = (double)out * (double)out;
     mx = fabs((double)out);
   }
-  if (write) {
-    for (int c = c0; c < c1; ++c) {
-      const Copy cp = a.copies[c];
-      const MacroDev& Mc = a.md[cp.macro];
-      a.Y[Mc.base + (DIM == 2 ? idx2(Mc.N, cp.x, cp.y) : idx3(Mc.N, cp.x, cp.y, cp.z))] = out;
-    }
-  }
-}
-
-// The whole operator in one launch: interior wave tiles first (mapped to
-// XCDs in contiguous chunks), then one thread per interface group.  The two
-// parts write disjoint entries, so they need no ordering.
-template <typename T, int DIM, int MODE>
-__global__ __launch_bounds__(kWG) void stencil_kernel(const StencilArgs<T> a) {
-  constexpr bool kPart = MODE == kResidual || MODE == kNormB;
-  double ss = 0.0, mx = 0.0;
-  if ((int)blockIdx.x < a.grid_int) {
-    const int nwg = a.ntiles / kWavesPerWG;
-    const int n = xcd_wg(nwg);
-    if (n < 0) return;
-    const int ti = n * kWavesPerWG + (threadIdx.x >> 6);
-    const Tile t = a.tiles[ti];
-    if (t.macro >= 0) {
-      const MacroDev& M = a.md[t.macro];
-      if (DIM == 2)
-        tile2d<T, MODE>(t, M, a.X, a.Y, a.B, a.omega, ss, mx);
-      else
-        tile3d<T, MODE>(t, M, a.X, a.Y, a.B, a.omega, ss, mx);
-    }
-    if (kPart && a.part != nullptr) {
-      ss = wave_sum(ss);
-      mx = wave_max(mx);
-      if ((threadIdx.x & (kWave - 1)) == 0) {
-        a.part[ti] = ss;
-        a.part[a.np + ti] = mx;
-      }
-    }
-    return;
-  }
-  const int ib = blockIdx.x - a.grid_int;
-  const int g = ib * kWG + threadIdx.x;
-  if (g < a.ngroups) iface_group<T, DIM, MODE>(a, g, ss, mx);
-  if (kPart && a.part != nullptr) {
-    __shared__ double s_ss[kWavesPerWG], s_mx[kWavesPerWG];
+  if ((MODE == kResidual || MODE == kNormB) && a.part != nullptr) {
+    __shared__ double s_ss[kIfaceWG / kWave], s_mx[kIfaceWG / kWave];
     ss = wave_sum(ss);
     mx = wave_max(mx);
     const int w = threadIdx.x / kWave;
@@ -428,14 +458,34 @@ __global__ __launch_bounds__(kWG) void stencil_kernel(const StencilArgs<T> a) {
     __syncthreads();
     if (threadIdx.x == 0) {
       double p = 0.0, q = 0.0;
-      for (int i = 0; i < kWavesPerWG; ++i) {
+      for (int i = 0; i < kIfaceWG / kWave; ++i) {
         p += s_ss[i];
         q = fmax(q, s_mx[i]);
       }
-      a.part[a.ntiles + ib] = p;
-      a.part[a.np + a.ntiles + ib] = q;
+      a.part[blockIdx.x] = p;
+      a.part[a.np + blockIdx.x] = q;
     }
   }
+}
+
+// Every macro-boundary DoF: kExchangeSum (y = sum of x over the copies,
+// Dirichlet -> 0, in place allowed) or kDirichletSet (y = b at Dirichlet DoFs).
+template <typename T, int DIM, int MODE>
+__global__ __launch_bounds__(kIfaceWG) void iface_kernel(const GroupArgs<T> a) {
+  const int g = blockIdx.x * kIfaceWG + threadIdx.x;
+  if (g >= a.ngroups) return;
+  const int c0 = a.gptr[g], c1 = a.gptr[g + 1];
+  const bool dir = a.gflag[g] & 1;
+  if (MODE == kDirichletSet) {
+    if (!dir) return;
+    const T v = a.B[copy_index<DIM>(a.md[a.copies[c0].macro], a.copies[c0])];
+    for (int c = c0; c < c1; ++c) a.Y[copy_index<DIM>(a.md[a.copies[c].macro], a.copies[c])] = v;
+    return;
+  }
+  T out = T(0);
+  if (!dir)
+    for (int c = c0; c < c1; ++c) out += a.X[copy_index<DIM>(a.md[a.copies[c].macro], a.copies[c])];
+  for (int c = c0; c < c1; ++c) a.Y[copy_index<DIM>(a.md[a.copies[c].macro], a.copies[c])] = out;
 }
 
 __global__ __launch_bounds__(256) void reduce_kernel(const double* __restrict__ part, int64_t np,
@@ -468,21 +518,14 @@ int check_launch() {
   return MF_OK;
 }
 
-// interior: include the interior tiles; iface: include the interface groups
 template <typename T, int DIM, int MODE>
-void run(const Level& L, bool interior, bool iface, const void* x, void* y, const void* b, double omega,
-         double* part, int64_t np, hipStream_t s) {
+void run_stencil(const Level& L, const void* x, void* y, const void* b, double omega, double* part,
+                 hipStream_t s) {
+  const int64_t np = L.n_partials();
   StencilArgs<T> a;
   a.tiles = L.dev.tiles;
-  a.ntiles = interior ? (int)L.tiles.size() : 0;
-  const int nwg = a.ntiles / kWavesPerWG;
-  a.grid_int = interior ? kXCD * ((nwg + kXCD - 1) / kXCD) : 0;
-  a.ngroups = iface ? (int)L.ngroups() : 0;
-  a.gptr = L.dev.grp_ptr;
-  a.copies = L.dev.copies;
-  a.gflag = L.dev.grp_flag;
-  a.ginv = L.dev.grp_invdiag;
-  a.ginvf = L.dev.grp_invdiagf;
+  a.ntiles = (int)L.tiles.size();
+  a.nwg = a.ntiles / kWavesPerWG;
   a.md = L.dev.md;
   a.X = (const T*)x;
   a.Y = (T*)y;
@@ -490,47 +533,84 @@ void run(const Level& L, bool interior, bool iface, const void* x, void* y, cons
   a.omega = (T)omega;
   a.part = part;
   a.np = (int)np;
-  const int grid_if = (a.ngroups + kWG - 1) / kWG;
-  const int grid = a.grid_int + grid_if;
-  if (grid == 0) return;
-  hipLaunchKernelGGL((stencil_kernel<T, DIM, MODE>), dim3(grid), dim3(kWG), 0, s, a);
+  const int grid = kXCD * ((a.nwg + kXCD - 1) / kXCD);
+  if (grid > 0) hipLaunchKernelGGL((stencil_kernel<T, DIM, MODE>), dim3(grid), dim3(kWG), 0, s, a);
+  GroupArgs<T> g;
+  g.ngroups = (int)L.nxgroups();
+  if (g.ngroups == 0) return;
+  g.gptr = L.dev.xgrp_ptr;
+  g.copies = L.dev.xcopies;
+  g.gflag = nullptr;
+  g.ginv = L.dev.xgrp_invdiag;
+  g.ginvf = L.dev.xgrp_invdiagf;
+  g.md = L.dev.md;
+  g.X = (const T*)x;
+  g.Y = (T*)y;
+  g.B = (const T*)b;
+  g.omega = (T)omega;
+  g.part = part ? part + a.ntiles : nullptr;
+  g.np = (int)np;
+  hipLaunchKernelGGL((exchange_kernel<T, DIM, MODE>), dim3((int)L.xgroup_blocks()), dim3(kIfaceWG), 0, s, g);
+}
+
+template <typename T, int DIM, int MODE>
+void run_iface(const Level& L, const void* x, void* y, const void* b, hipStream_t s) {
+  GroupArgs<T> g;
+  g.ngroups = (int)L.ngroups();
+  if (g.ngroups == 0) return;
+  g.gptr = L.dev.grp_ptr;
+  g.copies = L.dev.copies;
+  g.gflag = L.dev.grp_flag;
+  g.ginv = nullptr;
+  g.ginvf = nullptr;
+  g.md = L.dev.md;
+  g.X = (const T*)x;
+  g.Y = (T*)y;
+  g.B = (const T*)b;
+  g.omega = T(0);
+  g.part = nullptr;
+  g.np = 0;
+  const int nblk = (g.ngroups + kIfaceWG - 1) / kIfaceWG;
+  hipLaunchKernelGGL((iface_kernel<T, DIM, MODE>), dim3(nblk), dim3(kIfaceWG), 0, s, g);
 }
 
 template <typename T, int DIM>
-void dispatch(int mode, const Level& L, bool interior, bool iface, const void* x, void* y, const void* b,
-              double omega, double* part, int64_t np, hipStream_t s) {
+void dispatch(int mode, const Level& L, const void* x, void* y, const void* b, double omega, double* part,
+              hipStream_t s) {
   switch (mode) {
-    case kApply: run<T, DIM, kApply>(L, interior, iface, x, y, b, omega, part, np, s); break;
-    case kJacobi: run<T, DIM, kJacobi>(L, interior, iface, x, y, b, omega, part, np, s); break;
-    case kResidual: run<T, DIM, kResidual>(L, interior, iface, x, y, b, omega, part, np, s); break;
-    case kNormB: run<T, DIM, kNormB>(L, interior, iface, x, y, b, omega, part, np, s); break;
-    case kExchangeSum: run<T, DIM, kExchangeSum>(L, false, true, x, y, b, omega, part, np, s); break;
-    default: run<T, DIM, kDirichletSet>(L, false, true, x, y, b, omega, part, np, s); break;
+    case kApply: run_stencil<T, DIM, kApply>(L, x, y, b, omega, part, s); break;
+    case kJacobi: run_stencil<T, DIM, kJacobi>(L, x, y, b, omega, part, s); break;
+    case kResidual: run_stencil<T, DIM, kResidual>(L, x, y, b, omega, part, s); break;
+    case kNormB: run_stencil<T, DIM, kNormB>(L, x, y, b, omega, part, s); break;
+    case kExchangeSum: run_iface<T, DIM, kExchangeSum>(L, x, y, b, s); break;
+    default: run_iface<T, DIM, kDirichletSet>(L, x, y, b, s); break;
   }
 }
 
-int launch(const mf_mesh* m, const Level& L, int dtype, int mode, bool interior, bool iface, const void* x,
-           void* y, const void* b, double omega, double* part, int64_t np, hipStream_t s) {
+int launch(const mf_mesh* m, const Level& L, int dtype, int mode, const void* x, void* y, const void* b,
+           double omega, double* part, hipStream_t s) {
   if (dtype == MF_F64) {
-    if (m->dim == 2) dispatch<double, 2>(mode, L, interior, iface, x, y, b, omega, part, np, s);
-    else dispatch<double, 3>(mode, L, interior, iface, x, y, b, omega, part, np, s);
+    if (m->dim == 2) dispatch<double, 2>(mode, L, x, y, b, omega, part, s);
+    else dispatch<double, 3>(mode, L, x, y, b, omega, part, s);
   } else {
-    if (m->dim == 2) dispatch<float, 2>(mode, L, interior, iface, x, y, b, omega, part, np, s);
-    else dispatch<float, 3>(mode, L, interior, iface, x, y, b, omega, part, np, s);
+    if (m->dim == 2) dispatch<float, 2>(mode, L, x, y, b, omega, part, s);
+    else dispatch<float, 3>(mode, L, x, y, b, omega, part, s);
   }
   return check_launch();
 }
 
 }  // namespace
 
+int64_t stencil_partials(const Level& L) { return L.n_partials(); }
+
 int launch_stencil(const mf_mesh* m, const Level& L, int dtype, int mode, const void* x, void* y, const void* b,
                    double omega, double* part, hipStream_t s) {
-  return launch(m, L, dtype, mode, true, true, x, y, b, omega, part, L.n_partials(), s);
+  return launch(m, L, dtype, mode, x, y, b, omega, part, s);
 }
 
 int launch_iface(const mf_mesh* m, const Level& L, int dtype, int mode, const void* x, void* y, const void* b,
                  hipStream_t s) {
-  return launch(m, L, dtype, mode, false, true, x, y, b, 0.0, nullptr, 0, s);
+  return launch(m, L, dtype, mode, x, y, b, 0.0, nullptr, s);
 }
 
 int launch_reduce(const double* part, int64_t np, double* result, hipStream_t s) {
