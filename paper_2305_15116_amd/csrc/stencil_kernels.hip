@@ -108,12 +108,12 @@ static_assert(kTileH2 % kU2 == 0, "ring depth must divide the tile height");
 template <typename T>
 using WTab = T (*)[16];
 
+// Copies the 16 x 16 partial-stencil table of macro M into W with `nthreads`
+// threads starting at `first` (a wave or the whole workgroup).
 template <typename T>
-__device__ __forceinline__ void load_wtab(const MacroDev& M, WTab<T> W) {
-  const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-  for (int i = lane; i < 256; i += kWave) W[i >> 4][i & 15] = Prec<T>::w(M, i >> 4, i & 15);
-  __builtin_amdgcn_wave_barrier();
+__device__ __forceinline__ void load_wtab(const MacroDev& M, WTab<T> W, int first, int nthreads) {
+  for (int i = (int)threadIdx.x - first; i < 256; i += nthreads)
+    if (i >= 0) W[i >> 4][i & 15] = Prec<T>::w(M, i >> 4, i & 15);
 }
 
 // Partial stencil sum for a point with support `mask`: neighbours outside
@@ -180,9 +180,10 @@ __device__ __forceinline__ void point_row(const MacroDev& M, const WTab<T> W, co
   T acc = wi[0] * v[0];
 #pragma unroll
   for (int o = 1; o < NO; ++o) acc = fma(wi[o], v[o], acc);
-  const int mask = support_mask(DIM, N, x, y, z);
-  const bool special = inside && mask != FM;
+  // y and z are uniform, so only x == 0 and the far face are per-lane tests
+  const bool special = inside && (x == 0 || y == 0 || (DIM == 3 && z == 0) || x + y + z == N);
   if (__builtin_amdgcn_ballot_w64(special)) {
+    const int mask = support_mask(DIM, N, x, y, z);
     const T pacc = partial_sum<T, DIM>(W, special ? mask : FM, N, x, y, z, v);
     if (special) acc = pacc;
     if (inside) finish<T, DIM, MODE>(M, W, mask, acc, xc, bv, omega, yp, ss, mx);
@@ -200,32 +201,25 @@ __device__ __forceinline__ void point_row(const MacroDev& M, const WTab<T> W, co
   }
 }
 
-// ------------------------------------------------------------------ row cursors
-// Walks the rows of one triangle (side S) upward, yielding for row r the
-// storage offset of column x clamped into that row (row -1 reads row 0, rows
-// past `last` repeat row `last`): a valid point for every lane, so loads need
-// no predicate and the unrolled loop stays straight-line code.  Clamped
-// values are never used.
-struct RowCursor {
-  int r, rs, last, rs_last, S;
-  __device__ __forceinline__ void init(int S_, int r0, int last_) {
-    S = S_;
-    r = r0;
-    rs = r0 >= 0 ? (int)row_start(S_, r0) : 0;
-    last = last_;
-    rs_last = (int)row_start(S_, last_);
-  }
-  __device__ __forceinline__ int next(int x) {
-    const int xc = max(x, 0);
-    int o;
-    if (r < 0) o = min(xc, S);
-    else if (r <= last) o = rs + min(xc, S - r);
-    else o = rs_last + min(xc, S - last);
-    if (r >= 0) rs += S + 1 - r;
-    ++r;
-    return o;
-  }
-};
+// ------------------------------------------------------------------ row loads
+// Start of row y in a triangle of side S in 32-bit arithmetic (exact for
+// every supported level: S <= 32768).
+__device__ __forceinline__ int rs32(int S, int y) { return y * (S + 2) - ((y * (y + 1)) >> 1); }
+
+// Value at column xc (>= 0) of row r of a triangle of side S stored at base,
+// with the row clamped to [0, last] and the column into the row: a valid
+// point for every lane, so loads need no predicate and the unrolled loops
+// stay straight-line code (clamped values are never used).  The row address
+// is wave-uniform (scalar registers); only the unsigned column offset is per
+// lane.
+template <typename T>
+__device__ __forceinline__ T ldrow(const T* __restrict__ base, int S, int r, int last, int xc) {
+  // the row is clamped into [0, S] as well: `last` may name the row past the
+  // triangle's apex, and the column offset must stay non-negative
+  const int rr = min(max(r, 0), min(last, S));
+  const unsigned byte = (unsigned)min(xc, S - rr) * (unsigned)sizeof(T);
+  return *(const T*)((const char*)(base + rs32(S, rr)) + byte);
+}
 
 // ------------------------------------------------------------------ 2D tile
 template <typename T, int MODE>
@@ -244,43 +238,38 @@ __device__ __forceinline__ void tile2d(const int x0, const int y0, const MacroDe
 #pragma unroll
   for (int o = 0; o < 7; ++o) wi[o] = Prec<T>::w(M, FM, o);
 
-  RowCursor cx, cb;
-  cx.init(N, y0 - 1, y1);
-  T am = X[cx.next(x)];
-  T a0 = X[cx.next(x)];
+  const int xc = max(x, 0);
+  T am = ldrow(X, N, y0 - 1, y1, xc);
+  T a0 = ldrow(X, N, y0, y1, xc);
   T am_r = dn1(am), a0_l = up1(a0), a0_r = dn1(a0);
-  cb.init(N, y0, y1 - 1);  // right-hand side rows = output rows
   T q[kU2], qb[kU2];
 #pragma unroll
   for (int k = 0; k < kU2; ++k) {
-    q[k] = X[cx.next(x)];
-    if (MODE != kApply) qb[k] = B[cb.next(x)];
+    q[k] = ldrow(X, N, y0 + 1 + k, y1, xc);                    // x rows y0+1 ..
+    if (MODE != kApply) qb[k] = ldrow(B, N, y0 + k, y1 - 1, xc);  // b rows = output rows
   }
-  load_wtab<T>(M, W);
   // The tile's rows are fully unrolled so that the load ring needs no
   // register copies at a loop back-edge (which would wait for every load in
   // flight).  Loads are unconditional; rows past the tile's end only skip
   // the arithmetic (a uniform branch).
-  int rs_c = (int)row_start(N, y0);  // start of output row y
   const int nrows = y1 - y0;
 #pragma unroll
   for (int k = 0; k < kTileH2; ++k) {
     const int yy = y0 + k;
     const T ap = q[k % kU2];
     const T bv = MODE != kApply ? qb[k % kU2] : T(0);
-    q[k % kU2] = X[cx.next(x)];
-    if (MODE != kApply) qb[k % kU2] = B[cb.next(x)];
+    q[k % kU2] = ldrow(X, N, y0 + 1 + k + kU2, y1, xc);
+    if (MODE != kApply) qb[k % kU2] = ldrow(B, N, y0 + k + kU2, y1 - 1, xc);
     if (k >= nrows) continue;
     const T ap_l = up1(ap), ap_r = dn1(ap);
     const T v[7] = {am, am_r, a0_l, a0, a0_r, ap_l, ap};
     const bool inside = lane >= 1 && lane <= kTileW && x + yy <= N;
-    point_row<T, 2, MODE>(M, W, wi, inside, N, x, yy, 0, v, a0, bv, omega, Y + rs_c + x, ss, mx);
+    point_row<T, 2, MODE>(M, W, wi, inside, N, x, yy, 0, v, a0, bv, omega, Y + rs32(N, yy) + (unsigned)xc, ss, mx);
     am = a0;
     am_r = a0_r;
     a0 = ap;
     a0_l = ap_l;
     a0_r = ap_r;
-    rs_c += N + 1 - yy;
   }
 }
 
@@ -308,36 +297,49 @@ __device__ __forceinline__ void pencil3d(const int x0, const int y0, const int z
   T wi[15];
 #pragma unroll
   for (int o = 0; o < 15; ++o) wi[o] = Prec<T>::w(M, FM, o);
-  auto off = [&](int zp, int y) -> int64_t {
-    zp = min(max(zp, 0), N);
+  const int xc = max(x, 0);
+  // Slice z of a macro starts at sum_{k<z} (S_k+1)(S_k+2)/2, S_k = N - k;
+  // bases are advanced incrementally (slices past N are clamped to slice N).
+  auto next_base = [&](int64_t zb, int zp) -> int64_t {  // base of slice zp+1 given base of zp
     const int S = N - zp;
-    const int yc = min(max(y, 0), S);
-    return slice_base(N, zp) + row_start(S, yc) + min(max(x, 0), S - yc);
+    return zp >= N ? zb : zb + ((int64_t)(S + 1) * (S + 2) >> 1);
+  };
+  auto ld = [&](const T* __restrict__ base, int64_t zb, int zp, int y) -> T {
+    const int S = N - min(zp, N);
+    return ldrow(base + zb, S, y, S, xc);
   };
   T s[NS][NR];
+  int64_t lb = z0 > 0 ? slice_base(N, z0 - 1) : 0;  // base of the next slice to load
+  int lz = max(z0 - 1, 0);                          // its (clamped) index
 #pragma unroll
-  for (int i = 0; i < NS; ++i)
+  for (int i = 0; i < NS; ++i) {
 #pragma unroll
-    for (int j = 0; j < NR; ++j) s[i][j] = X[off(z0 - 1 + i, y0 - 1 + j)];
+    for (int j = 0; j < NR; ++j) s[i][j] = ld(X, lb, lz, y0 - 1 + j);
+    if (z0 - 1 + i >= 0) {
+      lb = next_base(lb, lz);
+      lz = min(lz + 1, N);
+    }
+  }
+  int64_t zb = slice_base(N, z0);  // output slice base
   T bq[2][kPenR];
   if (MODE != kApply) {
 #pragma unroll
-    for (int j = 0; j < kPenR; ++j) bq[0][j] = B[off(z0, y0 + j)];
+    for (int j = 0; j < kPenR; ++j) bq[0][j] = ld(B, zb, z0, y0 + j);
   }
-  load_wtab<T>(M, W);
 #pragma unroll
   for (int k = 0; k < kPenZ; ++k) {
     const int z = z0 + k;
+    const int64_t zb1 = next_base(zb, min(z, N));
     if (MODE != kApply && k + 1 < kPenZ) {
 #pragma unroll
-      for (int j = 0; j < kPenR; ++j) bq[(k + 1) % 2][j] = B[off(z + 1, y0 + j)];
+      for (int j = 0; j < kPenR; ++j) bq[(k + 1) % 2][j] = ld(B, zb1, z + 1, y0 + j);
     }
     const T* A = s[k % NS];
     const T* Bs = s[(k + 1) % NS];
     const T* C = s[(k + 2) % NS];
     if (k < nz) {
       const int S = N - z;
-      const int64_t zb = slice_base(N, z);
+      T* Yz = Y + zb;
 #pragma unroll
       for (int j = 1; j <= kPenR; ++j) {
         const int y = y0 + j - 1;
@@ -346,13 +348,16 @@ __device__ __forceinline__ void pencil3d(const int x0, const int y0, const int z
                          Bs[j + 1], C[j - 1],   dn1(C[j - 1]), up1(C[j]),     C[j]};
         const bool inside = lane >= 1 && lane <= kTileW && x + y + z <= N;
         const T bv = MODE != kApply ? bq[k % 2][j - 1] : T(0);
-        point_row<T, 3, MODE>(M, W, wi, inside, N, x, y, z, v, Bs[j], bv, omega, Y + zb + row_start(S, y) + x, ss,
+        point_row<T, 3, MODE>(M, W, wi, inside, N, x, y, z, v, Bs[j], bv, omega, Yz + rs32(S, y) + (unsigned)xc, ss,
                               mx);
       }
     }
-    // slice z-1 is done: its slot takes slice z+4
+    // slice z-1 is done: its slot takes the next slice (z+4)
 #pragma unroll
-    for (int j = 0; j < NR; ++j) s[k % NS][j] = X[off(z + NS - 1, y0 - 1 + j)];
+    for (int j = 0; j < NR; ++j) s[k % NS][j] = ld(X, lb, lz, y0 - 1 + j);
+    lb = next_base(lb, lz);
+    lz = min(lz + 1, N);
+    zb = zb1;
   }
 }
 
@@ -381,13 +386,25 @@ __global__ __launch_bounds__(kWG) void stencil_kernel(const StencilArgs<T> a) {
   const int ti = n * kWavesPerWG + wv;
   const Tile t = a.tiles[ti];
   __shared__ T wtab[kWavesPerWG][16][16];
+  // the workgroup's four tiles usually share one macro: then one table serves
+  // all waves (one load per thread); otherwise each wave loads its own
+  const int m0 = a.tiles[n * kWavesPerWG].macro, m3 = a.tiles[n * kWavesPerWG + kWavesPerWG - 1].macro;
+  const bool same = m0 == m3;
+  if (same) {
+    if (m0 >= 0) load_wtab<T>(a.md[m0], wtab[0], 0, kWG);
+    __syncthreads();
+  } else if (t.macro >= 0) {
+    load_wtab<T>(a.md[t.macro], wtab[wv], wv * kWave, kWave);
+    __builtin_amdgcn_wave_barrier();
+  }
   double ss = 0.0, mx = 0.0;
   if (t.macro >= 0) {
     const MacroDev& M = a.md[t.macro];
+    WTab<T> W = wtab[same ? 0 : wv];
     if (DIM == 2)
-      tile2d<T, MODE>(t.x0, t.y0, M, wtab[wv], a.X, a.Y, a.B, a.omega, ss, mx);
+      tile2d<T, MODE>(t.x0, t.y0, M, W, a.X, a.Y, a.B, a.omega, ss, mx);
     else
-      pencil3d<T, MODE>(t.x0, t.y0, t.z, M, wtab[wv], a.X, a.Y, a.B, a.omega, ss, mx);
+      pencil3d<T, MODE>(t.x0, t.y0, t.z, M, W, a.X, a.Y, a.B, a.omega, ss, mx);
   }
   if (kPart && a.part != nullptr) {
     ss = wave_sum(ss);
