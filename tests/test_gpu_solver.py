@@ -1,0 +1,152 @@
+"""GPU multigrid solves through the C ABI, checked by the oracle.
+
+A solve is accepted when the oracle's own CSR recomputes its FP64 residual
+||b - A x|| / ||b|| <= rtol (to rounding), and, for the manufactured problem
+on meshes where the discrete solution has a closed form, when x matches that
+solution within kappa * rtol.
+"""
+import numpy as np
+import pytest
+
+import harness
+import paper_2305_15116_amd as P
+from oracle.oracle import OracleMesh, solve
+from paper_2305_15116_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    yield
+    torch.cuda.synchronize()
+
+
+def _manufactured(co, ce, L):
+    """b = lumped mass * d pi^2 u* with u* = prod sin(pi x_k) (zero on the
+    unit square / cube boundary), in storage layout, and the oracle mesh."""
+    m = P.create_macro_mesh(co, ce, L)
+    om = OracleMesh(co, ce, L)
+    s2u = harness.storage_to_unique(P.mesh_dof_keys(m, L), om.keys())
+    xyz = om.xyz()
+    dim = co.shape[1]
+    us = np.prod(np.sin(np.pi * xyz), axis=1)
+    bu = om.lumped_mass() * dim * np.pi ** 2 * us
+    bu[om.boundary()] = 0.0
+    return m, om, s2u, bu, us
+
+
+@pytest.mark.parametrize("mesh,L,mode", [("cube", 4, 0), ("cube", 4, 1), ("cube", 5, 1), ("square", 6, 0),
+                                         ("square", 6, 1)])
+def test_manufactured_solution(mesh, L, mode):
+    co, ce = W.kuhn_cube() if mesh == "cube" else W.two_triangle_square()
+    m, om, s2u, bu, us = _manufactured(co, ce, L)
+    b = torch.as_tensor(bu[s2u], device="cuda")
+    x = torch.zeros_like(b)
+    ws = torch.empty(P.mesh_workspace_bytes(m, L, mode), dtype=torch.uint8, device="cuda")
+    rc, it, rel, sec = P.vcycle_solve(m, L, b, x, ws, mode=mode, rtol=1e-10)
+    torch.cuda.synchronize()
+    assert rc == P.MF_OK and rel <= 1e-10
+    xs = x.cpu().numpy()
+    assert harness.copies_consistent(xs, s2u)
+    xu = np.zeros(om.n)
+    xu[s2u] = xs
+    r = bu - om.spmv(xu)
+    assert np.linalg.norm(r) / np.linalg.norm(bu) <= 1.01e-10
+    h = 1.0 / om.N
+    uh = us * (np.pi ** 2 * h ** 2 / 4) / np.sin(np.pi * h / 2) ** 2
+    uh[om.boundary()] = 0.0
+    # kappa(A) <= ~ (4/(pi h))^2 bounds the error of a 1e-10 residual
+    kappa = (4.0 / (np.pi * h)) ** 2
+    assert np.abs(xu - uh).max() <= 2 * kappa * 1e-10 * np.abs(uh).max()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_random_mesh_against_oracle_solve(mode):
+    co, ce = W.kuhn_cube("random", 5)
+    J, t = W.random_affine(3, 8)
+    co = W.apply_affine(co, J, t)
+    L = 4
+    m = P.create_macro_mesh(co, ce, L)
+    om = OracleMesh(co, ce, L)
+    s2u = harness.storage_to_unique(P.mesh_dof_keys(m, L), om.keys())
+    s, _ = P.mesh_num_dofs(m, L)
+    b = torch.empty(s, dtype=torch.float64, device="cuda")
+    P.mesh_fill_random(m, L, 31, b)
+    x = torch.zeros_like(b)
+    ws = torch.empty(P.mesh_workspace_bytes(m, L, mode), dtype=torch.uint8, device="cuda")
+    # stretched (cond J up to 10), randomly ordered tets slow point-Jacobi
+    # multigrid down, but it still converges
+    rc, it, rel, sec = P.vcycle_solve(m, L, b, x, ws, mode=mode, rtol=1e-10, max_iter=2000)
+    torch.cuda.synchronize()
+    assert rc == P.MF_OK, (it, rel)
+    bo = om.keyed_random(31)
+    uo = solve(om, bo, tol=1e-14)
+    xu = np.zeros(om.n)
+    xu[s2u] = x.cpu().numpy()
+    r = bo - om.spmv(xu)
+    assert np.linalg.norm(r) / np.linalg.norm(bo) <= 1.01e-10
+    # Dirichlet values are exactly b's
+    bnd = om.boundary()
+    assert np.array_equal(xu[bnd], bo[bnd])
+    kappa_bound = 1e5
+    assert np.abs(xu - uo).max() <= kappa_bound * 1e-10 * max(1.0, np.abs(uo).max())
+
+
+def test_split_solve_equals_single_solve():
+    """Checkpoint/resume: k/2 + k/2 iterations from the saved x equal k iterations, bitwise."""
+    co, ce = W.strip_3d(7)
+    L = 4
+    m = P.create_macro_mesh(co, ce, L)
+    s, _ = P.mesh_num_dofs(m, L)
+    b = torch.empty(s, dtype=torch.float64, device="cuda")
+    P.mesh_fill_random(m, L, 5, b)
+    ws = torch.empty(P.mesh_workspace_bytes(m, L, 1), dtype=torch.uint8, device="cuda")
+    x1 = torch.zeros_like(b)
+    rc, it, rel, _ = P.vcycle_solve(m, L, b, x1, ws, mode=1, rtol=0.0, max_iter=6)
+    assert rc == P.MF_NOT_CONVERGED and it == 6
+    x2 = torch.zeros_like(b)
+    P.vcycle_solve(m, L, b, x2, ws, mode=1, rtol=0.0, max_iter=3)
+    P.vcycle_solve(m, L, b, x2, ws, mode=1, rtol=0.0, max_iter=3)
+    torch.cuda.synchronize()
+    assert torch.equal(x1, x2)
+
+
+def test_nan_rhs_is_reported():
+    co, ce = W.two_triangle_square()
+    L = 4
+    m = P.create_macro_mesh(co, ce, L)
+    s, _ = P.mesh_num_dofs(m, L)
+    b = torch.zeros(s, dtype=torch.float64, device="cuda")
+    b[s // 2] = float("nan")
+    x = torch.zeros_like(b)
+    ws = torch.empty(P.mesh_workspace_bytes(m, L, 0), dtype=torch.uint8, device="cuda")
+    with pytest.raises(P.MFError) as e:
+        P.vcycle_solve(m, L, b, x, ws, mode=0)
+    assert e.value.code == P.MF_ENUMERIC
+
+
+def test_zero_rhs_converges_immediately():
+    co, ce = W.kuhn_cube()
+    m = P.create_macro_mesh(co, ce, 3)
+    s, _ = P.mesh_num_dofs(m, 3)
+    b = torch.zeros(s, dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(b)
+    ws = torch.empty(P.mesh_workspace_bytes(m, 3, 1), dtype=torch.uint8, device="cuda")
+    rc, it, rel, _ = P.vcycle_solve(m, 3, b, x, ws, mode=1)
+    assert rc == P.MF_OK and it == 0 and float(x.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("L", [0, 1, 2])
+def test_coarse_levels_solve_directly(L):
+    co, ce = W.strip_2d(6)
+    m = P.create_macro_mesh(co, ce, L)
+    s, _ = P.mesh_num_dofs(m, L)
+    b = torch.empty(s, dtype=torch.float64, device="cuda")
+    P.mesh_fill_random(m, L, 3, b)
+    x = torch.zeros_like(b)
+    ws = torch.empty(P.mesh_workspace_bytes(m, L, 0), dtype=torch.uint8, device="cuda")
+    rc, it, rel, _ = P.vcycle_solve(m, L, b, x, ws, mode=0, rtol=1e-12)
+    assert rc == P.MF_OK and it <= 2
