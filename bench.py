@@ -159,6 +159,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-extra", action="store_true")
+    ap.add_argument("--skip-solve", action="store_true", help="leave the V-cycle solve out of the extras")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device copy of 1 GiB (counter calibration for profiles)")
     args = ap.parse_args()
@@ -212,8 +213,9 @@ def main():
         cbw = copy_bandwidth(torch)
         extra["device_copy_GBps"] = cbw
         extra["apply2d_frac_of_copy"] = achieved / cbw
-        log("C4 solve: mixed vs fp64")
-        extra["solve_cube_l8"] = solve_bench(P, torch, W)
+        if not args.skip_solve:
+            log("solve: mixed vs fp64, cube level 8")
+            extra["solve_cube_l8"] = solve_bench(P, torch, W)
     cpu = None
     if not args.skip_cpu:
         log("cpu baseline (oracle)")
