@@ -22,6 +22,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -133,7 +135,8 @@ def solve_bench(P, torch, W, L=8, repeats=10):
     f = 3 * np.pi ** 2 * np.prod(np.sin(np.pi * xyz), axis=1)
     b = torch.as_tensor(h ** 3 * f, device="cuda")
     out = {}
-    for mode in (0, 1):
+    names = {0: "fp64", 1: "mixed", 2: "fp64_pcg", 3: "mixed_pcg"}
+    for mode in (0, 1, 2, 3):
         ws = torch.empty(P.mesh_workspace_bytes(m, L, mode), dtype=torch.uint8, device="cuda")
         x = torch.zeros(s, dtype=torch.float64, device="cuda")
         rc, it, rel, sec = P.vcycle_solve(m, L, b, x, ws, mode=mode, rtol=1e-10)
@@ -146,9 +149,61 @@ def solve_bench(P, torch, W, L=8, repeats=10):
         dt = (time.perf_counter() - t0) / repeats
         uh = np.prod(np.sin(np.pi * xyz), axis=1) * (np.pi ** 2 * h ** 2 / 4) / np.sin(np.pi * h / 2) ** 2
         err = float(np.abs(x.cpu().numpy() - uh).max())
-        out["mixed" if mode else "fp64"] = {"status": rc, "iters": it, "rel_res": rel, "ms_per_solve": dt * 1e3,
-                                            "solves_per_s": 1.0 / dt, "max_err_vs_discrete_solution": err}
+        out[names[mode]] = {"mode": mode, "status": rc, "iters": it, "rel_res": rel, "ms_per_solve": dt * 1e3,
+                            "solves_per_s": 1.0 / dt, "max_err_vs_discrete_solution": err}
+        del ws
     P.destroy_macro_mesh(m)
+    return out
+
+
+def serve_bench(torch, variant, n, util=0.75, budget_gib=200.0, calib_n=40):
+    """Serving workload: Poisson arrivals of solve requests (2D strips of 1-64
+    triangles, 3D rows of 1-64 Kuhn tets, seeded affine maps, tol 1e-8).
+    capped: 3D levels 5-8 and an arrival rate set to `util` of the plain
+    server's measured capacity; full: levels 5-11 at 200 requests/s."""
+    from paper_2305_15116_amd import loadgen, serving
+    budget = int(budget_gib * 2 ** 30)
+    levels3 = (5, 8) if variant == "capped" else (5, 11)
+    out = {"variant": variant, "n": n, "budget_GiB": budget_gib}
+    if variant == "capped":
+        sample = loadgen.requests(n=calib_n, rate=1.0, levels3=levels3, seed_arrival=16, seed_req=17)
+        srv = serving.Server(budget, batched=False, keep_solutions=False)
+        t0 = time.perf_counter()
+        futs = [srv.submit(r.dim, r.coords, r.cells, r.level, r.rhs_seed, r.tol) for r in sample]
+        infos = [f.result()[1] for f in futs]
+        srv.close()
+        svc = (max(i["t_done"] for i in infos) - t0) / calib_n
+        rate = util / svc
+        out["calibration"] = {"requests": calib_n, "plain_service_ms": svc * 1e3, "target_utilisation": util}
+    else:
+        rate = 200.0
+    out["rate_req_per_s"] = rate
+    reqs = loadgen.requests(n=n, rate=rate, levels3=levels3)
+    for name, batched in (("plain_fp64_fifo", False), ("batched_mixed", True)):
+        log(f"serving {variant}: {name}, {n} requests at {rate:.1f}/s")
+        srv = serving.Server(budget, batched=batched, keep_solutions=False)
+        out.setdefault("solver_modes", {})[name] = srv.mode
+        futs, t0, _ = loadgen.replay(srv, reqs)
+        infos, rejected, status = [], 0, {}
+        for f in futs:
+            try:
+                x, info = f.result()
+            except Exception:
+                rejected += 1
+                continue
+            infos.append(info)
+            status[info["status"]] = status.get(info["status"], 0) + 1
+        srv.close()
+        t1 = max([i["t_done"] for i in infos], default=t0)
+        st = serving.latency_stats(infos, t0, t1)
+        st.update({"rejected": rejected, "status_counts": {str(k): v for k, v in status.items()},
+                   "offered_req_per_s": rate, "achieved_req_per_s": len(infos) / max(t1 - t0, 1e-9),
+                   "gpu_busy_frac": srv.busy_s / max(t1 - t0, 1e-9),
+                   "mean_iters": float(np.mean([i["iters"] for i in infos])) if infos else None})
+        out[name] = st
+    if "p50_ms" in out["plain_fp64_fifo"] and "p50_ms" in out["batched_mixed"]:
+        out["p50_speedup"] = out["plain_fp64_fifo"]["p50_ms"] / out["batched_mixed"]["p50_ms"]
+        out["p99_speedup"] = out["plain_fp64_fifo"]["p99_ms"] / out["batched_mixed"]["p99_ms"]
     return out
 
 
@@ -160,6 +215,9 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-extra", action="store_true")
     ap.add_argument("--skip-solve", action="store_true", help="leave the V-cycle solve out of the extras")
+    ap.add_argument("--serve", choices=["none", "capped", "full"], default="capped",
+                    help="serving workload in the extras (full: 2000 requests at 200/s, levels 5-11)")
+    ap.add_argument("--serve-n", type=int, default=None, help="requests of the serving run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device copy of 1 GiB (counter calibration for profiles)")
     args = ap.parse_args()
@@ -216,6 +274,9 @@ def main():
         if not args.skip_solve:
             log("solve: mixed vs fp64, cube level 8")
             extra["solve_cube_l8"] = solve_bench(P, torch, W)
+        if args.serve != "none":
+            n = args.serve_n or (200 if args.serve == "capped" else 2000)
+            extra[f"serving_{args.serve}"] = serve_bench(torch, args.serve, n)
     cpu = None
     if not args.skip_cpu:
         log("cpu baseline (oracle)")

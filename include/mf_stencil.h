@@ -104,8 +104,8 @@ int mesh_dof_index(const mf_mesh* mesh, int level, int64_t n, const int64_t* mac
  * in the 2D order, then (0,-1,1),(1,-1,1),(-1,0,1),(0,0,1). */
 int mesh_stencil(const mf_mesh* mesh, int level, int64_t macro, double* weights);
 
-/* Bytes of device workspace vcycle_solve needs at `level` for mode 0 (all
- * FP64) or 1 (FP32 V-cycle inside FP64 iterative refinement). */
+/* Bytes of device workspace vcycle_solve needs at `level` for a solver mode
+ * (mf_solve_opts.mode, 0..3). */
 int mesh_workspace_bytes(const mf_mesh* mesh, int level, int mode, int64_t* bytes);
 
 /* Fill a storage vector with x = 2u - 1, u uniform in [0,1) from SplitMix64
@@ -113,6 +113,13 @@ int mesh_workspace_bytes(const mf_mesh* mesh, int level, int mode, int64_t* byte
  * U[-1,1) input that is equal on all copies of a shared DoF.  Asynchronous.
  * Test-input helper; no part of the operator. */
 int mesh_fill_random(const mf_mesh* mesh, int level, int dtype, uint64_t seed, void* x_dev, void* stream);
+
+/* y = b at Dirichlet DoFs (b_dev == NULL: y = 0 there); every other entry of
+ * y is left unchanged.  Sets boundary values of a right-hand side or an
+ * initial guess (the paper's benchmark problems fix Dirichlet values on the
+ * domain boundary, Performance Modeling, Experiment Description).
+ * Asynchronous. */
+int mesh_set_dirichlet(const mf_mesh* mesh, int level, int dtype, const void* b_dev, void* y_dev, void* stream);
 
 /* y = A x (paper: the "apply", i.e. an operator applied to a function,
  * Performance Modeling section).  Interior rows of each macro use its
@@ -152,7 +159,9 @@ int restrict_residual(const mf_mesh* mesh, int level, int dtype, const void* rf_
 int prolong_add(const mf_mesh* mesh, int level, int dtype, const void* ec_dev, void* xf_dev, void* stream);
 
 typedef struct {
-  int mode;         /* 0: all-FP64 V-cycles; 1: FP32 V-cycles + FP64 residual and update */
+  int mode;         /* 0: FP64 V-cycles in iterative refinement; 1: FP32 V-cycles in FP64 iterative
+                       refinement; 2: conjugate gradients preconditioned by one FP64 V-cycle per
+                       iteration; 3: the same with an FP32 V-cycle (FP64 recurrences) */
   int pre, post;    /* smoothing sweeps (default 2, 2) */
   int coarse_level; /* solved directly (default min(2, level)) */
   int max_iter;     /* outer iterations (default 50) */
@@ -166,13 +175,57 @@ typedef struct {
   double seconds;
 } mf_solve_info;
 
-/* Solve A x = b by V(pre,post)-cycles of geometric multigrid (levels are the
- * refinement hierarchy, Intro) inside iterative refinement.  x_dev holds the
- * initial guess (its Dirichlet entries are set to b's); workspace_dev must
- * hold mesh_workspace_bytes(level, opts->mode) bytes.  Returns MF_OK,
- * MF_NOT_CONVERGED (x = last iterate) or an error.  Synchronous. */
+/* Solve A x = b with V(pre,post)-cycles of geometric multigrid (levels are
+ * the refinement hierarchy, Intro) as the correction of iterative refinement
+ * (modes 0, 1) or as the preconditioner of conjugate gradients (modes 2, 3;
+ * every CG scalar stays on the device).  x_dev holds the initial guess (its
+ * Dirichlet entries are set to b's); workspace_dev must hold
+ * mesh_workspace_bytes(level, opts->mode) bytes.  The stopping test uses the
+ * FP64 residual over unique DoFs (recomputed each iteration in modes 0, 1;
+ * the CG recurrence in modes 2, 3).  Returns MF_OK, MF_NOT_CONVERGED (x =
+ * last iterate) or an error.  Synchronous; one device-to-host copy of two
+ * doubles per iteration. */
 int vcycle_solve(const mf_mesh* mesh, int level, const double* b_dev, double* x_dev, void* workspace_dev,
                  const mf_solve_opts* opts, mf_solve_info* info, void* stream);
+
+/* ---- Continuous batching of solves (serving) ----------------------------
+ * A batch advances many independent solves of the kind vcycle_solve runs
+ * (any meshes, dimensions and levels on the current device) together: each
+ * batch_step performs one outer iteration for every member, and every kernel
+ * of that iteration is launched once for all members that need it, its
+ * workgroups dealt out among them.  The V-cycles of members of different
+ * depth are aligned at their coarse level.  A member's arithmetic and its
+ * order are those of vcycle_solve on its own, so its result is bitwise equal
+ * to vcycle_solve with the same options.  This is the multigrid use of the
+ * refinement levels (Intro, "Hybrid Tetrahedral Grids") applied to many
+ * small problems at once, where single solves would be bound by launch
+ * latency rather than by memory bandwidth. */
+typedef struct mf_batch mf_batch;
+
+/* opts: as for vcycle_solve (mode, pre, post, max_iter, omega; rtol is per
+ * member; coarse_level < 0 or above a member's level selects min(2, level)).
+ * NULL = mode 1, V(2,2), 50 iterations, omega 2/3.  capacity: maximum members
+ * (1..4096).  Allocates a small device table and pinned staging. */
+int batch_create(const mf_solve_opts* opts, int capacity, mf_batch** out);
+int batch_destroy(mf_batch* batch);
+int batch_size(const mf_batch* batch, int* n);
+
+/* Adds a solve of A x = b at `level` of `mesh`; x_dev holds the initial guess,
+ * workspace_dev at least mesh_workspace_bytes(level, opts.mode) bytes.  The
+ * caller keeps mesh, b, x and workspace alive and untouched until the member
+ * is reported done.  tag identifies the member (unique within the batch).
+ * MF_ENOMEM when the batch is full. */
+int batch_add(mf_batch* batch, const mf_mesh* mesh, int level, const double* b_dev, double* x_dev,
+              void* workspace_dev, double rtol, int64_t tag);
+
+/* One outer iteration for every member (synchronises `stream` once).
+ * Members that finished — converged (MF_OK), reached max_iter
+ * (MF_NOT_CONVERGED) or met a non-finite norm (MF_ENUMERIC) — leave the
+ * batch and are reported in done_tags / done_status / done_info (each with
+ * room for batch_size() entries; done_info may be NULL); *n_done = their
+ * number.  done_info.seconds = time since batch_add. */
+int batch_step(mf_batch* batch, void* stream, int64_t* done_tags, int* done_status, mf_solve_info* done_info,
+               int* n_done);
 
 #ifdef __cplusplus
 }

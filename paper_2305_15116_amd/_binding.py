@@ -23,7 +23,8 @@ MF_FLAG_DIRICHLET, MF_FLAG_HOST_ONLY = 1, 2
 #: every symbol include/mf_stencil.h declares
 EXPORTS = ["mf_last_error", "create_macro_mesh", "destroy_macro_mesh", "mesh_info", "mesh_num_dofs",
            "mesh_dof_keys", "mesh_dof_index", "mesh_stencil", "mesh_workspace_bytes", "mesh_fill_random",
-           "apply_stencil", "smooth", "residual", "restrict_residual", "prolong_add", "vcycle_solve"]
+           "mesh_set_dirichlet", "apply_stencil", "smooth", "residual", "restrict_residual", "prolong_add",
+           "vcycle_solve", "batch_create", "batch_destroy", "batch_size", "batch_add", "batch_step"]
 
 
 class MFError(RuntimeError):
@@ -62,12 +63,18 @@ def lib():
         L.mesh_stencil.argtypes = [vp, i, i64, vp]
         L.mesh_workspace_bytes.argtypes = [vp, i, i, C.POINTER(i64)]
         L.mesh_fill_random.argtypes = [vp, i, i, C.c_uint64, vp, vp]
+        L.mesh_set_dirichlet.argtypes = [vp, i, i, vp, vp, vp]
         L.apply_stencil.argtypes = [vp, i, i, vp, vp, vp]
         L.smooth.argtypes = [vp, i, i, dbl, i, vp, vp, vp, vp]
         L.residual.argtypes = [vp, i, i, vp, vp, vp, C.POINTER(dbl), vp]
         L.restrict_residual.argtypes = [vp, i, i, vp, vp, vp]
         L.prolong_add.argtypes = [vp, i, i, vp, vp, vp]
         L.vcycle_solve.argtypes = [vp, i, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
+        L.batch_create.argtypes = [C.POINTER(SolveOpts), i, C.POINTER(vp)]
+        L.batch_destroy.argtypes = [vp]
+        L.batch_size.argtypes = [vp, C.POINTER(i)]
+        L.batch_add.argtypes = [vp, vp, i, vp, vp, vp, dbl, i64]
+        L.batch_step.argtypes = [vp, vp, vp, vp, C.POINTER(SolveInfo), C.POINTER(i)]
         for name in EXPORTS[1:]:
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -181,6 +188,12 @@ def mesh_fill_random(mesh: Mesh, level: int, seed: int, x, stream=None):
     _check(lib().mesh_fill_random(mesh, level, _dtype_code(x), seed, C.c_void_p(x.data_ptr()), _stream(stream)))
 
 
+def mesh_set_dirichlet(mesh: Mesh, level: int, b, y, stream=None):
+    """y = b at Dirichlet DoFs (b=None: 0 there); other entries unchanged."""
+    _check(lib().mesh_set_dirichlet(mesh, level, _dtype_code(y), None if b is None else C.c_void_p(b.data_ptr()),
+                                    C.c_void_p(y.data_ptr()), _stream(stream)))
+
+
 def apply_stencil(mesh: Mesh, level: int, x, y, stream=None):
     _check(lib().apply_stencil(mesh, level, _dtype_code(x), C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
                                _stream(stream)))
@@ -219,3 +232,61 @@ def vcycle_solve(mesh: Mesh, level: int, b, x, workspace, mode: int = 0, pre: in
                                    C.c_void_p(workspace.data_ptr()), C.byref(o), C.byref(info), _stream(stream)),
                 allow=(MF_OK, MF_NOT_CONVERGED))
     return rc, info.iters, info.rel_res, info.seconds
+
+
+class Batch:
+    """Owner of an mf_batch* (continuous batching of solves); destroyed with the object."""
+
+    def __init__(self, handle, capacity):
+        self.handle = handle
+        self.capacity = capacity
+
+    def close(self):
+        if self.handle:
+            lib().batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def _as_parameter_(self):
+        return C.c_void_p(self.handle)
+
+
+def batch_create(capacity: int, mode: int = 1, pre: int = 2, post: int = 2, coarse_level: int = -1,
+                 max_iter: int = 50, omega: float = 2.0 / 3.0) -> Batch:
+    o = SolveOpts(mode, pre, post, coarse_level, max_iter, omega, 0.0)
+    out = C.c_void_p()
+    _check(lib().batch_create(C.byref(o), capacity, C.byref(out)))
+    return Batch(out.value, capacity)
+
+
+def batch_destroy(batch: Batch):
+    batch.close()
+
+
+def batch_size(batch: Batch) -> int:
+    n = C.c_int()
+    _check(lib().batch_size(batch, C.byref(n)))
+    return n.value
+
+
+def batch_add(batch: Batch, mesh: Mesh, level: int, b, x, workspace, rtol: float, tag: int):
+    _check(lib().batch_add(batch, mesh, level, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
+                           C.c_void_p(workspace.data_ptr()), rtol, tag))
+
+
+def batch_step(batch: Batch, stream=None):
+    """One outer iteration for every member; returns [(tag, status, iters, rel_res, seconds)] of those done."""
+    cap = max(1, batch.capacity)
+    tags = np.empty(cap, np.int64)
+    status = np.empty(cap, np.int32)
+    infos = (SolveInfo * cap)()
+    n = C.c_int()
+    _check(lib().batch_step(batch, _stream(stream), tags.ctypes.data, status.ctypes.data, infos, C.byref(n)))
+    return [(int(tags[k]), int(status[k]), infos[k].iters, infos[k].rel_res, infos[k].seconds)
+            for k in range(n.value)]

@@ -22,6 +22,7 @@
 #include "mf_stencil.h"
 #include "launch.hpp"
 #include "mesh.hpp"
+#include "solver.hpp"
 
 using namespace mf;
 
@@ -90,59 +91,6 @@ int jacobi_sweeps(const mf_mesh* m, const Level& L, int dtype, double omega, int
   return MF_OK;
 }
 
-constexpr int64_t kAlign = 256;
-int64_t align_up(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-struct Workspace {
-  std::vector<void*> b, x, t;  // per level
-  double* r64 = nullptr;
-  double* e64 = nullptr;
-  double* t64 = nullptr;
-  double* part = nullptr;
-  double* result = nullptr;
-  int64_t bytes = 0;
-};
-
-// Carves the workspace (base may be null to only measure it).
-Workspace carve(const mf_mesh* m, int level, int mode, int lc, char* base) {
-  Workspace w;
-  int64_t off = 0;
-  auto take = [&](int64_t nbytes) -> void* {
-    void* p = base ? (void*)(base + off) : nullptr;
-    off += align_up(nbytes);
-    return p;
-  };
-  const int64_t SL = m->levels[level].storage;
-  w.b.assign(level + 1, nullptr);
-  w.x.assign(level + 1, nullptr);
-  w.t.assign(level + 1, nullptr);
-  w.r64 = (double*)take(8 * SL);
-  if (mode == 0) {
-    w.e64 = (double*)take(8 * SL);
-    w.t64 = (double*)take(8 * SL);
-    w.b[level] = w.r64;
-    w.x[level] = w.e64;
-    w.t[level] = w.t64;
-    for (int l = lc; l < level; ++l) {
-      const int64_t S = m->levels[l].storage;
-      w.b[l] = take(8 * S);
-      w.x[l] = take(8 * S);
-      w.t[l] = take(8 * S);
-    }
-  } else {
-    for (int l = lc; l <= level; ++l) {
-      const int64_t S = m->levels[l].storage;
-      w.b[l] = take(4 * S);
-      w.x[l] = take(4 * S);
-      w.t[l] = take(4 * S);
-    }
-  }
-  w.part = (double*)take(8 * 2 * (m->levels[level].n_partials() + 1));
-  w.result = (double*)take(8 * 2);
-  w.bytes = off;
-  return w;
-}
-
 int vcycle(const mf_mesh* m, int l, int lc, int dtype, const Workspace& w, const mf_solve_opts& o, hipStream_t s) {
   const Level& L = m->levels[l];
   if (l == lc) return launch_coarse_solve(L, dtype, w.b[l], w.x[l], s);
@@ -156,8 +104,6 @@ int vcycle(const mf_mesh* m, int l, int lc, int dtype, const Workspace& w, const
   if (!rc) rc = jacobi_sweeps(m, L, dtype, o.omega, o.post, w.b[l], w.x[l], w.t[l], s);
   return rc;
 }
-
-int default_coarse(int level) { return std::min(2, level); }
 
 }  // namespace
 
@@ -262,7 +208,7 @@ int mesh_stencil(const mf_mesh* m, int level, int64_t macro, double* w) {
 int mesh_workspace_bytes(const mf_mesh* m, int level, int mode, int64_t* bytes) {
   int rc = check_mesh(m, level, false);
   if (rc) return rc;
-  if (mode != 0 && mode != 1) return set_error(MF_EINVAL, "mode must be 0 or 1");
+  if (mode < 0 || mode > 3) return set_error(MF_EINVAL, "mode must be 0, 1, 2 or 3");
   if (!bytes) return set_error(MF_EINVAL, "NULL output");
   *bytes = carve(m, level, mode, 0, nullptr).bytes;
   return MF_OK;
@@ -274,6 +220,14 @@ int mesh_fill_random(const mf_mesh* m, int level, int dtype, uint64_t seed, void
   if (rc) return rc;
   if (!x) return set_error(MF_EINVAL, "x is NULL");
   return launch_fill_random(m, m->levels[level], dtype, seed, x, (hipStream_t)stream);
+}
+
+int mesh_set_dirichlet(const mf_mesh* m, int level, int dtype, const void* b, void* y, void* stream) {
+  int rc = check_mesh(m, level, true);
+  if (!rc) rc = check_dtype(dtype);
+  if (rc) return rc;
+  if (!y) return set_error(MF_EINVAL, "y is NULL");
+  return launch_iface(m, m->levels[level], dtype, kDirichletSet, y, y, b, (hipStream_t)stream);
 }
 
 int apply_stencil(const mf_mesh* m, int level, int dtype, const void* x, void* y, void* stream) {
@@ -342,7 +296,7 @@ int vcycle_solve(const mf_mesh* m, int level, const double* b, double* x, void* 
   if (!b || !x || !workspace) return set_error(MF_EINVAL, "NULL vector or workspace");
   mf_solve_opts o = {0, 2, 2, default_coarse(level), 50, 2.0 / 3.0, 1e-10};
   if (opts) o = *opts;
-  if (o.mode != 0 && o.mode != 1) return set_error(MF_EINVAL, "mode must be 0 or 1");
+  if (o.mode < 0 || o.mode > 3) return set_error(MF_EINVAL, "mode must be 0, 1, 2 or 3");
   if (o.pre < 0 || o.post < 0 || o.max_iter < 0 || !(o.rtol >= 0.0))
     return set_error(MF_EINVAL, "bad solver options");
   if (o.coarse_level < 0 || o.coarse_level > level) return set_error(MF_EINVAL, "coarse_level outside [0, level]");
@@ -356,7 +310,8 @@ int vcycle_solve(const mf_mesh* m, int level, const double* b, double* x, void* 
   hipStream_t s = (hipStream_t)stream;
   const Level& L = m->levels[level];
   const Workspace w = carve(m, level, o.mode, 0, (char*)workspace);
-  const int vdt = o.mode == 0 ? MF_F64 : MF_F32;
+  const bool f32 = mode_f32(o.mode), pcg = mode_pcg(o.mode);
+  const int vdt = f32 ? MF_F32 : MF_F64;
   // Dirichlet entries of x take b's values; the correction never changes them.
   rc = launch_iface(m, L, MF_F64, kDirichletSet, x, x, b, s);
   // ||b|| over unique DoFs
@@ -364,28 +319,52 @@ int vcycle_solve(const mf_mesh* m, int level, const double* b, double* x, void* 
   if (!rc) rc = vector_norm(m, L, MF_F64, b, w.part, w.result, &ss, &mx, s);
   if (rc) return rc;
   const double bnorm = std::sqrt(ss);
+  // r = b - A x; PCG scalars start at zero (first direction p = z)
+  rc = residual_norm(m, L, MF_F64, b, x, w.r64, w.part, w.result, &ss, &mx, s);
+  if (!rc && pcg) rc = launch_fill(MF_F64, w.result + 2, 0.0, 6, s);
+  if (rc) return rc;
+  const int64_t nseg = (int64_t)L.segs.size();
   int it = 0;
   double rel = 0.0;
   bool converged = false;
   for (;;) {
-    rc = residual_norm(m, L, MF_F64, b, x, w.r64, w.part, w.result, &ss, &mx, s);
-    if (rc) return rc;
     rel = bnorm > 0.0 ? std::sqrt(ss) / bnorm : std::sqrt(ss);
     if (rel <= o.rtol || mx == 0.0) {
       converged = true;
       break;
     }
     if (it >= o.max_iter) break;
-    if (o.mode == 1) {
+    // preconditioner / correction: one V-cycle on r from zero
+    if (f32) {
       // scale r by its max norm before the cast so FP32 keeps its relative precision
-      rc = launch_scale_to_f32(w.r64, (float*)w.b[level], 1.0 / mx, L.storage, s);
+      rc = launch_scale_to_f32(w.r64, (float*)w.b[level], w.result, L.storage, s);
       if (!rc) rc = launch_fill(MF_F32, w.x[level], 0.0, L.storage, s);
-      if (!rc) rc = vcycle(m, level, lc, vdt, w, o, s);
-      if (!rc) rc = launch_axpy_f32(x, (const float*)w.x[level], mx, L.storage, s);
     } else {
       rc = launch_fill(MF_F64, w.x[level], 0.0, L.storage, s);
-      if (!rc) rc = vcycle(m, level, lc, vdt, w, o, s);
-      if (!rc) rc = launch_axpy(MF_F64, x, w.x[level], 1.0, L.storage, s);
+    }
+    if (!rc) rc = vcycle(m, level, lc, vdt, w, o, s);
+    if (rc) return rc;
+    if (!pcg) {
+      // iterative refinement: x += e, then the new residual
+      if (f32) rc = launch_axpy_f32(x, (const float*)w.x[level], w.result, L.storage, s);
+      else rc = launch_axpy(MF_F64, x, w.x[level], 1.0, L.storage, s);
+      if (!rc) rc = residual_norm(m, L, MF_F64, b, x, w.r64, w.part, w.result, &ss, &mx, s);
+    } else {
+      // conjugate gradients preconditioned by the V-cycle; scalars stay on the device
+      rc = launch_pcg_zdot(m, L, vdt, w.r64, w.x[level], w.z64, w.result, w.part, s);
+      if (!rc) rc = launch_reduce_shift(w.part, nseg, w.result + 2, s);                // r.z, previous r.z
+      if (!rc) rc = launch_pcg_dir(w.p64, w.z64, w.result, L.storage, s);              // p = z + beta p
+      if (!rc) rc = launch_stencil(m, L, MF_F64, kApplyDot, w.p64, w.q64, nullptr, 0.0, w.part, s);
+      if (!rc) rc = launch_reduce(w.part, stencil_partials(L), w.result + 4, s);       // p.Ap
+      if (!rc) rc = launch_pcg_update(m, L, x, w.r64, w.p64, w.q64, w.result, w.part, s);
+      if (!rc) rc = launch_reduce(w.part, nseg, w.result, s);                          // r.r, max|r|
+      double out[2] = {0.0, 0.0};
+      if (!rc) rc = sync_result(w.result, out, s);
+      if (!rc) {
+        ss = out[0];
+        mx = out[1];
+        if (!std::isfinite(ss) || !std::isfinite(mx)) rc = set_error(MF_ENUMERIC, "residual norm is not finite");
+      }
     }
     if (rc) return rc;
     ++it;

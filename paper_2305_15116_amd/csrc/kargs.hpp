@@ -1,0 +1,261 @@
+// Kernel argument records and batched launches.
+//
+// Every kernel of the library takes one Launch<A>: either the arguments of a
+// single request by value (nseg == 0), or a device table of per-request
+// arguments, in which request r owns the launch's workgroups
+// [wg0[r], wg0[r+1]).  A batched launch therefore runs the same kernel over
+// the tiles of many requests at once (continuous batching of solves), and
+// each request's work is decomposed exactly as in its own launch, so its
+// results are bitwise the same.
+#pragma once
+
+#include <cstdint>
+
+#include "mesh.hpp"
+
+namespace mf {
+
+template <class A>
+struct Launch {
+  A one;               // nseg == 0: the single request's arguments
+  const A* many;       // nseg > 0: per-request arguments (device)
+  const int32_t* wg0;  // nseg > 0: nseg + 1 workgroup offsets (device), wg0[0] = 0
+  int nseg;
+  int nwg;             // workgroups of the whole launch
+};
+
+// The request that owns workgroup g: the last r with wg0[r] <= g (requests
+// with no workgroups share their offset with the next one and are skipped).
+MF_HD int find_seg(const int32_t* wg0, int nseg, int g) {
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (wg0[mid] <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// stencil_kernel: every point of every macro of one level.
+template <typename T>
+struct StencilArgs {
+  const Tile* tiles;
+  int ntiles;  // wave tiles (one partial slot each)
+  int nwg;     // workgroups of tiles (natural order)
+  const MacroDev* md;
+  const T* X;
+  T* Y;
+  const T* B;
+  T omega;
+  double* part;  // sums at [0, np), maxima at [np, 2 np)
+  int np;
+};
+
+// exchange_kernel / iface_kernel: groups of copies of macro-boundary DoFs.
+template <typename T>
+struct GroupArgs {
+  int ngroups;
+  const int32_t* gptr;
+  const Copy* copies;
+  const uint8_t* gflag;  // all-groups list only
+  const double* ginv;    // exchange list only
+  const float* ginvf;
+  const MacroDev* md;
+  const T* X;
+  T* Y;
+  const T* B;
+  T omega;
+  double* part;  // block partials at [0, nblk), maxima at [np, ...)
+  int np;
+};
+
+// restrict_kernel / prolong_add_kernel: per-point segments of one level.
+template <typename T>
+struct TransferArgs {
+  const Tile* segs;
+  int nseg;
+  const MacroDev* mdc;
+  const MacroDev* mdf;
+  const T* src;
+  T* dst;
+};
+
+// coarse_solve_kernel
+template <typename T>
+struct CoarseArgs {
+  int n;
+  const T* Ainv;
+  const int32_t* first;
+  const int32_t* cptr;
+  const int64_t* cidx;
+  const T* B;
+  T* X;
+};
+
+// Plain vector kernels (fill, copy, axpy and the FP32 <-> FP64 pair of the
+// mixed solver, whose scale comes from a device norm result).
+struct VecArgs {
+  void* y;
+  const void* x;
+  const double* res;  // result pair (sum of squares, max |.|) of a reduction
+  int64_t n;
+  double a;
+  int nblk;  // grid-stride blocks of this request
+};
+
+// reduce_kernel: one block per request.
+struct ReduceArgs {
+  const double* part;
+  int64_t np;
+  double* result;  // 2 doubles: (sum, max), or (sum, previous sum) with shift
+  double* copy;    // nullable: a second copy of the 2 doubles
+  int shift;       // 1: result[1] takes the previous result[0] instead of the max
+  int pad_;
+};
+
+// Per-point kernels of preconditioned conjugate gradients: FP64 vectors, one
+// wave per 64-point row segment, partial sums over unique DoFs (owner copies).
+// Scalars live on the device in res: [0] r.r  [1] max |r|  [2] r.z
+// [3] previous r.z  [4] p.A p.
+struct PcgArgs {
+  const Tile* segs;
+  int nseg;
+  int pad_;
+  const MacroDev* md;
+  double* x;          // update: x += alpha p
+  double* r;          // zdot: read; update: r -= alpha q
+  double* p;          // update: read; direction: p = z + beta p
+  const double* q;    // update: A p
+  const void* e;      // zdot: preconditioner output (FP32 or FP64)
+  double* z;          // zdot: z = s e (not written when z == e)
+  const double* res;  // scalars
+  double* part;       // sums at [0, nseg), maxima at [nseg, 2 nseg)
+};
+
+inline int vec_blocks(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b > 8192) b = 8192;
+  return (int)(b < 1 ? 1 : b);
+}
+
+// ---------------------------------------------------------------- builders
+// The same records serve single launches and batch tables.
+template <typename T>
+StencilArgs<T> stencil_args(const Level& L, const void* x, void* y, const void* b, double omega, double* part) {
+  StencilArgs<T> a;
+  a.tiles = L.dev.tiles;
+  a.ntiles = (int)L.tiles.size();
+  a.nwg = a.ntiles / kWavesPerWG;
+  a.md = L.dev.md;
+  a.X = (const T*)x;
+  a.Y = (T*)y;
+  a.B = (const T*)b;
+  a.omega = (T)omega;
+  a.part = part;
+  a.np = (int)L.n_partials();
+  return a;
+}
+
+template <typename T>
+GroupArgs<T> exchange_args(const Level& L, const void* x, void* y, const void* b, double omega, double* part) {
+  GroupArgs<T> g;
+  g.ngroups = (int)L.nxgroups();
+  g.gptr = L.dev.xgrp_ptr;
+  g.copies = L.dev.xcopies;
+  g.gflag = nullptr;
+  g.ginv = L.dev.xgrp_invdiag;
+  g.ginvf = L.dev.xgrp_invdiagf;
+  g.md = L.dev.md;
+  g.X = (const T*)x;
+  g.Y = (T*)y;
+  g.B = (const T*)b;
+  g.omega = (T)omega;
+  g.part = part ? part + L.tiles.size() : nullptr;
+  g.np = (int)L.n_partials();
+  return g;
+}
+inline int exchange_blocks(const Level& L) { return (int)L.xgroup_blocks(); }
+
+template <typename T>
+GroupArgs<T> iface_args(const Level& L, const void* x, void* y, const void* b) {
+  GroupArgs<T> g;
+  g.ngroups = (int)L.ngroups();
+  g.gptr = L.dev.grp_ptr;
+  g.copies = L.dev.copies;
+  g.gflag = L.dev.grp_flag;
+  g.ginv = nullptr;
+  g.ginvf = nullptr;
+  g.md = L.dev.md;
+  g.X = (const T*)x;
+  g.Y = (T*)y;
+  g.B = (const T*)b;
+  g.omega = T(0);
+  g.part = nullptr;
+  g.np = 0;
+  return g;
+}
+inline int iface_blocks(const Level& L) { return (int)L.iface_blocks(); }
+
+// restriction: coarse points gather fine values; prolongation: fine points.
+template <typename T>
+TransferArgs<T> restrict_args(const Level& F, const Level& C, const void* rf, void* bc) {
+  return TransferArgs<T>{C.dev.segs, (int)C.segs.size(), C.dev.md, F.dev.md, (const T*)rf, (T*)bc};
+}
+template <typename T>
+TransferArgs<T> prolong_args(const Level& F, const Level& C, const void* ec, void* xf) {
+  return TransferArgs<T>{F.dev.segs, (int)F.segs.size(), C.dev.md, F.dev.md, (const T*)ec, (T*)xf};
+}
+inline int transfer_blocks(int nseg) { return (nseg + kWavesPerWG - 1) / kWavesPerWG; }
+
+template <typename T>
+CoarseArgs<T> coarse_args(const Level& L, const void* b, void* x);
+template <>
+inline CoarseArgs<double> coarse_args<double>(const Level& L, const void* b, void* x) {
+  return CoarseArgs<double>{(int)L.ncoarse, L.dev.cinv, L.dev.cfirst, L.dev.cptr, L.dev.cidx, (const double*)b,
+                            (double*)x};
+}
+template <>
+inline CoarseArgs<float> coarse_args<float>(const Level& L, const void* b, void* x) {
+  return CoarseArgs<float>{(int)L.ncoarse, L.dev.cinvf, L.dev.cfirst, L.dev.cptr, L.dev.cidx, (const float*)b,
+                           (float*)x};
+}
+inline int coarse_blocks(const Level& L) { return (int)((L.ncoarse + kWavesPerWG - 1) / kWavesPerWG); }
+
+inline VecArgs vec_args(void* y, const void* x, const double* res, int64_t n, double a) {
+  return VecArgs{y, x, res, n, a, vec_blocks(n)};
+}
+
+inline PcgArgs pcg_args(const Level& L, double* x, double* r, double* p, const double* q, const void* e, double* z,
+                        const double* res, double* part) {
+  return PcgArgs{L.dev.segs, (int)L.segs.size(), 0, L.dev.md, x, r, p, q, e, z, res, part};
+}
+inline int pcg_blocks(const Level& L) { return transfer_blocks((int)L.segs.size()); }
+
+// ---------------------------------------------------------------- batch ops
+enum OpKind : int {
+  kOpStencil = 0,  // StencilArgs<T>, mode = kApply / kJacobi / kResidual / kNormB
+  kOpExchange,     // GroupArgs<T>, same modes
+  kOpIface,        // GroupArgs<T>, mode = kExchangeSum / kDirichletSet
+  kOpReduce,       // ReduceArgs
+  kOpRestrict,     // TransferArgs<T>
+  kOpProlong,      // TransferArgs<T>
+  kOpCoarse,       // CoarseArgs<T>
+  kOpFill,         // VecArgs: y = a
+  kOpCopy,         // VecArgs: y = x
+  kOpAxpy,         // VecArgs: y += a x
+  kOpScaleF32,     // VecArgs: float y = x / res[1]
+  kOpAxpyF32,      // VecArgs: double y += res[1] * float x
+  kOpPcgZDot,      // PcgArgs, dtype = type of e: z = s e, partials of r . z
+  kOpPcgDir,       // VecArgs: y = x + beta y, beta = res[2] / res[3] (0 if res[3] == 0)
+  kOpPcgUpdate,    // PcgArgs: x += alpha p, r -= alpha q, alpha = res[2] / res[4]; partials of r . r
+};
+
+// One batched launch: a table of nseg argument records at args_off and nseg+1
+// workgroup offsets at wg0_off, inside the batch's device table.
+struct BatchOp {
+  int kind, dtype, dim, mode;
+  int nseg, nwg;
+  int64_t args_off, wg0_off;
+};
+
+}  // namespace mf

@@ -1,11 +1,13 @@
-// Host-side launchers of the HIP kernels (kernels.hip).  All are
-// asynchronous on `stream` and return an MF_* status.
+// Host-side launchers of the HIP kernels (stencil_kernels.hip,
+// vector_kernels.hip).  All are asynchronous on `stream` and return an MF_*
+// status.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 
+#include "kargs.hpp"
 #include "mesh.hpp"
 
 namespace mf {
@@ -38,7 +40,27 @@ int launch_coarse_solve(const Level& L, int dtype, const void* b, void* x, hipSt
 int launch_fill(int dtype, void* x, double v, int64_t n, hipStream_t s);
 int launch_copy(int dtype, void* dst, const void* src, int64_t n, hipStream_t s);
 int launch_axpy(int dtype, void* y, const void* x, double a, int64_t n, hipStream_t s);    // y += a x
-int launch_scale_to_f32(const double* r, float* b, double scale, int64_t n, hipStream_t s);  // b = float(scale r)
-int launch_axpy_f32(double* x, const float* e, double a, int64_t n, hipStream_t s);     // x += a double(e)
+// The mixed solver's pair: b = float((1 / res[1]) r) and x += res[1] double(e),
+// res = (sum of squares, max |.|) of r on the device.
+int launch_scale_to_f32(const double* r, float* b, const double* res, int64_t n, hipStream_t s);
+int launch_axpy_f32(double* x, const float* e, const double* res, int64_t n, hipStream_t s);
+
+// Preconditioned conjugate gradients (scalars in res, see PcgArgs):
+// z = s e and partials of r . z (edtype: type of e; z == e: not written);
+// x += alpha p, r -= alpha q and partials of r . r, max |r|; p = z + beta p.
+// Partials: L.segs.size() slots.
+int launch_pcg_zdot(const mf_mesh* m, const Level& L, int edtype, const double* r, const void* e, double* z,
+                    const double* res, double* part, hipStream_t s);
+int launch_pcg_update(const mf_mesh* m, const Level& L, double* x, double* r, double* p, const double* q,
+                      const double* res, double* part, hipStream_t s);
+int launch_pcg_dir(double* p, const double* z, const double* res, int64_t n, hipStream_t s);
+// result (2 doubles) = (sum, previous result[0]) of part[0, np)
+int launch_reduce_shift(const double* part, int64_t np, double* result, hipStream_t s);
+
+// Batched launches (one kernel over many requests; table = device base of
+// the op's argument table).  Stencil, exchange, iface and reduce ops:
+int launch_stencil_batch(const BatchOp& op, const char* table, hipStream_t s);
+// Transfer, coarse-solve and vector ops:
+int launch_vector_batch(const BatchOp& op, const char* table, hipStream_t s);
 
 }  // namespace mf

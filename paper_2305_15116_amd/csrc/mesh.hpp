@@ -63,6 +63,17 @@ struct Level {
   LevelDev dev;
 };
 
+// A vertex, edge or (3D) face of the macro mesh: the support of the
+// macro-boundary DoFs whose non-zero barycentric weights sit on exactly these
+// vertices.  cells lists every macro containing it, in increasing order, with
+// the local index (0..dim) of each of its vertices in that macro.
+struct Prim {
+  std::vector<int64_t> v;  // sorted global vertex ids
+  std::vector<int64_t> cell;
+  std::vector<std::array<int8_t, 3>> local;  // local[i][j]: local index of v[j] in cell[i]
+  bool dirichlet = false;
+};
+
 }  // namespace mf
 
 struct mf_mesh {
@@ -75,6 +86,7 @@ struct mf_mesh {
   std::vector<double> coords;
   std::vector<int64_t> cells;
   std::vector<uint16_t> own_mask, dir_mask, shared_mask;  // per macro
+  std::vector<mf::Prim> prims;                            // macro-boundary primitives, sorted by vertex ids
   std::vector<mf::Level> levels;
   std::mutex norm_mutex;  // serialises residual() calls that return a norm
 };

@@ -12,10 +12,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <map>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "mesh.hpp"
@@ -144,6 +146,25 @@ void for_each_boundary_point(int dim, int N, F&& fn) {
   }
 }
 
+// Runs fn(i) for i in [0, n) on up to 16 host threads when `work` is large.
+template <class F>
+void parallel_for(size_t n, int64_t work, F&& fn) {
+  unsigned nt = std::min(16u, std::max(1u, std::thread::hardware_concurrency()));
+  if (work < (1 << 20) || n < 2) nt = 1;
+  nt = (unsigned)std::min<size_t>(nt, n);
+  if (nt <= 1) {
+    for (size_t i = 0; i < n; ++i) fn(i);
+    return;
+  }
+  std::atomic<size_t> next{0};
+  std::vector<std::thread> th;
+  for (unsigned t = 0; t < nt; ++t)
+    th.emplace_back([&] {
+      for (size_t i; (i = next.fetch_add(1)) < n;) fn(i);
+    });
+  for (auto& t : th) t.join();
+}
+
 template <class T>
 int dev_upload(T** dst, const std::vector<T>& src) {
   *dst = nullptr;
@@ -215,6 +236,31 @@ static int build_topology(mf_mesh* m) {
       if (owner[prim] == c) m->own_mask[c] |= (uint16_t)(1u << s);
       if (containing[prim] >= 2) m->shared_mask[c] |= (uint16_t)(1u << s);
       if (dirichlet && on_boundary.count(prim)) m->dir_mask[c] |= (uint16_t)(1u << s);
+    }
+  // every proper vertex subset of a cell is a macro-boundary primitive
+  m->prims.clear();
+  std::map<std::vector<int64_t>, size_t> index;
+  for (auto& kv : containing) {
+    if ((int)kv.first.size() == d1) continue;
+    index[kv.first] = m->prims.size();
+    Prim P;
+    P.v = kv.first;
+    P.dirichlet = dirichlet && on_boundary.count(kv.first) > 0;
+    m->prims.push_back(std::move(P));
+  }
+  for (int64_t c = 0; c < m->nc; ++c)
+    for (int s = 1; s < (1 << d1) - 1; ++s) {
+      std::vector<int64_t> prim;
+      for (int k = 0; k < d1; ++k)
+        if (s & (1 << k)) prim.push_back(m->cells[c * d1 + k]);
+      std::sort(prim.begin(), prim.end());
+      Prim& P = m->prims[index.at(prim)];
+      std::array<int8_t, 3> loc{};
+      for (size_t j = 0; j < P.v.size(); ++j)
+        for (int k = 0; k < d1; ++k)
+          if (m->cells[c * d1 + k] == P.v[j]) loc[j] = (int8_t)k;
+      P.cell.push_back(c);  // cells are visited in increasing order
+      P.local.push_back(loc);
     }
   return MF_OK;
 }
@@ -298,54 +344,78 @@ static int build_level(mf_mesh* m, int level, Level& L) {
   }
   L.storage = off;
 
-  // interface groups: every macro-boundary point, grouped by key, copies in macro order
-  struct Ent {
-    PointKey k;
-    int32_t macro, x, y, z;
+  // interface groups: every macro-boundary DoF, primitive by primitive (the
+  // points whose support is exactly that vertex / edge / face), with one copy
+  // per containing macro in macro order.  Offsets are counted first, then the
+  // primitives are filled in parallel.
+  const size_t np = m->prims.size();
+  std::vector<int64_t> g_off(np + 1, 0), c_off(np + 1, 0), x_off(np + 1, 0), xc_off(np + 1, 0);
+  auto prim_points = [N](int p) -> int64_t {
+    if (p == 1) return 1;
+    if (p == 2) return std::max(N - 1, 0);
+    return N >= 2 ? (int64_t)(N - 1) * (N - 2) / 2 : 0;
   };
-  std::vector<Ent> ent;
-  for (int64_t c = 0; c < m->nc; ++c)
-    for_each_boundary_point(dim, N, [&](int x, int y, int z) {
-      ent.push_back({point_key(dim, &m->cells[c * d1], N, x, y, z), (int32_t)c, x, y, z});
-    });
-  std::sort(ent.begin(), ent.end(), [](const Ent& a, const Ent& b) {
-    if (!(a.k == b.k)) return a.k < b.k;
-    return a.macro < b.macro;
-  });
-  L.grp_ptr.clear();
-  L.copies.clear();
-  L.grp_flag.clear();
-  L.xgrp_ptr.clear();
-  L.xcopies.clear();
-  L.xgrp_invdiag.clear();
-  const int fmask = full_mask(dim);
-  for (size_t i = 0; i < ent.size();) {
-    size_t j = i;
-    while (j < ent.size() && ent[j].k == ent[i].k) ++j;
-    const int s0 = support_mask(dim, N, ent[i].x, ent[i].y, ent[i].z);
-    const bool dir = (m->dir_mask[ent[i].macro] >> s0) & 1;
-    L.grp_ptr.push_back((int32_t)L.copies.size());
-    L.grp_flag.push_back(dir ? 1 : 0);
-    for (size_t k = i; k < j; ++k) L.copies.push_back({ent[k].macro, ent[k].x, ent[k].y, ent[k].z});
-    if (!dir && j - i >= 2) {
-      // shared, not Dirichlet: the stencil kernel leaves partial rows in every
-      // copy and the exchange sums them; the assembled diagonal is the sum
-      // of the copies' partial centre weights
-      L.xgrp_ptr.push_back((int32_t)L.xcopies.size());
-      double diag = 0.0;
-      for (size_t k = i; k < j; ++k) {
-        L.xcopies.push_back({ent[k].macro, ent[k].x, ent[k].y, ent[k].z});
-        const int sk = support_mask(dim, N, ent[k].x, ent[k].y, ent[k].z);
-        diag += L.md[ent[k].macro].wm[sk][ST.centre];
-      }
-      L.xgrp_invdiag.push_back(diag != 0.0 ? 1.0 / diag : 0.0);
-    }
-    (void)fmask;
-    i = j;
+  for (size_t i = 0; i < np; ++i) {
+    const Prim& P = m->prims[i];
+    const int64_t n = prim_points((int)P.v.size()), nc = (int64_t)P.cell.size();
+    const bool xg = !P.dirichlet && nc >= 2;
+    g_off[i + 1] = g_off[i] + n;
+    c_off[i + 1] = c_off[i] + n * nc;
+    x_off[i + 1] = x_off[i] + (xg ? n : 0);
+    xc_off[i + 1] = xc_off[i] + (xg ? n * nc : 0);
   }
-  if (L.copies.size() > (size_t)INT32_MAX) return set_error(MF_ENOMEM, "too many interface copies");
-  L.grp_ptr.push_back((int32_t)L.copies.size());
-  L.xgrp_ptr.push_back((int32_t)L.xcopies.size());
+  if (c_off[np] > (int64_t)INT32_MAX) return set_error(MF_ENOMEM, "too many interface copies");
+  L.grp_ptr.assign(g_off[np] + 1, 0);
+  L.grp_flag.assign(g_off[np], 0);
+  L.copies.assign(c_off[np], Copy{});
+  L.xgrp_ptr.assign(x_off[np] + 1, 0);
+  L.xcopies.assign(xc_off[np], Copy{});
+  L.xgrp_invdiag.assign(x_off[np], 0.0);
+  L.grp_ptr[g_off[np]] = (int32_t)c_off[np];
+  L.xgrp_ptr[x_off[np]] = (int32_t)xc_off[np];
+  auto fill = [&](size_t i) {
+    const Prim& P = m->prims[i];
+    const int p = (int)P.v.size();
+    const size_t nc = P.cell.size();
+    const bool xg = !P.dirichlet && nc >= 2;
+    int64_t g = g_off[i], c = c_off[i], xi = x_off[i], xc = xc_off[i];
+    auto emit = [&](const int* w) {
+      L.grp_ptr[g] = (int32_t)c;
+      L.grp_flag[g] = P.dirichlet ? 1 : 0;
+      ++g;
+      double diag = 0.0;
+      if (xg) L.xgrp_ptr[xi] = (int32_t)xc;
+      for (size_t k = 0; k < nc; ++k) {
+        int wl[4] = {0, 0, 0, 0};
+        for (int j = 0; j < p; ++j) wl[P.local[k][j]] = w[j];
+        const Copy cp{(int32_t)P.cell[k], wl[1], wl[2], dim == 3 ? wl[3] : 0};
+        L.copies[c++] = cp;
+        if (xg) {
+          L.xcopies[xc++] = cp;
+          // the assembled diagonal is the sum of the copies' partial centre weights
+          diag += L.md[cp.macro].wm[support_mask(dim, N, cp.x, cp.y, cp.z)][ST.centre];
+        }
+      }
+      if (xg) L.xgrp_invdiag[xi++] = diag != 0.0 ? 1.0 / diag : 0.0;
+    };
+    int w[3];
+    if (p == 1) {
+      w[0] = N;
+      emit(w);
+    } else if (p == 2) {
+      for (w[0] = 1; w[0] <= N - 1; ++w[0]) {
+        w[1] = N - w[0];
+        emit(w);
+      }
+    } else {
+      for (w[0] = 1; w[0] <= N - 2; ++w[0])
+        for (w[1] = 1; w[0] + w[1] <= N - 1; ++w[1]) {
+          w[2] = N - w[0] - w[1];
+          emit(w);
+        }
+    }
+  };
+  parallel_for(np, c_off[np], fill);
   const int64_t ngroups = L.ngroups();
   // unique DoFs: interior points of every macro + groups
   int64_t interior = 0;
@@ -356,6 +426,7 @@ static int build_level(mf_mesh* m, int level, Level& L) {
   // wave tiles over every point of every macro, natural order: macro,
   // (slice chunk,) strip, band
   L.tiles.clear();
+  L.tiles.reserve((size_t)m->nc * (macro_points(dim, N) / (kTileW * (dim == 2 ? kTileH2 : kPenR * kPenZ)) * 2 + 64));
   for (int64_t c = 0; c < m->nc; ++c) {
     if (dim == 2) {
       for (int y0 = 0; y0 <= N; y0 += kTileH2)
@@ -370,6 +441,7 @@ static int build_level(mf_mesh* m, int level, Level& L) {
 
   // row segments of 64 points over every storage point
   L.segs.clear();
+  L.segs.reserve((size_t)m->nc * (macro_points(dim, N) / kWave * 2 + 64));
   for (int64_t c = 0; c < m->nc; ++c) {
     const int zmax = dim == 3 ? N : 0;
     for (int z = 0; z <= zmax; ++z) {

@@ -142,7 +142,11 @@ enum Mode : int {
   kJacobi = 1,    // y = x + omega D^-1 (b - A x)
   kResidual = 2,  // y = b - A x  (+ sum of squares and max |.| partials)
   kNormB = 3,     // no output; partials of b only (||b|| over unique DoFs)
+  kApplyDot = 4,  // y = A x  (+ partials of x . y over unique DoFs)
 };
+
+// Modes whose kernels leave (sum, max) partials.
+MF_HD constexpr bool has_partials(int mode) { return mode == kResidual || mode == kNormB || mode == kApplyDot; }
 
 // Interface-kernel-only modes.
 enum IfaceMode : int {

@@ -1,0 +1,85 @@
+// Solver workspace layout shared by vcycle_solve and the batched solver.
+#pragma once
+
+#include <algorithm>
+#include <cstdint>
+#include <vector>
+
+#include "mesh.hpp"
+
+namespace mf {
+
+constexpr int64_t kAlign = 256;
+inline int64_t align_up(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Solver modes: bit 0 = FP32 V-cycles (else FP64); bit 1 = preconditioned
+// conjugate gradients around the V-cycle (else iterative refinement).
+inline bool mode_f32(int mode) { return (mode & 1) != 0; }
+inline bool mode_pcg(int mode) { return (mode & 2) != 0; }
+
+struct Workspace {
+  std::vector<void*> b, x, t;  // per level
+  double* r64 = nullptr;
+  double* e64 = nullptr;
+  double* t64 = nullptr;
+  double* z64 = nullptr;  // PCG: preconditioned residual (== e64 in FP64 mode)
+  double* p64 = nullptr;  // PCG: search direction
+  double* q64 = nullptr;  // PCG: A p
+  double* part = nullptr;
+  double* result = nullptr;  // 8 doubles: r.r, max|r|, r.z, previous r.z, p.Ap
+  int64_t bytes = 0;
+};
+
+// Carves the workspace (base may be null to only measure it).  Per level l
+// in [lc, level]: right-hand side b[l], iterate x[l] and ping-pong t[l] of the
+// V-cycle (FP64 or FP32 by the mode); r64 = outer FP64 residual; the PCG
+// vectors; part and result = norm / dot partials and their reductions.
+inline Workspace carve(const mf_mesh* m, int level, int mode, int lc, char* base) {
+  Workspace w;
+  int64_t off = 0;
+  auto take = [&](int64_t nbytes) -> void* {
+    void* p = base ? (void*)(base + off) : nullptr;
+    off += align_up(nbytes);
+    return p;
+  };
+  const int64_t SL = m->levels[level].storage;
+  w.b.assign(level + 1, nullptr);
+  w.x.assign(level + 1, nullptr);
+  w.t.assign(level + 1, nullptr);
+  w.r64 = (double*)take(8 * SL);
+  if (!mode_f32(mode)) {
+    w.e64 = (double*)take(8 * SL);
+    w.t64 = (double*)take(8 * SL);
+    w.b[level] = w.r64;
+    w.x[level] = w.e64;
+    w.t[level] = w.t64;
+    for (int l = lc; l < level; ++l) {
+      const int64_t S = m->levels[l].storage;
+      w.b[l] = take(8 * S);
+      w.x[l] = take(8 * S);
+      w.t[l] = take(8 * S);
+    }
+  } else {
+    for (int l = lc; l <= level; ++l) {
+      const int64_t S = m->levels[l].storage;
+      w.b[l] = take(4 * S);
+      w.x[l] = take(4 * S);
+      w.t[l] = take(4 * S);
+    }
+  }
+  if (mode_pcg(mode)) {
+    w.z64 = mode_f32(mode) ? (double*)take(8 * SL) : w.e64;
+    w.p64 = (double*)take(8 * SL);
+    w.q64 = (double*)take(8 * SL);
+  }
+  const Level& L = m->levels[level];
+  const int64_t np = std::max<int64_t>(L.n_partials(), mode_pcg(mode) ? (int64_t)L.segs.size() : 0);
+  w.part = (double*)take(8 * 2 * (np + 1));
+  w.result = (double*)take(8 * 8);
+  w.bytes = off;
+  return w;
+}
+
+inline int default_coarse(int level) { return std::min(2, level); }
+
+}  // namespace mf

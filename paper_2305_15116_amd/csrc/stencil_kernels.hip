@@ -137,6 +137,18 @@ __device__ __forceinline__ T partial_sum(const WTab<T> W, int mask, int N, int x
 // points no other macro shares are finished here; shared non-Dirichlet points
 // get their partial row for the exchange.  Norm partials count each unique
 // DoF once (Dirichlet DoFs on shared primitives only in their owner).
+// Norm / dot partials of one finished row value `out` (xc = the point's x).
+template <typename T, int MODE>
+__device__ __forceinline__ void accum(double& ss, double& mx, T out, T xc) {
+  if (MODE == kResidual || MODE == kNormB) {
+    ss += (double)out * (double)out;
+    mx = fmax(mx, fabs((double)out));
+  } else if (MODE == kApplyDot) {
+    ss += (double)xc * (double)out;
+    mx = fmax(mx, fabs((double)out));
+  }
+}
+
 template <typename T, int DIM, int MODE>
 __device__ __forceinline__ void finish(const MacroDev& M, const WTab<T> W, int mask, T acc, T xc, T bv, T omega,
                                        T* yp, double& ss, double& mx) {
@@ -148,21 +160,15 @@ __device__ __forceinline__ void finish(const MacroDev& M, const WTab<T> W, int m
   if (dir) {
     const T out = MODE == kResidual ? bv - xc : (MODE == kNormB ? bv : xc);
     if (MODE != kNormB) st(yp, out);
-    if ((MODE == kResidual || MODE == kNormB) && ((M.own_mask >> mask) & 1)) {
-      ss += (double)out * (double)out;
-      mx = fmax(mx, fabs((double)out));
-    }
+    if ((M.own_mask >> mask) & 1) accum<T, MODE>(ss, mx, out, xc);
   } else if (full || !shared) {
     T out;
-    if (MODE == kApply) out = acc;
+    if (MODE == kApply || MODE == kApplyDot) out = acc;
     else if (MODE == kJacobi) out = fma(omega * (full ? Prec<T>::invd(M) : T(1) / W[mask][ST.centre]), bv - acc, xc);
     else if (MODE == kResidual) out = bv - acc;
     else out = bv;
     if (MODE != kNormB) st(yp, out);
-    if (MODE == kResidual || MODE == kNormB) {
-      ss += (double)out * (double)out;
-      mx = fmax(mx, fabs((double)out));
-    }
+    accum<T, MODE>(ss, mx, out, xc);
   } else if (MODE != kNormB) {
     st(yp, acc);
   }
@@ -189,15 +195,12 @@ __device__ __forceinline__ void point_row(const MacroDev& M, const WTab<T> W, co
     if (inside) finish<T, DIM, MODE>(M, W, mask, acc, xc, bv, omega, yp, ss, mx);
   } else if (inside) {
     T out;
-    if (MODE == kApply) out = acc;
+    if (MODE == kApply || MODE == kApplyDot) out = acc;
     else if (MODE == kJacobi) out = fma(omega * Prec<T>::invd(M), bv - acc, xc);
     else if (MODE == kResidual) out = bv - acc;
     else out = bv;
     if (MODE != kNormB) st(yp, out);
-    if (MODE == kResidual || MODE == kNormB) {
-      ss += (double)out * (double)out;
-      mx = fmax(mx, fabs((double)out));
-    }
+    accum<T, MODE>(ss, mx, out, xc);
   }
 }
 
@@ -361,26 +364,49 @@ __device__ __forceinline__ void pencil3d(const int x0, const int y0, const int z
   }
 }
 
-// Arguments of one stencil launch (passed by value).
-template <typename T>
-struct StencilArgs {
-  const Tile* tiles;
-  int ntiles;   // wave tiles (one partial slot each)
-  int nwg;      // workgroups of tiles (natural order)
-  const MacroDev* md;
-  const T* X;
-  T* Y;
-  const T* B;
-  T omega;
-  double* part;  // sums at [0, np), maxima at [np, 2 np)
-  int np;
-};
+// Argument tables are read-only for the whole launch: reading them through
+// the constant address space lets the compiler use scalar loads, so the
+// request's arguments stay in scalar registers as a by-value argument does.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T* as_const(const T* p) {
+  return (const __attribute__((address_space(4))) T*)p;
+}
+
+__device__ __forceinline__ int find_seg_c(const int32_t* wg0, int nseg, int g) {
+  const auto* w = as_const(wg0);
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (w[mid] <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Resolves workgroup g of a launch to its request's arguments and the
+// workgroup index inside that request.
+template <class A>
+__device__ __forceinline__ int resolve(const Launch<A>& L, int g, A& a) {
+  if (L.nseg == 0) {
+    a = L.one;
+    return g;
+  }
+  const int r = find_seg_c(L.wg0, L.nseg, g);
+#if defined(__HIP_DEVICE_COMPILE__)
+  a = as_const(L.many)[r];
+#else
+  a = L.many[r];  // the host pass only type-checks device code
+#endif
+  return g - as_const(L.wg0)[r];
+}
 
 template <typename T, int DIM, int MODE>
-__global__ __launch_bounds__(kWG) void stencil_kernel(const StencilArgs<T> a) {
-  constexpr bool kPart = MODE == kResidual || MODE == kNormB;
-  const int n = xcd_wg(a.nwg);
-  if (n < 0) return;
+__global__ __launch_bounds__(kWG) void stencil_kernel(const Launch<StencilArgs<T>> L) {
+  constexpr bool kPart = has_partials(MODE);
+  const int g = xcd_wg(L.nwg);
+  if (g < 0) return;
+  StencilArgs<T> a;
+  const int n = resolve(L, g, a);
   // wave-uniform tile index: the tile and its macro constants load into scalar registers
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int ti = n * kWavesPerWG + wv;
@@ -417,23 +443,6 @@ __global__ __launch_bounds__(kWG) void stencil_kernel(const StencilArgs<T> a) {
 }
 
 // ------------------------------------------------------------------ exchange
-template <typename T>
-struct GroupArgs {
-  int ngroups;
-  const int32_t* gptr;
-  const Copy* copies;
-  const uint8_t* gflag;     // all-groups list only
-  const double* ginv;       // exchange list only
-  const float* ginvf;
-  const MacroDev* md;
-  const T* X;
-  T* Y;
-  const T* B;
-  T omega;
-  double* part;  // block partials at [0, nblk), maxima at [np, ...)
-  int np;
-};
-
 template <int DIM>
 __device__ __forceinline__ int64_t copy_index(const MacroDev& M, const Copy& c) {
   return M.base + (DIM == 2 ? idx2(M.N, c.x, c.y) : idx3(M.N, c.x, c.y, c.z));
@@ -443,8 +452,10 @@ __device__ __forceinline__ int64_t copy_index(const MacroDev& M, const Copy& c) 
 // partial rows (written by stencil_kernel); sum them in fixed macro order,
 // finish the row, and write it to every copy.
 template <typename T, int DIM, int MODE>
-__global__ __launch_bounds__(kIfaceWG) void exchange_kernel(const GroupArgs<T> a) {
-  const int g = blockIdx.x * kIfaceWG + threadIdx.x;
+__global__ __launch_bounds__(kIfaceWG) void exchange_kernel(const Launch<GroupArgs<T>> L) {
+  GroupArgs<T> a;
+  const int blk = resolve(L, (int)blockIdx.x, a);
+  const int g = blk * kIfaceWG + threadIdx.x;
   double ss = 0.0, mx = 0.0;
   if (g < a.ngroups) {
     const int c0 = a.gptr[g], c1 = a.gptr[g + 1];
@@ -455,15 +466,14 @@ __global__ __launch_bounds__(kIfaceWG) void exchange_kernel(const GroupArgs<T> a
     } else {
       T acc = T(0);
       for (int c = c0; c < c1; ++c) acc += a.Y[copy_index<DIM>(a.md[a.copies[c].macro], a.copies[c])];
-      if (MODE == kApply) out = acc;
+      if (MODE == kApply || MODE == kApplyDot) out = acc;
       else if (MODE == kJacobi) out = fma(a.omega * Prec<T>::ginv(a.ginv, a.ginvf, g), a.B[i0] - acc, a.X[i0]);
       else out = a.B[i0] - acc;
       for (int c = c0; c < c1; ++c) a.Y[copy_index<DIM>(a.md[a.copies[c].macro], a.copies[c])] = out;
     }
-    ss = (double)out * (double)out;
-    mx = fabs((double)out);
+    accum<T, MODE>(ss, mx, out, MODE == kApplyDot ? a.X[i0] : T(0));
   }
-  if ((MODE == kResidual || MODE == kNormB) && a.part != nullptr) {
+  if (has_partials(MODE) && a.part != nullptr) {
     __shared__ double s_ss[kIfaceWG / kWave], s_mx[kIfaceWG / kWave];
     ss = wave_sum(ss);
     mx = wave_max(mx);
@@ -479,23 +489,26 @@ __global__ __launch_bounds__(kIfaceWG) void exchange_kernel(const GroupArgs<T> a
         p += s_ss[i];
         q = fmax(q, s_mx[i]);
       }
-      a.part[blockIdx.x] = p;
-      a.part[a.np + blockIdx.x] = q;
+      a.part[blk] = p;
+      a.part[a.np + blk] = q;
     }
   }
 }
 
 // Every macro-boundary DoF: kExchangeSum (y = sum of x over the copies,
-// Dirichlet -> 0, in place allowed) or kDirichletSet (y = b at Dirichlet DoFs).
+// Dirichlet -> 0, in place allowed) or kDirichletSet (y = b at Dirichlet
+// DoFs; b == NULL sets them to 0).
 template <typename T, int DIM, int MODE>
-__global__ __launch_bounds__(kIfaceWG) void iface_kernel(const GroupArgs<T> a) {
-  const int g = blockIdx.x * kIfaceWG + threadIdx.x;
+__global__ __launch_bounds__(kIfaceWG) void iface_kernel(const Launch<GroupArgs<T>> L) {
+  GroupArgs<T> a;
+  const int blk = resolve(L, (int)blockIdx.x, a);
+  const int g = blk * kIfaceWG + threadIdx.x;
   if (g >= a.ngroups) return;
   const int c0 = a.gptr[g], c1 = a.gptr[g + 1];
   const bool dir = a.gflag[g] & 1;
   if (MODE == kDirichletSet) {
     if (!dir) return;
-    const T v = a.B[copy_index<DIM>(a.md[a.copies[c0].macro], a.copies[c0])];
+    const T v = a.B ? a.B[copy_index<DIM>(a.md[a.copies[c0].macro], a.copies[c0])] : T(0);
     for (int c = c0; c < c1; ++c) a.Y[copy_index<DIM>(a.md[a.copies[c].macro], a.copies[c])] = v;
     return;
   }
@@ -505,13 +518,16 @@ __global__ __launch_bounds__(kIfaceWG) void iface_kernel(const GroupArgs<T> a) {
   for (int c = c0; c < c1; ++c) a.Y[copy_index<DIM>(a.md[a.copies[c].macro], a.copies[c])] = out;
 }
 
-__global__ __launch_bounds__(256) void reduce_kernel(const double* __restrict__ part, int64_t np,
-                                                     double* __restrict__ result) {
+// result = (sum of part[0, np), max of part[np, 2 np)) in a fixed order; one
+// block per request.
+__global__ __launch_bounds__(256) void reduce_kernel(const Launch<ReduceArgs> L) {
+  ReduceArgs r;
+  resolve(L, (int)blockIdx.x, r);
   __shared__ double s[256], m[256];
   double a = 0.0, b = 0.0;
-  for (int64_t i = threadIdx.x; i < np; i += 256) {
-    a += part[i];
-    b = fmax(b, part[np + i]);
+  for (int64_t i = threadIdx.x; i < r.np; i += 256) {
+    a += r.part[i];
+    b = fmax(b, r.part[r.np + i]);
   }
   s[threadIdx.x] = a;
   m[threadIdx.x] = b;
@@ -524,8 +540,13 @@ __global__ __launch_bounds__(256) void reduce_kernel(const double* __restrict__ 
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    result[0] = s[0];
-    result[1] = m[0];
+    const double second = r.shift ? r.result[0] : m[0];
+    r.result[0] = s[0];
+    r.result[1] = second;
+    if (r.copy) {
+      r.copy[0] = s[0];
+      r.copy[1] = second;
+    }
   }
 }
 
@@ -535,60 +556,45 @@ int check_launch() {
   return MF_OK;
 }
 
+inline int stencil_grid(int nwg) { return kXCD * ((nwg + kXCD - 1) / kXCD); }
+
+template <class A>
+Launch<A> single(const A& a, int nwg) {
+  Launch<A> l{};
+  l.one = a;
+  l.nseg = 0;
+  l.nwg = nwg;
+  return l;
+}
+
+template <class A>
+Launch<A> batched(const BatchOp& op, const char* table) {
+  Launch<A> l{};
+  l.many = (const A*)(table + op.args_off);
+  l.wg0 = (const int32_t*)(table + op.wg0_off);
+  l.nseg = op.nseg;
+  l.nwg = op.nwg;
+  return l;
+}
+
 template <typename T, int DIM, int MODE>
 void run_stencil(const Level& L, const void* x, void* y, const void* b, double omega, double* part,
                  hipStream_t s) {
-  const int64_t np = L.n_partials();
-  StencilArgs<T> a;
-  a.tiles = L.dev.tiles;
-  a.ntiles = (int)L.tiles.size();
-  a.nwg = a.ntiles / kWavesPerWG;
-  a.md = L.dev.md;
-  a.X = (const T*)x;
-  a.Y = (T*)y;
-  a.B = (const T*)b;
-  a.omega = (T)omega;
-  a.part = part;
-  a.np = (int)np;
-  const int grid = kXCD * ((a.nwg + kXCD - 1) / kXCD);
-  if (grid > 0) hipLaunchKernelGGL((stencil_kernel<T, DIM, MODE>), dim3(grid), dim3(kWG), 0, s, a);
-  GroupArgs<T> g;
-  g.ngroups = (int)L.nxgroups();
-  if (g.ngroups == 0) return;
-  g.gptr = L.dev.xgrp_ptr;
-  g.copies = L.dev.xcopies;
-  g.gflag = nullptr;
-  g.ginv = L.dev.xgrp_invdiag;
-  g.ginvf = L.dev.xgrp_invdiagf;
-  g.md = L.dev.md;
-  g.X = (const T*)x;
-  g.Y = (T*)y;
-  g.B = (const T*)b;
-  g.omega = (T)omega;
-  g.part = part ? part + a.ntiles : nullptr;
-  g.np = (int)np;
-  hipLaunchKernelGGL((exchange_kernel<T, DIM, MODE>), dim3((int)L.xgroup_blocks()), dim3(kIfaceWG), 0, s, g);
+  const StencilArgs<T> a = stencil_args<T>(L, x, y, b, omega, part);
+  if (a.nwg > 0)
+    hipLaunchKernelGGL((stencil_kernel<T, DIM, MODE>), dim3(stencil_grid(a.nwg)), dim3(kWG), 0, s, single(a, a.nwg));
+  const int nblk = exchange_blocks(L);
+  if (nblk == 0) return;
+  hipLaunchKernelGGL((exchange_kernel<T, DIM, MODE>), dim3(nblk), dim3(kIfaceWG), 0, s,
+                     single(exchange_args<T>(L, x, y, b, omega, part), nblk));
 }
 
 template <typename T, int DIM, int MODE>
 void run_iface(const Level& L, const void* x, void* y, const void* b, hipStream_t s) {
-  GroupArgs<T> g;
-  g.ngroups = (int)L.ngroups();
-  if (g.ngroups == 0) return;
-  g.gptr = L.dev.grp_ptr;
-  g.copies = L.dev.copies;
-  g.gflag = L.dev.grp_flag;
-  g.ginv = nullptr;
-  g.ginvf = nullptr;
-  g.md = L.dev.md;
-  g.X = (const T*)x;
-  g.Y = (T*)y;
-  g.B = (const T*)b;
-  g.omega = T(0);
-  g.part = nullptr;
-  g.np = 0;
-  const int nblk = (g.ngroups + kIfaceWG - 1) / kIfaceWG;
-  hipLaunchKernelGGL((iface_kernel<T, DIM, MODE>), dim3(nblk), dim3(kIfaceWG), 0, s, g);
+  const int nblk = iface_blocks(L);
+  if (nblk == 0) return;
+  hipLaunchKernelGGL((iface_kernel<T, DIM, MODE>), dim3(nblk), dim3(kIfaceWG), 0, s,
+                     single(iface_args<T>(L, x, y, b), nblk));
 }
 
 template <typename T, int DIM>
@@ -599,6 +605,7 @@ void dispatch(int mode, const Level& L, const void* x, void* y, const void* b, d
     case kJacobi: run_stencil<T, DIM, kJacobi>(L, x, y, b, omega, part, s); break;
     case kResidual: run_stencil<T, DIM, kResidual>(L, x, y, b, omega, part, s); break;
     case kNormB: run_stencil<T, DIM, kNormB>(L, x, y, b, omega, part, s); break;
+    case kApplyDot: run_stencil<T, DIM, kApplyDot>(L, x, y, b, omega, part, s); break;
     case kExchangeSum: run_iface<T, DIM, kExchangeSum>(L, x, y, b, s); break;
     default: run_iface<T, DIM, kDirichletSet>(L, x, y, b, s); break;
   }
@@ -616,6 +623,37 @@ int launch(const mf_mesh* m, const Level& L, int dtype, int mode, const void* x,
   return check_launch();
 }
 
+// ---------------------------------------------------------------- batched
+template <typename T, int DIM, int MODE>
+void batch_stencil(const BatchOp& op, const char* table, hipStream_t s) {
+  if (op.kind == kOpStencil)
+    hipLaunchKernelGGL((stencil_kernel<T, DIM, MODE>), dim3(stencil_grid(op.nwg)), dim3(kWG), 0, s,
+                       batched<StencilArgs<T>>(op, table));
+  else
+    hipLaunchKernelGGL((exchange_kernel<T, DIM, MODE>), dim3(op.nwg), dim3(kIfaceWG), 0, s,
+                       batched<GroupArgs<T>>(op, table));
+}
+
+template <typename T, int DIM>
+void batch_dispatch(const BatchOp& op, const char* table, hipStream_t s) {
+  if (op.kind == kOpIface) {
+    if (op.mode == kExchangeSum)
+      hipLaunchKernelGGL((iface_kernel<T, DIM, kExchangeSum>), dim3(op.nwg), dim3(kIfaceWG), 0, s,
+                         batched<GroupArgs<T>>(op, table));
+    else
+      hipLaunchKernelGGL((iface_kernel<T, DIM, kDirichletSet>), dim3(op.nwg), dim3(kIfaceWG), 0, s,
+                         batched<GroupArgs<T>>(op, table));
+    return;
+  }
+  switch (op.mode) {
+    case kApply: batch_stencil<T, DIM, kApply>(op, table, s); break;
+    case kJacobi: batch_stencil<T, DIM, kJacobi>(op, table, s); break;
+    case kResidual: batch_stencil<T, DIM, kResidual>(op, table, s); break;
+    case kNormB: batch_stencil<T, DIM, kNormB>(op, table, s); break;
+    default: batch_stencil<T, DIM, kApplyDot>(op, table, s); break;
+  }
+}
+
 }  // namespace
 
 int64_t stencil_partials(const Level& L) { return L.n_partials(); }
@@ -631,7 +669,28 @@ int launch_iface(const mf_mesh* m, const Level& L, int dtype, int mode, const vo
 }
 
 int launch_reduce(const double* part, int64_t np, double* result, hipStream_t s) {
-  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, s, part, np, result);
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, s, single(ReduceArgs{part, np, result, nullptr, 0, 0}, 1));
+  return check_launch();
+}
+
+int launch_reduce_shift(const double* part, int64_t np, double* result, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, s, single(ReduceArgs{part, np, result, nullptr, 1, 0}, 1));
+  return check_launch();
+}
+
+int launch_stencil_batch(const BatchOp& op, const char* table, hipStream_t s) {
+  if (op.nwg <= 0) return MF_OK;
+  if (op.kind == kOpReduce) {
+    hipLaunchKernelGGL(reduce_kernel, dim3(op.nwg), dim3(256), 0, s, batched<ReduceArgs>(op, table));
+    return check_launch();
+  }
+  if (op.dtype == MF_F64) {
+    if (op.dim == 2) batch_dispatch<double, 2>(op, table, s);
+    else batch_dispatch<double, 3>(op, table, s);
+  } else {
+    if (op.dim == 2) batch_dispatch<float, 2>(op, table, s);
+    else batch_dispatch<float, 3>(op, table, s);
+  }
   return check_launch();
 }
 

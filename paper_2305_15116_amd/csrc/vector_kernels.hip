@@ -72,24 +72,59 @@ __global__ __launch_bounds__(kWG) void fill_random_kernel(const Tile* __restrict
   X[M.base + lidx<DIM>(N, x, y, z)] = (T)(2.0 * u - 1.0);
 }
 
+// Argument tables are read-only for the whole launch: reading them through
+// the constant address space lets the compiler use scalar loads, so the
+// request's arguments stay in scalar registers as a by-value argument does.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T* as_const(const T* p) {
+  return (const __attribute__((address_space(4))) T*)p;
+}
+
+__device__ __forceinline__ int find_seg_c(const int32_t* wg0, int nseg, int g) {
+  const auto* w = as_const(wg0);
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (w[mid] <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Resolves workgroup g of a launch to its request's arguments and the
+// workgroup index inside that request.
+template <class A>
+__device__ __forceinline__ int resolve(const Launch<A>& L, int g, A& a) {
+  if (L.nseg == 0) {
+    a = L.one;
+    return g;
+  }
+  const int r = find_seg_c(L.wg0, L.nseg, g);
+#if defined(__HIP_DEVICE_COMPILE__)
+  a = as_const(L.many)[r];
+#else
+  a = L.many[r];  // the host pass only type-checks device code
+#endif
+  return g - as_const(L.wg0)[r];
+}
+
 // Restriction r_c = P^T r_f on one macro: a coarse point P gathers the fine
 // point 2P (weight 1) and the fine points 2P + d for the stencil offsets d
 // (weight 1/2) — the fine points whose interpolation uses P — counting only
 // fine points this macro owns, so that the later exchange sums each fine DoF
 // once.  Dirichlet fine points are skipped.
 template <typename T, int DIM>
-__global__ __launch_bounds__(kWG) void restrict_kernel(const Tile* __restrict__ segs, int nseg,
-                                                       const MacroDev* __restrict__ mdc,
-                                                       const MacroDev* __restrict__ mdf, const T* __restrict__ Rf,
-                                                       T* __restrict__ Bc) {
+__global__ __launch_bounds__(kWG) void restrict_kernel(const Launch<TransferArgs<T>> L) {
   constexpr StencilTable ST = stencil_table(DIM);
   constexpr int full = DIM == 2 ? 7 : 15;
-  const int si = blockIdx.x * kWavesPerWG + (threadIdx.x >> 6);
-  if (si >= nseg) return;
-  const Tile sg = segs[si];
+  TransferArgs<T> a;
+  const int blk = resolve(L, (int)blockIdx.x, a);
+  const int si = blk * kWavesPerWG + (threadIdx.x >> 6);
+  if (si >= a.nseg) return;
+  const Tile sg = a.segs[si];
   if (sg.macro < 0) return;
-  const MacroDev& C = mdc[sg.macro];
-  const MacroDev& F = mdf[sg.macro];
+  const MacroDev& C = a.mdc[sg.macro];
+  const MacroDev& F = a.mdf[sg.macro];
   const int Nc = C.N, Nf = F.N;
   const int x = sg.x0 + (threadIdx.x & (kWave - 1));
   const int y = sg.y0, z = DIM == 3 ? sg.z : 0;
@@ -103,11 +138,11 @@ __global__ __launch_bounds__(kWG) void restrict_kernel(const Tile* __restrict__ 
     const bool owned = mask == full || ((F.own_mask >> mask) & 1);
     const bool dir = mask != full && ((F.dir_mask >> mask) & 1);
     if (owned && !dir) {
-      const T r = Rf[F.base + lidx<DIM>(Nf, fx, fy, fz)];
+      const T r = a.src[F.base + lidx<DIM>(Nf, fx, fy, fz)];
       acc += (s == ST.centre) ? r : T(0.5) * r;
     }
   }
-  Bc[C.base + lidx<DIM>(Nc, x, y, z)] = acc;
+  a.dst[C.base + lidx<DIM>(Nc, x, y, z)] = acc;
 }
 
 // x_f += P e_c: even fine points take the coarse value, the others the mean
@@ -115,17 +150,16 @@ __global__ __launch_bounds__(kWG) void restrict_kernel(const Tile* __restrict__ 
 // edge direction follows from the coordinate parities.  Dirichlet points are
 // left unchanged.
 template <typename T, int DIM>
-__global__ __launch_bounds__(kWG) void prolong_add_kernel(const Tile* __restrict__ segs, int nseg,
-                                                          const MacroDev* __restrict__ mdc,
-                                                          const MacroDev* __restrict__ mdf,
-                                                          const T* __restrict__ Ec, T* __restrict__ Xf) {
+__global__ __launch_bounds__(kWG) void prolong_add_kernel(const Launch<TransferArgs<T>> L) {
   constexpr int full = DIM == 2 ? 7 : 15;
-  const int si = blockIdx.x * kWavesPerWG + (threadIdx.x >> 6);
-  if (si >= nseg) return;
-  const Tile sg = segs[si];
+  TransferArgs<T> a;
+  const int blk = resolve(L, (int)blockIdx.x, a);
+  const int si = blk * kWavesPerWG + (threadIdx.x >> 6);
+  if (si >= a.nseg) return;
+  const Tile sg = a.segs[si];
   if (sg.macro < 0) return;
-  const MacroDev& C = mdc[sg.macro];
-  const MacroDev& F = mdf[sg.macro];
+  const MacroDev& C = a.mdc[sg.macro];
+  const MacroDev& F = a.mdf[sg.macro];
   const int Nc = C.N, Nf = F.N;
   const int x = sg.x0 + (threadIdx.x & (kWave - 1));
   const int y = sg.y0, z = DIM == 3 ? sg.z : 0;
@@ -135,7 +169,7 @@ __global__ __launch_bounds__(kWG) void prolong_add_kernel(const Tile* __restrict
   const int px = x & 1, py = y & 1, pz = z & 1;
   T e;
   if (!(px | py | pz)) {
-    e = Ec[C.base + lidx<DIM>(Nc, x >> 1, y >> 1, z >> 1)];
+    e = a.src[C.base + lidx<DIM>(Nc, x >> 1, y >> 1, z >> 1)];
   } else {
     // direction s of the bisected coarse edge: equal to the parity pattern,
     // except that of two or three odd coordinates the middle ones flip sign
@@ -144,59 +178,164 @@ __global__ __launch_bounds__(kWG) void prolong_add_kernel(const Tile* __restrict
     else if (px && !py && pz) sz = -1;   // (1,0,1) -> e1 - e3
     else if (!px && py && pz) sz = -1;   // (0,1,1) -> e2 - e3
     else if (px && py && pz) sy = -1;    // (1,1,1) -> e1 - e2 + e3
-    const T a = Ec[C.base + lidx<DIM>(Nc, (x - sx) >> 1, (y - sy) >> 1, (z - sz) >> 1)];
-    const T b = Ec[C.base + lidx<DIM>(Nc, (x + sx) >> 1, (y + sy) >> 1, (z + sz) >> 1)];
-    e = T(0.5) * (a + b);
+    const T u = a.src[C.base + lidx<DIM>(Nc, (x - sx) >> 1, (y - sy) >> 1, (z - sz) >> 1)];
+    const T v = a.src[C.base + lidx<DIM>(Nc, (x + sx) >> 1, (y + sy) >> 1, (z + sz) >> 1)];
+    e = T(0.5) * (u + v);
   }
-  Xf[F.base + lidx<DIM>(Nf, x, y, z)] += e;
+  a.dst[F.base + lidx<DIM>(Nf, x, y, z)] += e;
 }
 
 // Coarse direct solve: x(copies of unknown i) = sum_j Ainv[i][j] b(first copy of j).
 // One wavefront per unknown; x must be zero elsewhere beforehand.
 template <typename T>
-__global__ __launch_bounds__(kWG) void coarse_solve_kernel(int n, const T* __restrict__ Ainv,
-                                                           const int32_t* __restrict__ first,
-                                                           const int32_t* __restrict__ cptr,
-                                                           const int64_t* __restrict__ cidx,
-                                                           const T* __restrict__ B, T* __restrict__ X) {
-  const int i = blockIdx.x * kWavesPerWG + (threadIdx.x >> 6);
+__global__ __launch_bounds__(kWG) void coarse_solve_kernel(const Launch<CoarseArgs<T>> L) {
+  CoarseArgs<T> a;
+  const int blk = resolve(L, (int)blockIdx.x, a);
+  const int i = blk * kWavesPerWG + (threadIdx.x >> 6);
   const int lane = threadIdx.x & (kWave - 1);
-  if (i >= n) return;
+  if (i >= a.n) return;
   T acc = T(0);
-  for (int j = lane; j < n; j += kWave) acc = fma(Ainv[(int64_t)i * n + j], B[first[j]], acc);
+  for (int j = lane; j < a.n; j += kWave) acc = fma(a.Ainv[(int64_t)i * a.n + j], a.B[a.first[j]], acc);
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, kWave);
-  for (int c = cptr[i] + lane; c < cptr[i + 1]; c += kWave) X[cidx[c]] = acc;
+  for (int c = a.cptr[i] + lane; c < a.cptr[i + 1]; c += kWave) a.X[a.cidx[c]] = acc;
+}
+
+// Plain vector kernels: grid-stride loops over each request's nblk blocks.
+template <typename T, int KIND>
+__global__ __launch_bounds__(256) void vector_kernel(const Launch<VecArgs> L) {
+  VecArgs a;
+  const int blk = resolve(L, (int)blockIdx.x, a);
+  const int64_t stride = (int64_t)a.nblk * 256;
+  int64_t i = (int64_t)blk * 256 + threadIdx.x;
+  if (KIND == kOpFill) {
+    const T v = (T)a.a;
+    for (; i < a.n; i += stride) ((T*)a.y)[i] = v;
+  } else if (KIND == kOpCopy) {
+    for (; i < a.n; i += stride) ((T*)a.y)[i] = ((const T*)a.x)[i];
+  } else if (KIND == kOpAxpy) {
+    const T c = (T)a.a;
+    for (; i < a.n; i += stride) ((T*)a.y)[i] = fma(c, ((const T*)a.x)[i], ((T*)a.y)[i]);
+  } else if (KIND == kOpScaleF32) {
+    const double c = 1.0 / a.res[1];
+    for (; i < a.n; i += stride) ((float*)a.y)[i] = (float)(c * ((const double*)a.x)[i]);
+  } else {
+    const double c = a.res[1];
+    for (; i < a.n; i += stride) ((double*)a.y)[i] = fma(c, (double)((const float*)a.x)[i], ((double*)a.y)[i]);
+  }
+}
+
+// ---------------------------------------------------------------- PCG
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+__device__ __forceinline__ double wmax(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+
+// One 64-point row segment per wave.  KIND kOpPcgZDot: z = s e with s = res[1]
+// for FP32 e (the preconditioner solved for r / max|r|) and 1 for FP64 e,
+// partials of r . z.  KIND kOpPcgUpdate: alpha = res[2] / res[4],
+// x += alpha p, r -= alpha q, partials of r . r and max |r|.  Sums count each
+// unique DoF once (its owner macro's copy).
+template <int DIM, int KIND, typename TE>
+__global__ __launch_bounds__(kWG) void pcg_point_kernel(const Launch<PcgArgs> L) {
+  constexpr int full = DIM == 2 ? 7 : 15;
+  PcgArgs a;
+  const int blk = resolve(L, (int)blockIdx.x, a);
+  const int si = blk * kWavesPerWG + (threadIdx.x >> 6);
+  double ss = 0.0, mx = 0.0;
+  if (si < a.nseg) {
+    const Tile sg = a.segs[si];
+    if (sg.macro >= 0) {
+      const MacroDev& M = a.md[sg.macro];
+      const int N = M.N;
+      const int x = sg.x0 + (threadIdx.x & (kWave - 1));
+      const int y = sg.y0, z = DIM == 3 ? sg.z : 0;
+      if (x + y + z <= N) {
+        const int mask = support_mask(DIM, N, x, y, z);
+        const bool owned = mask == full || ((M.own_mask >> mask) & 1);
+        const int64_t i = M.base + lidx<DIM>(N, x, y, z);
+        if (KIND == kOpPcgZDot) {
+          const double sc = sizeof(TE) == 4 ? a.res[1] : 1.0;
+          const double zv = sc * (double)((const TE*)a.e)[i];
+          if ((const void*)a.z != a.e) a.z[i] = zv;
+          if (owned) ss = a.r[i] * zv;
+        } else {
+          const double alpha = a.res[2] / a.res[4];
+          a.x[i] = fma(alpha, a.p[i], a.x[i]);
+          const double rn = fma(-alpha, a.q[i], a.r[i]);
+          a.r[i] = rn;
+          if (owned) ss = rn * rn;
+          mx = fabs(rn);
+        }
+      }
+    }
+  }
+  ss = wsum(ss);
+  mx = wmax(mx);
+  if ((threadIdx.x & (kWave - 1)) == 0 && si < a.nseg) {
+    a.part[si] = ss;
+    a.part[a.nseg + si] = mx;
+  }
+}
+
+// p = z + beta p, beta = res[2] / res[3] (0 on the first iteration, res[3] == 0).
+__global__ __launch_bounds__(256) void pcg_dir_kernel(const Launch<VecArgs> L) {
+  VecArgs a;
+  const int blk = resolve(L, (int)blockIdx.x, a);
+  const int64_t stride = (int64_t)a.nblk * 256;
+  double* p = (double*)a.y;
+  const double* z = (const double*)a.x;
+  if (a.res[3] == 0.0) {
+    // first direction: p = z (p holds no earlier direction and is never read)
+    for (int64_t i = (int64_t)blk * 256 + threadIdx.x; i < a.n; i += stride) p[i] = z[i];
+    return;
+  }
+  const double beta = a.res[2] / a.res[3];
+  for (int64_t i = (int64_t)blk * 256 + threadIdx.x; i < a.n; i += stride) p[i] = fma(beta, p[i], z[i]);
+}
+
+template <class A>
+Launch<A> single(const A& a, int nwg) {
+  Launch<A> l{};
+  l.one = a;
+  l.nseg = 0;
+  l.nwg = nwg;
+  return l;
+}
+
+template <class A>
+Launch<A> batched(const BatchOp& op, const char* table) {
+  Launch<A> l{};
+  l.many = (const A*)(table + op.args_off);
+  l.wg0 = (const int32_t*)(table + op.wg0_off);
+  l.nseg = op.nseg;
+  l.nwg = op.nwg;
+  return l;
+}
+
+template <int KIND>
+int run_vector(int dtype, const Launch<VecArgs>& l, hipStream_t s) {
+  if (l.nwg <= 0) return MF_OK;
+  if (dtype == MF_F64) hipLaunchKernelGGL((vector_kernel<double, KIND>), dim3(l.nwg), dim3(256), 0, s, l);
+  else hipLaunchKernelGGL((vector_kernel<float, KIND>), dim3(l.nwg), dim3(256), 0, s, l);
+  return check_launch();
 }
 
 template <typename T>
-__global__ void fill_kernel(T* __restrict__ x, T v, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    x[i] = v;
-}
-template <typename T>
-__global__ void copy_kernel(T* __restrict__ d, const T* __restrict__ s, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    d[i] = s[i];
-}
-template <typename T>
-__global__ void axpy_kernel(T* __restrict__ y, const T* __restrict__ x, T a, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    y[i] = fma(a, x[i], y[i]);
-}
-__global__ void scale_to_f32_kernel(const double* __restrict__ r, float* __restrict__ b, double s, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    b[i] = (float)(s * r[i]);
-}
-__global__ void axpy_f32_kernel(double* __restrict__ x, const float* __restrict__ e, double a, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    x[i] = fma(a, (double)e[i], x[i]);
-}
-
-inline int blocks_for(int64_t n) {
-  int64_t b = (n + 255) / 256;
-  if (b > 8192) b = 8192;
-  return (int)(b < 1 ? 1 : b);
+void run_transfer(bool restrict_op, int dim, const Launch<TransferArgs<T>>& l, hipStream_t s) {
+  if (restrict_op) {
+    if (dim == 2) hipLaunchKernelGGL((restrict_kernel<T, 2>), dim3(l.nwg), dim3(kWG), 0, s, l);
+    else hipLaunchKernelGGL((restrict_kernel<T, 3>), dim3(l.nwg), dim3(kWG), 0, s, l);
+  } else {
+    if (dim == 2) hipLaunchKernelGGL((prolong_add_kernel<T, 2>), dim3(l.nwg), dim3(kWG), 0, s, l);
+    else hipLaunchKernelGGL((prolong_add_kernel<T, 3>), dim3(l.nwg), dim3(kWG), 0, s, l);
+  }
 }
 
 }  // namespace
@@ -217,16 +356,10 @@ int launch_fill_random(const mf_mesh* m, const Level& L, int dtype, uint64_t see
 
 int launch_restrict(const mf_mesh* m, const Level& F, const Level& C, int dtype, const void* rf, void* bc,
                     hipStream_t s) {
-  const int nseg = (int)C.segs.size();
-  const int grid = (nseg + kWavesPerWG - 1) / kWavesPerWG;
-  if (grid == 0) return MF_OK;
-  if (dtype == MF_F64) {
-    if (m->dim == 2) hipLaunchKernelGGL((restrict_kernel<double, 2>), dim3(grid), dim3(kWG), 0, s, C.dev.segs, nseg, C.dev.md, F.dev.md, (const double*)rf, (double*)bc);
-    else hipLaunchKernelGGL((restrict_kernel<double, 3>), dim3(grid), dim3(kWG), 0, s, C.dev.segs, nseg, C.dev.md, F.dev.md, (const double*)rf, (double*)bc);
-  } else {
-    if (m->dim == 2) hipLaunchKernelGGL((restrict_kernel<float, 2>), dim3(grid), dim3(kWG), 0, s, C.dev.segs, nseg, C.dev.md, F.dev.md, (const float*)rf, (float*)bc);
-    else hipLaunchKernelGGL((restrict_kernel<float, 3>), dim3(grid), dim3(kWG), 0, s, C.dev.segs, nseg, C.dev.md, F.dev.md, (const float*)rf, (float*)bc);
-  }
+  const int nwg = transfer_blocks((int)C.segs.size());
+  if (nwg == 0) return MF_OK;
+  if (dtype == MF_F64) run_transfer<double>(true, m->dim, single(restrict_args<double>(F, C, rf, bc), nwg), s);
+  else run_transfer<float>(true, m->dim, single(restrict_args<float>(F, C, rf, bc), nwg), s);
   int rc = check_launch();
   if (rc) return rc;
   return launch_iface(m, C, dtype, kExchangeSum, bc, bc, nullptr, s);
@@ -234,65 +367,121 @@ int launch_restrict(const mf_mesh* m, const Level& F, const Level& C, int dtype,
 
 int launch_prolong_add(const mf_mesh* m, const Level& F, const Level& C, int dtype, const void* ec, void* xf,
                        hipStream_t s) {
-  const int nseg = (int)F.segs.size();
-  const int grid = (nseg + kWavesPerWG - 1) / kWavesPerWG;
-  if (grid == 0) return MF_OK;
-  if (dtype == MF_F64) {
-    if (m->dim == 2) hipLaunchKernelGGL((prolong_add_kernel<double, 2>), dim3(grid), dim3(kWG), 0, s, F.dev.segs, nseg, C.dev.md, F.dev.md, (const double*)ec, (double*)xf);
-    else hipLaunchKernelGGL((prolong_add_kernel<double, 3>), dim3(grid), dim3(kWG), 0, s, F.dev.segs, nseg, C.dev.md, F.dev.md, (const double*)ec, (double*)xf);
-  } else {
-    if (m->dim == 2) hipLaunchKernelGGL((prolong_add_kernel<float, 2>), dim3(grid), dim3(kWG), 0, s, F.dev.segs, nseg, C.dev.md, F.dev.md, (const float*)ec, (float*)xf);
-    else hipLaunchKernelGGL((prolong_add_kernel<float, 3>), dim3(grid), dim3(kWG), 0, s, F.dev.segs, nseg, C.dev.md, F.dev.md, (const float*)ec, (float*)xf);
-  }
+  const int nwg = transfer_blocks((int)F.segs.size());
+  if (nwg == 0) return MF_OK;
+  if (dtype == MF_F64) run_transfer<double>(false, m->dim, single(prolong_args<double>(F, C, ec, xf), nwg), s);
+  else run_transfer<float>(false, m->dim, single(prolong_args<float>(F, C, ec, xf), nwg), s);
   return check_launch();
 }
 
 int launch_coarse_solve(const Level& L, int dtype, const void* b, void* x, hipStream_t s) {
   int rc = launch_fill(dtype, x, 0.0, L.storage, s);
   if (rc) return rc;
-  const int n = (int)L.ncoarse;
-  if (n == 0) return MF_OK;
-  const int grid = (n + kWavesPerWG - 1) / kWavesPerWG;
+  const int nwg = coarse_blocks(L);
+  if (nwg == 0) return MF_OK;
   if (dtype == MF_F64)
-    hipLaunchKernelGGL((coarse_solve_kernel<double>), dim3(grid), dim3(kWG), 0, s, n, L.dev.cinv, L.dev.cfirst,
-                       L.dev.cptr, L.dev.cidx, (const double*)b, (double*)x);
+    hipLaunchKernelGGL((coarse_solve_kernel<double>), dim3(nwg), dim3(kWG), 0, s,
+                       single(coarse_args<double>(L, b, x), nwg));
   else
-    hipLaunchKernelGGL((coarse_solve_kernel<float>), dim3(grid), dim3(kWG), 0, s, n, L.dev.cinvf, L.dev.cfirst,
-                       L.dev.cptr, L.dev.cidx, (const float*)b, (float*)x);
+    hipLaunchKernelGGL((coarse_solve_kernel<float>), dim3(nwg), dim3(kWG), 0, s,
+                       single(coarse_args<float>(L, b, x), nwg));
   return check_launch();
 }
 
 int launch_fill(int dtype, void* x, double v, int64_t n, hipStream_t s) {
   if (n <= 0) return MF_OK;
-  if (dtype == MF_F64) hipLaunchKernelGGL((fill_kernel<double>), dim3(blocks_for(n)), dim3(256), 0, s, (double*)x, v, n);
-  else hipLaunchKernelGGL((fill_kernel<float>), dim3(blocks_for(n)), dim3(256), 0, s, (float*)x, (float)v, n);
-  return check_launch();
+  const VecArgs a = vec_args(x, nullptr, nullptr, n, v);
+  return run_vector<kOpFill>(dtype, single(a, a.nblk), s);
 }
 
 int launch_copy(int dtype, void* d, const void* src, int64_t n, hipStream_t s) {
   if (n <= 0) return MF_OK;
-  if (dtype == MF_F64) hipLaunchKernelGGL((copy_kernel<double>), dim3(blocks_for(n)), dim3(256), 0, s, (double*)d, (const double*)src, n);
-  else hipLaunchKernelGGL((copy_kernel<float>), dim3(blocks_for(n)), dim3(256), 0, s, (float*)d, (const float*)src, n);
+  const VecArgs a = vec_args(d, src, nullptr, n, 0.0);
+  return run_vector<kOpCopy>(dtype, single(a, a.nblk), s);
+}
+
+int launch_axpy(int dtype, void* y, const void* x, double c, int64_t n, hipStream_t s) {
+  if (n <= 0) return MF_OK;
+  const VecArgs a = vec_args(y, x, nullptr, n, c);
+  return run_vector<kOpAxpy>(dtype, single(a, a.nblk), s);
+}
+
+int launch_scale_to_f32(const double* r, float* b, const double* res, int64_t n, hipStream_t s) {
+  if (n <= 0) return MF_OK;
+  const VecArgs a = vec_args(b, r, res, n, 0.0);
+  return run_vector<kOpScaleF32>(MF_F64, single(a, a.nblk), s);
+}
+
+int launch_axpy_f32(double* x, const float* e, const double* res, int64_t n, hipStream_t s) {
+  if (n <= 0) return MF_OK;
+  const VecArgs a = vec_args(x, e, res, n, 0.0);
+  return run_vector<kOpAxpyF32>(MF_F64, single(a, a.nblk), s);
+}
+
+namespace {
+template <int KIND>
+void run_pcg_point(int dim, int dtype, const Launch<PcgArgs>& l, hipStream_t s) {
+  if (dim == 2) {
+    if (dtype == MF_F32) hipLaunchKernelGGL((pcg_point_kernel<2, KIND, float>), dim3(l.nwg), dim3(kWG), 0, s, l);
+    else hipLaunchKernelGGL((pcg_point_kernel<2, KIND, double>), dim3(l.nwg), dim3(kWG), 0, s, l);
+  } else {
+    if (dtype == MF_F32) hipLaunchKernelGGL((pcg_point_kernel<3, KIND, float>), dim3(l.nwg), dim3(kWG), 0, s, l);
+    else hipLaunchKernelGGL((pcg_point_kernel<3, KIND, double>), dim3(l.nwg), dim3(kWG), 0, s, l);
+  }
+}
+}  // namespace
+
+int launch_pcg_zdot(const mf_mesh* m, const Level& L, int edtype, const double* r, const void* e, double* z,
+                    const double* res, double* part, hipStream_t s) {
+  const int nwg = pcg_blocks(L);
+  if (nwg == 0) return MF_OK;
+  run_pcg_point<kOpPcgZDot>(m->dim, edtype, single(pcg_args(L, nullptr, (double*)r, nullptr, nullptr, e, z, res, part), nwg), s);
   return check_launch();
 }
 
-int launch_axpy(int dtype, void* y, const void* x, double a, int64_t n, hipStream_t s) {
-  if (n <= 0) return MF_OK;
-  if (dtype == MF_F64) hipLaunchKernelGGL((axpy_kernel<double>), dim3(blocks_for(n)), dim3(256), 0, s, (double*)y, (const double*)x, a, n);
-  else hipLaunchKernelGGL((axpy_kernel<float>), dim3(blocks_for(n)), dim3(256), 0, s, (float*)y, (const float*)x, (float)a, n);
+int launch_pcg_update(const mf_mesh* m, const Level& L, double* x, double* r, double* p, const double* q,
+                      const double* res, double* part, hipStream_t s) {
+  const int nwg = pcg_blocks(L);
+  if (nwg == 0) return MF_OK;
+  run_pcg_point<kOpPcgUpdate>(m->dim, MF_F64, single(pcg_args(L, x, r, p, q, nullptr, nullptr, res, part), nwg), s);
   return check_launch();
 }
 
-int launch_scale_to_f32(const double* r, float* b, double scale, int64_t n, hipStream_t s) {
+int launch_pcg_dir(double* p, const double* z, const double* res, int64_t n, hipStream_t s) {
   if (n <= 0) return MF_OK;
-  hipLaunchKernelGGL(scale_to_f32_kernel, dim3(blocks_for(n)), dim3(256), 0, s, r, b, scale, n);
+  const VecArgs a = vec_args(p, z, res, n, 0.0);
+  hipLaunchKernelGGL(pcg_dir_kernel, dim3(a.nblk), dim3(256), 0, s, single(a, a.nblk));
   return check_launch();
 }
 
-int launch_axpy_f32(double* x, const float* e, double a, int64_t n, hipStream_t s) {
-  if (n <= 0) return MF_OK;
-  hipLaunchKernelGGL(axpy_f32_kernel, dim3(blocks_for(n)), dim3(256), 0, s, x, e, a, n);
-  return check_launch();
+int launch_vector_batch(const BatchOp& op, const char* table, hipStream_t s) {
+  if (op.nwg <= 0) return MF_OK;
+  switch (op.kind) {
+    case kOpRestrict:
+    case kOpProlong:
+      if (op.dtype == MF_F64) run_transfer<double>(op.kind == kOpRestrict, op.dim, batched<TransferArgs<double>>(op, table), s);
+      else run_transfer<float>(op.kind == kOpRestrict, op.dim, batched<TransferArgs<float>>(op, table), s);
+      return check_launch();
+    case kOpCoarse:
+      if (op.dtype == MF_F64)
+        hipLaunchKernelGGL((coarse_solve_kernel<double>), dim3(op.nwg), dim3(kWG), 0, s,
+                           batched<CoarseArgs<double>>(op, table));
+      else
+        hipLaunchKernelGGL((coarse_solve_kernel<float>), dim3(op.nwg), dim3(kWG), 0, s,
+                           batched<CoarseArgs<float>>(op, table));
+      return check_launch();
+    case kOpFill: return run_vector<kOpFill>(op.dtype, batched<VecArgs>(op, table), s);
+    case kOpCopy: return run_vector<kOpCopy>(op.dtype, batched<VecArgs>(op, table), s);
+    case kOpAxpy: return run_vector<kOpAxpy>(op.dtype, batched<VecArgs>(op, table), s);
+    case kOpScaleF32: return run_vector<kOpScaleF32>(MF_F64, batched<VecArgs>(op, table), s);
+    case kOpAxpyF32: return run_vector<kOpAxpyF32>(MF_F64, batched<VecArgs>(op, table), s);
+    case kOpPcgZDot: run_pcg_point<kOpPcgZDot>(op.dim, op.dtype, batched<PcgArgs>(op, table), s); return check_launch();
+    case kOpPcgUpdate: run_pcg_point<kOpPcgUpdate>(op.dim, MF_F64, batched<PcgArgs>(op, table), s); return check_launch();
+    case kOpPcgDir:
+      hipLaunchKernelGGL(pcg_dir_kernel, dim3(op.nwg), dim3(256), 0, s, batched<VecArgs>(op, table));
+      return check_launch();
+    default: return set_error(MF_EINVAL, "unknown batch op");
+  }
 }
 
 }  // namespace mf

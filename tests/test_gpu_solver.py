@@ -39,7 +39,8 @@ def _manufactured(co, ce, L):
 
 
 @pytest.mark.parametrize("mesh,L,mode", [("cube", 4, 0), ("cube", 4, 1), ("cube", 5, 1), ("square", 6, 0),
-                                         ("square", 6, 1)])
+                                         ("square", 6, 1), ("cube", 4, 2), ("cube", 5, 3), ("square", 6, 2),
+                                         ("square", 6, 3)])
 def test_manufactured_solution(mesh, L, mode):
     co, ce = W.kuhn_cube() if mesh == "cube" else W.two_triangle_square()
     m, om, s2u, bu, us = _manufactured(co, ce, L)
@@ -54,7 +55,8 @@ def test_manufactured_solution(mesh, L, mode):
     xu = np.zeros(om.n)
     xu[s2u] = xs
     r = bu - om.spmv(xu)
-    assert np.linalg.norm(r) / np.linalg.norm(bu) <= 1.01e-10
+    # CG (modes 2, 3) stops on its recurred residual, which may trail the true one slightly
+    assert np.linalg.norm(r) / np.linalg.norm(bu) <= (1.01 if mode < 2 else 1.5) * 1e-10
     h = 1.0 / om.N
     uh = us * (np.pi ** 2 * h ** 2 / 4) / np.sin(np.pi * h / 2) ** 2
     uh[om.boundary()] = 0.0
@@ -63,7 +65,7 @@ def test_manufactured_solution(mesh, L, mode):
     assert np.abs(xu - uh).max() <= 2 * kappa * 1e-10 * np.abs(uh).max()
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
 def test_random_mesh_against_oracle_solve(mode):
     co, ce = W.kuhn_cube("random", 5)
     J, t = W.random_affine(3, 8)
@@ -87,7 +89,7 @@ def test_random_mesh_against_oracle_solve(mode):
     xu = np.zeros(om.n)
     xu[s2u] = x.cpu().numpy()
     r = bo - om.spmv(xu)
-    assert np.linalg.norm(r) / np.linalg.norm(bo) <= 1.01e-10
+    assert np.linalg.norm(r) / np.linalg.norm(bo) <= (1.01 if mode < 2 else 1.5) * 1e-10
     # Dirichlet values are exactly b's
     bnd = om.boundary()
     assert np.array_equal(xu[bnd], bo[bnd])
@@ -96,7 +98,8 @@ def test_random_mesh_against_oracle_solve(mode):
 
 
 def test_split_solve_equals_single_solve():
-    """Checkpoint/resume: k/2 + k/2 iterations from the saved x equal k iterations, bitwise."""
+    """Checkpoint/resume (iterative refinement): k/2 + k/2 iterations from the saved x equal k
+    iterations, bitwise."""
     co, ce = W.strip_3d(7)
     L = 4
     m = P.create_macro_mesh(co, ce, L)
@@ -150,3 +153,26 @@ def test_coarse_levels_solve_directly(L):
     ws = torch.empty(P.mesh_workspace_bytes(m, L, 0), dtype=torch.uint8, device="cuda")
     rc, it, rel, _ = P.vcycle_solve(m, L, b, x, ws, mode=0, rtol=1e-12)
     assert rc == P.MF_OK and it <= 2
+
+
+@pytest.mark.parametrize("mode", [2, 3])
+def test_pcg_needs_fewer_iterations_on_a_stretched_mesh(mode):
+    """Conjugate gradients around the V-cycle against refinement with the same
+    V-cycle on a stretched 2D strip: same tolerance, fewer iterations."""
+    co, ce = W.strip_2d(4)
+    J, t = W.random_affine(2, 2)
+    co = W.apply_affine(co, J, t)
+    L = 7
+    m = P.create_macro_mesh(co, ce, L)
+    s, _ = P.mesh_num_dofs(m, L)
+    b = torch.empty(s, dtype=torch.float64, device="cuda")
+    P.mesh_fill_random(m, L, 9, b)
+    P.mesh_set_dirichlet(m, L, None, b)
+    its = {}
+    for md in (mode - 2, mode):
+        x = torch.zeros_like(b)
+        ws = torch.empty(P.mesh_workspace_bytes(m, L, md), dtype=torch.uint8, device="cuda")
+        rc, it, rel, _ = P.vcycle_solve(m, L, b, x, ws, mode=md, rtol=1e-8, max_iter=300)
+        assert rc == P.MF_OK and rel <= 1e-8
+        its[md] = it
+    assert its[mode] < its[mode - 2]
