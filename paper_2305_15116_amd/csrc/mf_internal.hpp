@@ -26,8 +26,14 @@ constexpr int kTileW = 62;
 constexpr int kTileH2 = MF_TILE_H2;   // rows per 2D wave tile
 // 3D: a wave walks a "pencil" of kPenR rows upward through kPenZ slices,
 // keeping the rows of slices z-1, z, z+1 in registers.
-constexpr int kPenR = 4;
-constexpr int kPenZ = 8;
+#ifndef MF_PEN_R
+#define MF_PEN_R 4
+#endif
+#ifndef MF_PEN_Z
+#define MF_PEN_Z 8
+#endif
+constexpr int kPenR = MF_PEN_R;
+constexpr int kPenZ = MF_PEN_Z;
 constexpr int kWavesPerWG = 4;
 constexpr int kWG = kWave * kWavesPerWG;
 constexpr int kIfaceWG = 256;  // groups per interface workgroup

@@ -174,33 +174,110 @@ __device__ __forceinline__ void finish(const MacroDev& M, const WTab<T> W, int m
   }
 }
 
-// Row of one point from its neighbour values v: the interior stencil for
-// every lane, then — only when some lane of the wave lies on a face, edge or
-// vertex of the macro (a uniform branch) — the partial stencils of those lanes.
+// Interior finish of one row value (full stencil, interior point).
+template <typename T, int MODE>
+__device__ __forceinline__ void finish_interior(const MacroDev& M, T acc, T xc, T bv, T omega, T* yp, double& ss,
+                                                double& mx) {
+  T out;
+  if (MODE == kApply || MODE == kApplyDot) out = acc;
+  else if (MODE == kJacobi) out = fma(omega * Prec<T>::invd(M), bv - acc, xc);
+  else if (MODE == kResidual) out = bv - acc;
+  else out = bv;
+  if (MODE != kNormB) st(yp, out);
+  accum<T, MODE>(ss, mx, out, xc);
+}
+
+// Rows off the y = 0 (and, in 3D, z = 0) faces: a boundary lane is the row's
+// first point (x = 0), its last (on the far face x + y + z = N), or both, so
+// it has one of three support masks known at compile time.  Their partial
+// stencils are uniform (one weight per offset for all lanes), and the
+// neighbours outside the macro are known at compile time — x - 1 for x = 0,
+// the offsets of coordinate sum +1 on the far face — so those terms are left
+// out.
+template <int DIM>
+struct RowMasks {
+  static constexpr int L = full_mask(DIM) & ~2;   // x = 0
+  static constexpr int F = full_mask(DIM) & ~1;   // far face
+  static constexpr int LF = full_mask(DIM) & ~3;  // both
+};
+
+template <typename T, int DIM, int MASK>
+__device__ __forceinline__ T group_sum(const WTab<T> W, const T* v) {
+  constexpr StencilTable ST = stencil_table(DIM);
+  constexpr bool left = !(MASK & 2), far = !(MASK & 1);
+  T acc = T(0);
+#pragma unroll
+  for (int o = 0; o < ST.n; ++o) {
+    const int osum = ST.off[o][0] + ST.off[o][1] + ST.off[o][2];
+    if ((left && ST.off[o][0] < 0) || (far && osum > 0)) continue;
+    acc = fma(W[MASK][o], v[o], acc);
+  }
+  return acc;
+}
+
+// Row of one point from its neighbour values v (xc = its x, bv = its b).
+// Every lane first takes the interior stencil.  may_face (a compile-time
+// constant after unrolling) marks the rows that can lie on the y = 0 / z = 0
+// faces: those go through the general per-lane path.  Other rows fix up
+// their x = 0 lane (only in tiles starting at x0 = 0, tile_left) and their
+// far-face lane branch-free, with the uniform partial stencils above;
+// Jacobi needs bid = 1 / centre weight of the L, F and LF masks.
 template <typename T, int DIM, int MODE>
 __device__ __forceinline__ void point_row(const MacroDev& M, const WTab<T> W, const T* wi, bool inside, int N, int x,
                                           int y, int z, const T* v, T xc, T bv, T omega, T* yp, double& ss,
-                                          double& mx) {
+                                          double& mx, bool may_face, bool tile_left, const T* bid) {
+  using RM = RowMasks<DIM>;
   constexpr int FM = full_mask(DIM);
   constexpr int NO = DIM == 2 ? 7 : 15;
   T acc = wi[0] * v[0];
 #pragma unroll
   for (int o = 1; o < NO; ++o) acc = fma(wi[o], v[o], acc);
-  // y and z are uniform, so only x == 0 and the far face are per-lane tests
-  const bool special = inside && (x == 0 || y == 0 || (DIM == 3 && z == 0) || x + y + z == N);
-  if (__builtin_amdgcn_ballot_w64(special)) {
-    const int mask = support_mask(DIM, N, x, y, z);
-    const T pacc = partial_sum<T, DIM>(W, special ? mask : FM, N, x, y, z, v);
-    if (special) acc = pacc;
-    if (inside) finish<T, DIM, MODE>(M, W, mask, acc, xc, bv, omega, yp, ss, mx);
-  } else if (inside) {
-    T out;
-    if (MODE == kApply || MODE == kApplyDot) out = acc;
-    else if (MODE == kJacobi) out = fma(omega * Prec<T>::invd(M), bv - acc, xc);
-    else if (MODE == kResidual) out = bv - acc;
-    else out = bv;
+  if (may_face && (y == 0 || (DIM == 3 && z == 0))) {
+    // a row on the y = 0 or z = 0 face: every lane is a boundary point
+    if (__builtin_amdgcn_ballot_w64(inside)) {
+      const int mask = support_mask(DIM, N, x, y, z);
+      acc = partial_sum<T, DIM>(W, inside ? mask : FM, N, x, y, z, v);
+      if (inside) finish<T, DIM, MODE>(M, W, mask, acc, xc, bv, omega, yp, ss, mx);
+    }
+    return;
+  }
+  const bool far = inside && x + y + z == N;
+  const bool left = tile_left && inside && x == 0;
+  if (!__builtin_amdgcn_ballot_w64(far || left)) {
+    if (inside) finish_interior<T, MODE>(M, acc, xc, bv, omega, yp, ss, mx);
+    return;
+  }
+  T ab = group_sum<T, DIM, RM::F>(W, v);
+  int bm = RM::F;
+  T bd = MODE == kJacobi ? bid[1] : T(0);
+  if (tile_left) {
+    const T al = group_sum<T, DIM, RM::L>(W, v);
+    const T alf = group_sum<T, DIM, RM::LF>(W, v);
+    if (left) {
+      ab = far ? alf : al;
+      bm = far ? RM::LF : RM::L;
+      if (MODE == kJacobi) bd = far ? bid[2] : bid[0];
+    }
+  }
+  const bool bnd = far || left;
+  const T a = bnd ? ab : acc;
+  const bool dir = bnd && ((M.dir_mask >> bm) & 1);
+  const bool shared = bnd && !dir && ((M.shared_mask >> bm) & 1);
+  const bool own = !bnd || ((M.own_mask >> bm) & 1);
+  T out;
+  if (MODE == kApply || MODE == kApplyDot) {
+    out = dir ? xc : a;
+  } else if (MODE == kJacobi) {
+    const T id = bnd ? bd : Prec<T>::invd(M);
+    out = dir ? xc : (shared ? a : fma(omega * id, bv - a, xc));
+  } else if (MODE == kResidual) {
+    out = dir ? bv - xc : (shared ? a : bv - a);
+  } else {
+    out = bv;
+  }
+  if (inside) {
     if (MODE != kNormB) st(yp, out);
-    accum<T, MODE>(ss, mx, out, xc);
+    if (dir ? own : !shared) accum<T, MODE>(ss, mx, out, xc);
   }
 }
 
@@ -240,6 +317,13 @@ __device__ __forceinline__ void tile2d(const int x0, const int y0, const MacroDe
   T wi[7];
 #pragma unroll
   for (int o = 0; o < 7; ++o) wi[o] = Prec<T>::w(M, FM, o);
+  T bid[3] = {T(0), T(0), T(0)};
+  if (MODE == kJacobi) {
+    constexpr int c = stencil_table(2).centre;
+    bid[0] = T(1) / W[RowMasks<2>::L][c];
+    bid[1] = T(1) / W[RowMasks<2>::F][c];
+    bid[2] = T(1) / W[RowMasks<2>::LF][c];
+  }
 
   const int xc = max(x, 0);
   T am = ldrow(X, N, y0 - 1, y1, xc);
@@ -267,7 +351,8 @@ __device__ __forceinline__ void tile2d(const int x0, const int y0, const MacroDe
     const T ap_l = up1(ap), ap_r = dn1(ap);
     const T v[7] = {am, am_r, a0_l, a0, a0_r, ap_l, ap};
     const bool inside = lane >= 1 && lane <= kTileW && x + yy <= N;
-    point_row<T, 2, MODE>(M, W, wi, inside, N, x, yy, 0, v, a0, bv, omega, Y + rs32(N, yy) + (unsigned)xc, ss, mx);
+    point_row<T, 2, MODE>(M, W, wi, inside, N, x, yy, 0, v, a0, bv, omega, Y + rs32(N, yy) + (unsigned)xc, ss, mx,
+                          k == 0, x0 == 0, bid);
     am = a0;
     am_r = a0_r;
     a0 = ap;
@@ -300,6 +385,13 @@ __device__ __forceinline__ void pencil3d(const int x0, const int y0, const int z
   T wi[15];
 #pragma unroll
   for (int o = 0; o < 15; ++o) wi[o] = Prec<T>::w(M, FM, o);
+  T bid[3] = {T(0), T(0), T(0)};
+  if (MODE == kJacobi) {
+    constexpr int c = stencil_table(3).centre;
+    bid[0] = T(1) / W[RowMasks<3>::L][c];
+    bid[1] = T(1) / W[RowMasks<3>::F][c];
+    bid[2] = T(1) / W[RowMasks<3>::LF][c];
+  }
   const int xc = max(x, 0);
   // Slice z of a macro starts at sum_{k<z} (S_k+1)(S_k+2)/2, S_k = N - k;
   // bases are advanced incrementally (slices past N are clamped to slice N).
@@ -352,7 +444,7 @@ __device__ __forceinline__ void pencil3d(const int x0, const int y0, const int z
         const bool inside = lane >= 1 && lane <= kTileW && x + y + z <= N;
         const T bv = MODE != kApply ? bq[k % 2][j - 1] : T(0);
         point_row<T, 3, MODE>(M, W, wi, inside, N, x, y, z, v, Bs[j], bv, omega, Yz + rs32(S, y) + (unsigned)xc, ss,
-                              mx);
+                              mx, j == 1 || k == 0, x0 == 0, bid);
       }
     }
     // slice z-1 is done: its slot takes the next slice (z+4)
