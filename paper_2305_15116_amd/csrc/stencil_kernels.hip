@@ -247,12 +247,15 @@ __device__ __forceinline__ void point_row(const MacroDev& M, const WTab<T> W, co
     if (inside) finish_interior<T, MODE>(M, acc, xc, bv, omega, yp, ss, mx);
     return;
   }
-  T ab = group_sum<T, DIM, RM::F>(W, v);
+  // a group on the Dirichlet boundary only copies x (or b - x): no partial sum
+  T ab = acc;
+  if (!((M.dir_mask >> RM::F) & 1)) ab = group_sum<T, DIM, RM::F>(W, v);
   int bm = RM::F;
   T bd = MODE == kJacobi ? bid[1] : T(0);
   if (tile_left) {
-    const T al = group_sum<T, DIM, RM::L>(W, v);
-    const T alf = group_sum<T, DIM, RM::LF>(W, v);
+    T al = acc, alf = acc;
+    if (!((M.dir_mask >> RM::L) & 1)) al = group_sum<T, DIM, RM::L>(W, v);
+    if (!((M.dir_mask >> RM::LF) & 1)) alf = group_sum<T, DIM, RM::LF>(W, v);
     if (left) {
       ab = far ? alf : al;
       bm = far ? RM::LF : RM::L;
