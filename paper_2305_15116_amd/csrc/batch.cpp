@@ -324,7 +324,7 @@ void build_plan(mf_batch* B) {
                       M.w.part);
     });
     reduce_corr([](const Member& M) {
-      return ReduceArgs{M.w.part, (int64_t)lev(M, M.level).segs.size(), M.w.result + 2, nullptr, 1, 0};
+      return ReduceArgs{M.w.part, lev(M, M.level).lin_blocks(), M.w.result + 2, nullptr, 1, 0};
     });
     for (int dim = 2; dim <= 3; ++dim)
       vector_op(P, corr, dim, kOpPcgDir, MF_F64, [](const Member& M, VecArgs& a) {
@@ -347,7 +347,7 @@ void build_plan(mf_batch* B) {
       return pcg_args(lev(M, M.level), M.x, M.w.r64, M.w.p64, M.w.q64, nullptr, nullptr, M.w.result, M.w.part);
     });
     reduce_corr([&](const Member& M) {
-      return ReduceArgs{M.w.part, (int64_t)lev(M, M.level).segs.size(), M.w.result, slot(M), 0, 0};
+      return ReduceArgs{M.w.part, lev(M, M.level).lin_blocks(), M.w.result, slot(M), 0, 0};
     });
   }
   // ---- first step of new members: Dirichlet values of x, then ||b||

@@ -323,7 +323,7 @@ int vcycle_solve(const mf_mesh* m, int level, const double* b, double* x, void* 
   rc = residual_norm(m, L, MF_F64, b, x, w.r64, w.part, w.result, &ss, &mx, s);
   if (!rc && pcg) rc = launch_fill(MF_F64, w.result + 2, 0.0, 6, s);
   if (rc) return rc;
-  const int64_t nseg = (int64_t)L.segs.size();
+  const int64_t nlin = L.lin_blocks();
   int it = 0;
   double rel = 0.0;
   bool converged = false;
@@ -352,12 +352,12 @@ int vcycle_solve(const mf_mesh* m, int level, const double* b, double* x, void* 
     } else {
       // conjugate gradients preconditioned by the V-cycle; scalars stay on the device
       rc = launch_pcg_zdot(m, L, vdt, w.r64, w.x[level], w.z64, w.result, w.part, s);
-      if (!rc) rc = launch_reduce_shift(w.part, nseg, w.result + 2, s);                // r.z, previous r.z
+      if (!rc) rc = launch_reduce_shift(w.part, nlin, w.result + 2, s);                // r.z, previous r.z
       if (!rc) rc = launch_pcg_dir(w.p64, w.z64, w.result, L.storage, s);              // p = z + beta p
       if (!rc) rc = launch_stencil(m, L, MF_F64, kApplyDot, w.p64, w.q64, nullptr, 0.0, w.part, s);
       if (!rc) rc = launch_reduce(w.part, stencil_partials(L), w.result + 4, s);       // p.Ap
       if (!rc) rc = launch_pcg_update(m, L, x, w.r64, w.p64, w.q64, w.result, w.part, s);
-      if (!rc) rc = launch_reduce(w.part, nseg, w.result, s);                          // r.r, max|r|
+      if (!rc) rc = launch_reduce(w.part, nlin, w.result, s);                          // r.r, max|r|
       double out[2] = {0.0, 0.0};
       if (!rc) rc = sync_result(w.result, out, s);
       if (!rc) {

@@ -113,23 +113,24 @@ struct ReduceArgs {
   int pad_;
 };
 
-// Per-point kernels of preconditioned conjugate gradients: FP64 vectors, one
-// wave per 64-point row segment, partial sums over unique DoFs (owner copies).
-// Scalars live on the device in res: [0] r.r  [1] max |r|  [2] r.z
-// [3] previous r.z  [4] p.A p.
+// Vector kernels of preconditioned conjugate gradients: FP64 vectors,
+// grid-stride over the storage index with nblk blocks, one (sum, max)
+// partial per block; sums count each unique DoF once (its owner copy, from
+// the level's owner bits).  Scalars live on the device in res:
+// [0] r.r  [1] max |r|  [2] r.z  [3] previous r.z  [4] p.A p.
 struct PcgArgs {
-  const Tile* segs;
-  int nseg;
+  int64_t n;
+  const uint32_t* own;  // owner bits of the storage DoFs
+  double* x;            // update: x += alpha p
+  double* r;            // zdot: read; update: r -= alpha q
+  double* p;            // update: read
+  const double* q;      // update: A p
+  const void* e;        // zdot: preconditioner output (FP32 or FP64)
+  double* z;            // zdot: z = s e (not written when z == e)
+  const double* res;    // scalars
+  double* part;         // sums at [0, nblk), maxima at [nblk, 2 nblk)
+  int nblk;
   int pad_;
-  const MacroDev* md;
-  double* x;          // update: x += alpha p
-  double* r;          // zdot: read; update: r -= alpha q
-  double* p;          // update: read; direction: p = z + beta p
-  const double* q;    // update: A p
-  const void* e;      // zdot: preconditioner output (FP32 or FP64)
-  double* z;          // zdot: z = s e (not written when z == e)
-  const double* res;  // scalars
-  double* part;       // sums at [0, nseg), maxima at [nseg, 2 nseg)
 };
 
 inline int vec_blocks(int64_t n) {
@@ -170,7 +171,7 @@ GroupArgs<T> exchange_args(const Level& L, const void* x, void* y, const void* b
   g.Y = (T*)y;
   g.B = (const T*)b;
   g.omega = (T)omega;
-  g.part = part ? part + L.tiles.size() : nullptr;
+  g.part = part ? part + L.tiles.size() / kWavesPerWG : nullptr;
   g.np = (int)L.n_partials();
   return g;
 }
@@ -227,9 +228,9 @@ inline VecArgs vec_args(void* y, const void* x, const double* res, int64_t n, do
 
 inline PcgArgs pcg_args(const Level& L, double* x, double* r, double* p, const double* q, const void* e, double* z,
                         const double* res, double* part) {
-  return PcgArgs{L.dev.segs, (int)L.segs.size(), 0, L.dev.md, x, r, p, q, e, z, res, part};
+  return PcgArgs{L.storage, L.dev.own_bits, x, r, p, q, e, z, res, part, (int)L.lin_blocks(), 0};
 }
-inline int pcg_blocks(const Level& L) { return transfer_blocks((int)L.segs.size()); }
+inline int pcg_blocks(const Level& L) { return (int)L.lin_blocks(); }
 
 // ---------------------------------------------------------------- batch ops
 enum OpKind : int {

@@ -48,7 +48,7 @@ int launch_axpy_f32(double* x, const float* e, const double* res, int64_t n, hip
 // Preconditioned conjugate gradients (scalars in res, see PcgArgs):
 // z = s e and partials of r . z (edtype: type of e; z == e: not written);
 // x += alpha p, r -= alpha q and partials of r . r, max |r|; p = z + beta p.
-// Partials: L.segs.size() slots.
+// Partials: L.lin_blocks() slots.
 int launch_pcg_zdot(const mf_mesh* m, const Level& L, int edtype, const double* r, const void* e, double* z,
                     const double* res, double* part, hipStream_t s);
 int launch_pcg_update(const mf_mesh* m, const Level& L, double* x, double* r, double* p, const double* q,

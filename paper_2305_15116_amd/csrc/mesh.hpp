@@ -1,6 +1,7 @@
 // Host-side macro mesh and per-level metadata.
 #pragma once
 
+#include <algorithm>
 #include <array>
 #include <cstdint>
 #include <mutex>
@@ -33,6 +34,7 @@ struct LevelDev {
   int32_t* cfirst = nullptr;   // storage index of each coarse unknown's first copy
   int32_t* cptr = nullptr;     // copies of each coarse unknown
   int64_t* cidx = nullptr;
+  uint32_t* own_bits = nullptr;
 };
 
 struct Level {
@@ -54,7 +56,11 @@ struct Level {
   int64_t nxgroups() const { return (int64_t)xgrp_ptr.size() - 1; }
   int64_t iface_blocks() const { return (ngroups() + kIfaceWG - 1) / kIfaceWG; }
   int64_t xgroup_blocks() const { return (nxgroups() + kIfaceWG - 1) / kIfaceWG; }
-  int64_t n_partials() const { return (int64_t)tiles.size() + xgroup_blocks(); }
+  // norm / dot partials of one stencil pass: one per workgroup of tiles, then one per exchange block
+  int64_t n_partials() const { return (int64_t)tiles.size() / kWavesPerWG + xgroup_blocks(); }
+  // blocks of the linear (grid-stride) vector kernels with partials
+  int64_t lin_blocks() const { return std::min<int64_t>(2048, std::max<int64_t>(1, (storage + 1023) / 1024)); }
+  std::vector<uint32_t> own_bits;  // bit i: storage DoF i is its unique DoF's owner copy
   // coarse direct solve
   int64_t ncoarse = 0;          // unknowns (unique non-Dirichlet DoFs); 0 = not prepared
   std::vector<double> cinv;     // ncoarse^2 inverse of the interior block

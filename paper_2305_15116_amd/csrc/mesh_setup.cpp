@@ -423,6 +423,43 @@ static int build_level(mf_mesh* m, int level, Level& L) {
   else interior = N >= 4 ? tet_count(N - 3) : 0;
   L.unique = interior * m->nc + ngroups;
 
+  // owner bits: bit i set iff storage DoF i is the copy that counts its
+  // unique DoF in norms and dot products (interior points, and boundary
+  // points whose primitive this macro owns)
+  L.own_bits.assign((size_t)((L.storage + 31) / 32), 0u);
+  auto set_range = [&](int64_t lo, int64_t hi) {  // bits [lo, hi)
+    for (int64_t i = lo; i < hi;) {
+      if ((i & 31) == 0 && i + 32 <= hi) {
+        L.own_bits[i >> 5] = 0xffffffffu;
+        i += 32;
+      } else {
+        L.own_bits[i >> 5] |= 1u << (i & 31);
+        ++i;
+      }
+    }
+  };
+  for (int64_t c = 0; c < m->nc; ++c) {
+    const uint16_t om = m->own_mask[c];
+    const int zmax = dim == 3 ? N : 0;
+    for (int z = 0; z <= zmax; ++z) {
+      const int S = N - z;
+      for (int y = 0; y <= S; ++y) {
+        const int64_t r0 = L.base[c] + (dim == 2 ? idx2(N, 0, y) : idx3(N, 0, y, z));
+        const int len = S - y + 1;
+        if (y >= 1 && z >= 1 - (dim == 2 ? 1 : 0) && len >= 3) {
+          set_range(r0 + 1, r0 + len - 1);
+          for (int x : {0, len - 1})
+            if ((om >> support_mask(dim, N, x, y, z)) & 1) set_range(r0 + x, r0 + x + 1);
+        } else {
+          for (int x = 0; x < len; ++x) {
+            const int mk = support_mask(dim, N, x, y, z);
+            if (mk == full_mask(dim) || ((om >> mk) & 1)) set_range(r0 + x, r0 + x + 1);
+          }
+        }
+      }
+    }
+  }
+
   // wave tiles over every point of every macro, natural order: macro,
   // (slice chunk,) strip, band
   L.tiles.clear();
@@ -466,6 +503,7 @@ int upload_level(mf_mesh* m, Level& L) {
   if ((rc = dev_upload(&D.xgrp_ptr, L.xgrp_ptr))) return rc;
   if ((rc = dev_upload(&D.xcopies, L.xcopies))) return rc;
   if ((rc = dev_upload(&D.xgrp_invdiag, L.xgrp_invdiag))) return rc;
+  if ((rc = dev_upload(&D.own_bits, L.own_bits))) return rc;
   std::vector<float> f(L.xgrp_invdiag.begin(), L.xgrp_invdiag.end());
   if ((rc = dev_upload(&D.xgrp_invdiagf, f))) return rc;
   std::vector<double> zeros(2 * (L.n_partials() + 1), 0.0);
@@ -636,7 +674,7 @@ void free_device(mf_mesh* m) {
     LevelDev& D = L.dev;
     void* ptrs[] = {D.md, D.tiles, D.segs, D.grp_ptr, D.copies, D.grp_flag, D.xgrp_ptr, D.xcopies, D.xgrp_invdiag,
                     D.xgrp_invdiagf,
-                    D.part, D.result, D.cinv, D.cinvf, D.cfirst, D.cptr, D.cidx};
+                    D.part, D.result, D.cinv, D.cinvf, D.cfirst, D.cptr, D.cidx, D.own_bits};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
     if (D.host_result) (void)hipHostFree(D.host_result);

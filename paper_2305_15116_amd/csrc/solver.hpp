@@ -73,7 +73,7 @@ inline Workspace carve(const mf_mesh* m, int level, int mode, int lc, char* base
     w.q64 = (double*)take(8 * SL);
   }
   const Level& L = m->levels[level];
-  const int64_t np = std::max<int64_t>(L.n_partials(), mode_pcg(mode) ? (int64_t)L.segs.size() : 0);
+  const int64_t np = std::max<int64_t>(L.n_partials(), mode_pcg(mode) ? L.lin_blocks() : 0);
   w.part = (double*)take(8 * 2 * (np + 1));
   w.result = (double*)take(8 * 8);
   w.bytes = off;

@@ -528,11 +528,18 @@ __global__ __launch_bounds__(kWG) void stencil_kernel(const Launch<StencilArgs<T
       pencil3d<T, MODE>(t.x0, t.y0, t.z, M, W, a.X, a.Y, a.B, a.omega, ss, mx);
   }
   if (kPart && a.part != nullptr) {
+    // one partial per workgroup: its four waves summed in a fixed order
     ss = wave_sum(ss);
     mx = wave_max(mx);
+    __shared__ double s_ss[kWavesPerWG], s_mx[kWavesPerWG];
     if ((threadIdx.x & (kWave - 1)) == 0) {
-      a.part[ti] = ss;
-      a.part[a.np + ti] = mx;
+      s_ss[wv] = ss;
+      s_mx[wv] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      a.part[n] = (s_ss[0] + s_ss[1]) + (s_ss[2] + s_ss[3]);
+      a.part[a.np + n] = fmax(fmax(s_mx[0], s_mx[1]), fmax(s_mx[2], s_mx[3]));
     }
   }
 }
@@ -614,20 +621,30 @@ __global__ __launch_bounds__(kIfaceWG) void iface_kernel(const Launch<GroupArgs<
 }
 
 // result = (sum of part[0, np), max of part[np, 2 np)) in a fixed order; one
-// block per request.
-__global__ __launch_bounds__(256) void reduce_kernel(const Launch<ReduceArgs> L) {
+// block of kRedT threads per request, four loads in flight per thread.
+constexpr int kRedT = 512;
+__global__ __launch_bounds__(kRedT) void reduce_kernel(const Launch<ReduceArgs> L) {
   ReduceArgs r;
   resolve(L, (int)blockIdx.x, r);
-  __shared__ double s[256], m[256];
-  double a = 0.0, b = 0.0;
-  for (int64_t i = threadIdx.x; i < r.np; i += 256) {
-    a += r.part[i];
+  __shared__ double s[kRedT], m[kRedT];
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, b = 0.0;
+  int64_t i = threadIdx.x;
+  for (; i + 3 * kRedT < r.np; i += 4 * kRedT) {
+    a0 += r.part[i];
+    a1 += r.part[i + kRedT];
+    a2 += r.part[i + 2 * kRedT];
+    a3 += r.part[i + 3 * kRedT];
+    b = fmax(fmax(b, fmax(r.part[r.np + i], r.part[r.np + i + kRedT])),
+             fmax(r.part[r.np + i + 2 * kRedT], r.part[r.np + i + 3 * kRedT]));
+  }
+  for (; i < r.np; i += kRedT) {
+    a0 += r.part[i];
     b = fmax(b, r.part[r.np + i]);
   }
-  s[threadIdx.x] = a;
+  s[threadIdx.x] = (a0 + a1) + (a2 + a3);
   m[threadIdx.x] = b;
   __syncthreads();
-  for (int w = 128; w >= 1; w >>= 1) {
+  for (int w = kRedT / 2; w >= 1; w >>= 1) {
     if ((int)threadIdx.x < w) {
       s[threadIdx.x] += s[threadIdx.x + w];
       m[threadIdx.x] = fmax(m[threadIdx.x], m[threadIdx.x + w]);
@@ -764,19 +781,19 @@ int launch_iface(const mf_mesh* m, const Level& L, int dtype, int mode, const vo
 }
 
 int launch_reduce(const double* part, int64_t np, double* result, hipStream_t s) {
-  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, s, single(ReduceArgs{part, np, result, nullptr, 0, 0}, 1));
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kRedT), 0, s, single(ReduceArgs{part, np, result, nullptr, 0, 0}, 1));
   return check_launch();
 }
 
 int launch_reduce_shift(const double* part, int64_t np, double* result, hipStream_t s) {
-  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, s, single(ReduceArgs{part, np, result, nullptr, 1, 0}, 1));
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kRedT), 0, s, single(ReduceArgs{part, np, result, nullptr, 1, 0}, 1));
   return check_launch();
 }
 
 int launch_stencil_batch(const BatchOp& op, const char* table, hipStream_t s) {
   if (op.nwg <= 0) return MF_OK;
   if (op.kind == kOpReduce) {
-    hipLaunchKernelGGL(reduce_kernel, dim3(op.nwg), dim3(256), 0, s, batched<ReduceArgs>(op, table));
+    hipLaunchKernelGGL(reduce_kernel, dim3(op.nwg), dim3(kRedT), 0, s, batched<ReduceArgs>(op, table));
     return check_launch();
   }
   if (op.dtype == MF_F64) {

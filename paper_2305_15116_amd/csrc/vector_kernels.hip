@@ -237,50 +237,49 @@ __device__ __forceinline__ double wmax(double v) {
   return v;
 }
 
-// One 64-point row segment per wave.  KIND kOpPcgZDot: z = s e with s = res[1]
-// for FP32 e (the preconditioner solved for r / max|r|) and 1 for FP64 e,
-// partials of r . z.  KIND kOpPcgUpdate: alpha = res[2] / res[4],
-// x += alpha p, r -= alpha q, partials of r . r and max |r|.  Sums count each
-// unique DoF once (its owner macro's copy).
-template <int DIM, int KIND, typename TE>
-__global__ __launch_bounds__(kWG) void pcg_point_kernel(const Launch<PcgArgs> L) {
-  constexpr int full = DIM == 2 ? 7 : 15;
+// Grid-stride over the storage index, nblk blocks of 256 threads.  KIND
+// kOpPcgZDot: z = s e with s = res[1] for FP32 e (the preconditioner solved
+// for r / max|r|) and 1 for FP64 e, partials of r . z.  KIND kOpPcgUpdate:
+// alpha = res[2] / res[4], x += alpha p, r -= alpha q, partials of r . r and
+// max |r|.  Sums count each unique DoF once (owner bits); each block leaves
+// one partial, its four waves summed in a fixed order.
+template <int KIND, typename TE>
+__global__ __launch_bounds__(256) void pcg_lin_kernel(const Launch<PcgArgs> L) {
   PcgArgs a;
   const int blk = resolve(L, (int)blockIdx.x, a);
-  const int si = blk * kWavesPerWG + (threadIdx.x >> 6);
+  const int64_t stride = (int64_t)a.nblk * 256;
   double ss = 0.0, mx = 0.0;
-  if (si < a.nseg) {
-    const Tile sg = a.segs[si];
-    if (sg.macro >= 0) {
-      const MacroDev& M = a.md[sg.macro];
-      const int N = M.N;
-      const int x = sg.x0 + (threadIdx.x & (kWave - 1));
-      const int y = sg.y0, z = DIM == 3 ? sg.z : 0;
-      if (x + y + z <= N) {
-        const int mask = support_mask(DIM, N, x, y, z);
-        const bool owned = mask == full || ((M.own_mask >> mask) & 1);
-        const int64_t i = M.base + lidx<DIM>(N, x, y, z);
-        if (KIND == kOpPcgZDot) {
-          const double sc = sizeof(TE) == 4 ? a.res[1] : 1.0;
-          const double zv = sc * (double)((const TE*)a.e)[i];
-          if ((const void*)a.z != a.e) a.z[i] = zv;
-          if (owned) ss = a.r[i] * zv;
-        } else {
-          const double alpha = a.res[2] / a.res[4];
-          a.x[i] = fma(alpha, a.p[i], a.x[i]);
-          const double rn = fma(-alpha, a.q[i], a.r[i]);
-          a.r[i] = rn;
-          if (owned) ss = rn * rn;
-          mx = fabs(rn);
-        }
-      }
+  if (KIND == kOpPcgZDot) {
+    const double sc = sizeof(TE) == 4 ? a.res[1] : 1.0;
+    const TE* e = (const TE*)a.e;
+    const bool wz = (const void*)a.z != a.e;
+    for (int64_t i = (int64_t)blk * 256 + threadIdx.x; i < a.n; i += stride) {
+      const double zv = sc * (double)e[i];
+      if (wz) a.z[i] = zv;
+      if ((a.own[i >> 5] >> (i & 31)) & 1u) ss = fma(a.r[i], zv, ss);
+    }
+  } else {
+    const double alpha = a.res[2] / a.res[4];
+    for (int64_t i = (int64_t)blk * 256 + threadIdx.x; i < a.n; i += stride) {
+      a.x[i] = fma(alpha, a.p[i], a.x[i]);
+      const double rn = fma(-alpha, a.q[i], a.r[i]);
+      a.r[i] = rn;
+      if ((a.own[i >> 5] >> (i & 31)) & 1u) ss = fma(rn, rn, ss);
+      mx = fmax(mx, fabs(rn));
     }
   }
   ss = wsum(ss);
   mx = wmax(mx);
-  if ((threadIdx.x & (kWave - 1)) == 0 && si < a.nseg) {
-    a.part[si] = ss;
-    a.part[a.nseg + si] = mx;
+  __shared__ double s_ss[4], s_mx[4];
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    s_ss[w] = ss;
+    s_mx[w] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a.part[blk] = (s_ss[0] + s_ss[1]) + (s_ss[2] + s_ss[3]);
+    a.part[a.nblk + blk] = fmax(fmax(s_mx[0], s_mx[1]), fmax(s_mx[2], s_mx[3]));
   }
 }
 
@@ -421,13 +420,9 @@ int launch_axpy_f32(double* x, const float* e, const double* res, int64_t n, hip
 namespace {
 template <int KIND>
 void run_pcg_point(int dim, int dtype, const Launch<PcgArgs>& l, hipStream_t s) {
-  if (dim == 2) {
-    if (dtype == MF_F32) hipLaunchKernelGGL((pcg_point_kernel<2, KIND, float>), dim3(l.nwg), dim3(kWG), 0, s, l);
-    else hipLaunchKernelGGL((pcg_point_kernel<2, KIND, double>), dim3(l.nwg), dim3(kWG), 0, s, l);
-  } else {
-    if (dtype == MF_F32) hipLaunchKernelGGL((pcg_point_kernel<3, KIND, float>), dim3(l.nwg), dim3(kWG), 0, s, l);
-    else hipLaunchKernelGGL((pcg_point_kernel<3, KIND, double>), dim3(l.nwg), dim3(kWG), 0, s, l);
-  }
+  (void)dim;
+  if (dtype == MF_F32) hipLaunchKernelGGL((pcg_lin_kernel<KIND, float>), dim3(l.nwg), dim3(256), 0, s, l);
+  else hipLaunchKernelGGL((pcg_lin_kernel<KIND, double>), dim3(l.nwg), dim3(256), 0, s, l);
 }
 }  // namespace
 
