@@ -62,7 +62,7 @@ struct PlanBuilder {
   }
   // items: (argument record, workgroups); members with no workgroups are dropped.
   template <class A>
-  void add(int kind, int dtype, int dim, int mode, const std::vector<std::pair<A, int>>& items) {
+  void add(int kind, int dtype, int dim, int mode, const std::vector<std::pair<A, int>>& items, int variant = 0) {
     std::vector<const std::pair<A, int>*> live;
     for (const auto& it : items)
       if (it.second > 0) live.push_back(&it);
@@ -72,6 +72,7 @@ struct PlanBuilder {
     op.dtype = dtype;
     op.dim = dim;
     op.mode = mode;
+    op.variant = variant;
     op.nseg = (int)live.size();
     align(64);
     op.args_off = (int64_t)buf.size();
@@ -125,7 +126,8 @@ struct Pass {
 template <typename T, class Sel>
 void stencil_pass(PlanBuilder& P, const std::vector<Member*>& ms, int dim, int dtype, int mode, double omega,
                   Sel sel) {
-  std::vector<std::pair<StencilArgs<T>, int>> sa;
+  // one stencil launch per pencil depth (levels differ in it), then one exchange launch
+  std::vector<std::pair<StencilArgs<T>, int>> sa[2];
   std::vector<std::pair<GroupArgs<T>, int>> ga;
   for (Member* M : ms) {
     if (M->m->dim != dim) continue;
@@ -133,10 +135,11 @@ void stencil_pass(PlanBuilder& P, const std::vector<Member*>& ms, int dim, int d
     if (!sel(*M, p)) continue;
     const Level& L = lev(*M, p.level);
     const StencilArgs<T> a = stencil_args<T>(L, p.x, p.y, p.b, omega, p.part);
-    sa.push_back({a, a.nwg});
+    sa[dim == 3 && L.pen_z == kPenZSmall ? 1 : 0].push_back({a, a.nwg});
     ga.push_back({exchange_args<T>(L, p.x, p.y, p.b, omega, p.part), exchange_blocks(L)});
   }
-  P.add(kOpStencil, dtype, dim, mode, sa);
+  P.add(kOpStencil, dtype, dim, mode, sa[0], kPenZ);
+  P.add(kOpStencil, dtype, dim, mode, sa[1], kPenZSmall);
   P.add(kOpExchange, dtype, dim, mode, ga);
 }
 

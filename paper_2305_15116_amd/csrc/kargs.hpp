@@ -74,6 +74,7 @@ template <typename T>
 struct TransferArgs {
   const Tile* segs;
   int nseg;
+  int nblk;  // blocks of this request: each wave loops over segments with stride 4 nblk
   const MacroDev* mdc;
   const MacroDev* mdf;
   const T* src;
@@ -198,15 +199,21 @@ GroupArgs<T> iface_args(const Level& L, const void* x, void* y, const void* b) {
 inline int iface_blocks(const Level& L) { return (int)L.iface_blocks(); }
 
 // restriction: coarse points gather fine values; prolongation: fine points.
+// At most kTransferBlocks workgroups; each wave walks several segments.
+constexpr int kTransferBlocks = 8192;
+inline int transfer_blocks(int nseg) {
+  return std::min(kTransferBlocks, (nseg + kWavesPerWG - 1) / kWavesPerWG);
+}
 template <typename T>
 TransferArgs<T> restrict_args(const Level& F, const Level& C, const void* rf, void* bc) {
-  return TransferArgs<T>{C.dev.segs, (int)C.segs.size(), C.dev.md, F.dev.md, (const T*)rf, (T*)bc};
+  const int n = (int)C.segs.size();
+  return TransferArgs<T>{C.dev.segs, n, transfer_blocks(n), C.dev.md, F.dev.md, (const T*)rf, (T*)bc};
 }
 template <typename T>
 TransferArgs<T> prolong_args(const Level& F, const Level& C, const void* ec, void* xf) {
-  return TransferArgs<T>{F.dev.segs, (int)F.segs.size(), C.dev.md, F.dev.md, (const T*)ec, (T*)xf};
+  const int n = (int)F.segs.size();
+  return TransferArgs<T>{F.dev.segs, n, transfer_blocks(n), C.dev.md, F.dev.md, (const T*)ec, (T*)xf};
 }
-inline int transfer_blocks(int nseg) { return (nseg + kWavesPerWG - 1) / kWavesPerWG; }
 
 template <typename T>
 CoarseArgs<T> coarse_args(const Level& L, const void* b, void* x);
@@ -257,6 +264,8 @@ struct BatchOp {
   int kind, dtype, dim, mode;
   int nseg, nwg;
   int64_t args_off, wg0_off;
+  int variant;  // stencil ops: 3D pencil depth of the members' levels
+  int pad_;
 };
 
 }  // namespace mf

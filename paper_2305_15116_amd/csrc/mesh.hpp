@@ -40,6 +40,7 @@ struct LevelDev {
 struct Level {
   int level = 0;
   int N = 0;
+  int pen_z = 0;  // 3D pencil depth of the wave tiles (kPenZ or kPenZSmall)
   int64_t storage = 0, unique = 0;
   std::vector<int64_t> base;    // per macro storage offset
   std::vector<MacroDev> md;

@@ -463,13 +463,14 @@ static int build_level(mf_mesh* m, int level, Level& L) {
   // wave tiles over every point of every macro, natural order: macro,
   // (slice chunk,) strip, band
   L.tiles.clear();
-  L.tiles.reserve((size_t)m->nc * (macro_points(dim, N) / (kTileW * (dim == 2 ? kTileH2 : kPenR * kPenZ)) * 2 + 64));
+  L.pen_z = N < kPenZSmallBelowN ? kPenZSmall : kPenZ;
+  L.tiles.reserve((size_t)m->nc * (macro_points(dim, N) / (kTileW * (dim == 2 ? kTileH2 : kPenR * L.pen_z)) * 2 + 64));
   for (int64_t c = 0; c < m->nc; ++c) {
     if (dim == 2) {
       for (int y0 = 0; y0 <= N; y0 += kTileH2)
         for (int x0 = 0; x0 + y0 <= N; x0 += kTileW) L.tiles.push_back({(int32_t)c, x0, y0, 0});
     } else {
-      for (int z0 = 0; z0 <= N; z0 += kPenZ)
+      for (int z0 = 0; z0 <= N; z0 += L.pen_z)
         for (int y0 = 0; y0 + z0 <= N; y0 += kPenR)
           for (int x0 = 0; x0 + y0 + z0 <= N; x0 += kTileW) L.tiles.push_back({(int32_t)c, x0, y0, z0});
     }

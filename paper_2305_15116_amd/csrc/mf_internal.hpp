@@ -34,6 +34,10 @@ constexpr int kTileH2 = MF_TILE_H2;   // rows per 2D wave tile
 #endif
 constexpr int kPenR = MF_PEN_R;
 constexpr int kPenZ = MF_PEN_Z;
+// Small levels use shorter pencils: a wave's walk is a chain of dependent
+// slice loads, and with few waves in flight its length sets the kernel time.
+constexpr int kPenZSmall = 4;
+constexpr int kPenZSmallBelowN = 128;  // pencil depth kPenZSmall when N < this
 constexpr int kWavesPerWG = 4;
 constexpr int kWG = kWave * kWavesPerWG;
 constexpr int kIfaceWG = 256;  // groups per interface workgroup

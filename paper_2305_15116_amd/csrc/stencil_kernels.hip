@@ -371,7 +371,7 @@ __device__ __forceinline__ void tile2d(const int x0, const int y0, const MacroDe
 // consecutive slices in registers (z-1, z, z+1 and two in flight) and walks
 // z upward, so each value is loaded once per pencil.  Rows, columns and
 // slices outside the macro are clamped to a valid point (values never used).
-template <typename T, int MODE>
+template <typename T, int MODE, int PZ>
 __device__ __forceinline__ void pencil3d(const int x0, const int y0, const int z0, const MacroDev& M, WTab<T> W,
                                          const T* __restrict__ X, T* __restrict__ Y, const T* __restrict__ B,
                                          T omega, double& ss, double& mx) {
@@ -381,7 +381,7 @@ __device__ __forceinline__ void pencil3d(const int x0, const int y0, const int z
   const int lane = threadIdx.x & (kWave - 1);
   const int N = M.N;
   const int x = x0 - 1 + lane;
-  const int nz = min(kPenZ, N + 1 - x0 - y0 - z0);  // output slices z0 .. z0+nz-1
+  const int nz = min(PZ, N + 1 - x0 - y0 - z0);  // output slices z0 .. z0+nz-1
   X += M.base;
   Y += M.base;
   if (MODE != kApply) B += M.base;
@@ -425,10 +425,10 @@ __device__ __forceinline__ void pencil3d(const int x0, const int y0, const int z
     for (int j = 0; j < kPenR; ++j) bq[0][j] = ld(B, zb, z0, y0 + j);
   }
 #pragma unroll
-  for (int k = 0; k < kPenZ; ++k) {
+  for (int k = 0; k < PZ; ++k) {
     const int z = z0 + k;
     const int64_t zb1 = next_base(zb, min(z, N));
-    if (MODE != kApply && k + 1 < kPenZ) {
+    if (MODE != kApply && k + 1 < PZ) {
 #pragma unroll
       for (int j = 0; j < kPenR; ++j) bq[(k + 1) % 2][j] = ld(B, zb1, z + 1, y0 + j);
     }
@@ -495,7 +495,7 @@ __device__ __forceinline__ int resolve(const Launch<A>& L, int g, A& a) {
   return g - as_const(L.wg0)[r];
 }
 
-template <typename T, int DIM, int MODE>
+template <typename T, int DIM, int MODE, int PZ>
 __global__ __launch_bounds__(kWG) void stencil_kernel(const Launch<StencilArgs<T>> L) {
   constexpr bool kPart = has_partials(MODE);
   const int g = xcd_wg(L.nwg);
@@ -525,7 +525,7 @@ __global__ __launch_bounds__(kWG) void stencil_kernel(const Launch<StencilArgs<T
     if (DIM == 2)
       tile2d<T, MODE>(t.x0, t.y0, M, W, a.X, a.Y, a.B, a.omega, ss, mx);
     else
-      pencil3d<T, MODE>(t.x0, t.y0, t.z, M, W, a.X, a.Y, a.B, a.omega, ss, mx);
+      pencil3d<T, MODE, PZ>(t.x0, t.y0, t.z, M, W, a.X, a.Y, a.B, a.omega, ss, mx);
   }
   if (kPart && a.part != nullptr) {
     // one partial per workgroup: its four waves summed in a fixed order
@@ -693,8 +693,14 @@ template <typename T, int DIM, int MODE>
 void run_stencil(const Level& L, const void* x, void* y, const void* b, double omega, double* part,
                  hipStream_t s) {
   const StencilArgs<T> a = stencil_args<T>(L, x, y, b, omega, part);
-  if (a.nwg > 0)
-    hipLaunchKernelGGL((stencil_kernel<T, DIM, MODE>), dim3(stencil_grid(a.nwg)), dim3(kWG), 0, s, single(a, a.nwg));
+  if (a.nwg > 0) {
+    if (DIM == 3 && L.pen_z == kPenZSmall)
+      hipLaunchKernelGGL((stencil_kernel<T, DIM, MODE, kPenZSmall>), dim3(stencil_grid(a.nwg)), dim3(kWG), 0, s,
+                         single(a, a.nwg));
+    else
+      hipLaunchKernelGGL((stencil_kernel<T, DIM, MODE, kPenZ>), dim3(stencil_grid(a.nwg)), dim3(kWG), 0, s,
+                         single(a, a.nwg));
+  }
   const int nblk = exchange_blocks(L);
   if (nblk == 0) return;
   hipLaunchKernelGGL((exchange_kernel<T, DIM, MODE>), dim3(nblk), dim3(kIfaceWG), 0, s,
@@ -738,8 +744,11 @@ int launch(const mf_mesh* m, const Level& L, int dtype, int mode, const void* x,
 // ---------------------------------------------------------------- batched
 template <typename T, int DIM, int MODE>
 void batch_stencil(const BatchOp& op, const char* table, hipStream_t s) {
-  if (op.kind == kOpStencil)
-    hipLaunchKernelGGL((stencil_kernel<T, DIM, MODE>), dim3(stencil_grid(op.nwg)), dim3(kWG), 0, s,
+  if (op.kind == kOpStencil && DIM == 3 && op.variant == kPenZSmall)
+    hipLaunchKernelGGL((stencil_kernel<T, DIM, MODE, kPenZSmall>), dim3(stencil_grid(op.nwg)), dim3(kWG), 0, s,
+                       batched<StencilArgs<T>>(op, table));
+  else if (op.kind == kOpStencil)
+    hipLaunchKernelGGL((stencil_kernel<T, DIM, MODE, kPenZ>), dim3(stencil_grid(op.nwg)), dim3(kWG), 0, s,
                        batched<StencilArgs<T>>(op, table));
   else
     hipLaunchKernelGGL((exchange_kernel<T, DIM, MODE>), dim3(op.nwg), dim3(kIfaceWG), 0, s,

@@ -114,15 +114,9 @@ __device__ __forceinline__ int resolve(const Launch<A>& L, int g, A& a) {
 // fine points this macro owns, so that the later exchange sums each fine DoF
 // once.  Dirichlet fine points are skipped.
 template <typename T, int DIM>
-__global__ __launch_bounds__(kWG) void restrict_kernel(const Launch<TransferArgs<T>> L) {
+__device__ __forceinline__ void restrict_segment(const TransferArgs<T>& a, const Tile sg) {
   constexpr StencilTable ST = stencil_table(DIM);
   constexpr int full = DIM == 2 ? 7 : 15;
-  TransferArgs<T> a;
-  const int blk = resolve(L, (int)blockIdx.x, a);
-  const int si = blk * kWavesPerWG + (threadIdx.x >> 6);
-  if (si >= a.nseg) return;
-  const Tile sg = a.segs[si];
-  if (sg.macro < 0) return;
   const MacroDev& C = a.mdc[sg.macro];
   const MacroDev& F = a.mdf[sg.macro];
   const int Nc = C.N, Nf = F.N;
@@ -145,19 +139,24 @@ __global__ __launch_bounds__(kWG) void restrict_kernel(const Launch<TransferArgs
   a.dst[C.base + lidx<DIM>(Nc, x, y, z)] = acc;
 }
 
+template <typename T, int DIM>
+__global__ __launch_bounds__(kWG) void restrict_kernel(const Launch<TransferArgs<T>> L) {
+  TransferArgs<T> a;
+  const int blk = resolve(L, (int)blockIdx.x, a);
+  const int stride = a.nblk * kWavesPerWG;
+  for (int si = blk * kWavesPerWG + (threadIdx.x >> 6); si < a.nseg; si += stride) {
+    const Tile sg = a.segs[si];
+    if (sg.macro >= 0) restrict_segment<T, DIM>(a, sg);
+  }
+}
+
 // x_f += P e_c: even fine points take the coarse value, the others the mean
 // of the two coarse endpoints of the coarse micro-edge they bisect; the
 // edge direction follows from the coordinate parities.  Dirichlet points are
 // left unchanged.
 template <typename T, int DIM>
-__global__ __launch_bounds__(kWG) void prolong_add_kernel(const Launch<TransferArgs<T>> L) {
+__device__ __forceinline__ void prolong_segment(const TransferArgs<T>& a, const Tile sg) {
   constexpr int full = DIM == 2 ? 7 : 15;
-  TransferArgs<T> a;
-  const int blk = resolve(L, (int)blockIdx.x, a);
-  const int si = blk * kWavesPerWG + (threadIdx.x >> 6);
-  if (si >= a.nseg) return;
-  const Tile sg = a.segs[si];
-  if (sg.macro < 0) return;
   const MacroDev& C = a.mdc[sg.macro];
   const MacroDev& F = a.mdf[sg.macro];
   const int Nc = C.N, Nf = F.N;
@@ -183,6 +182,18 @@ __global__ __launch_bounds__(kWG) void prolong_add_kernel(const Launch<TransferA
     e = T(0.5) * (u + v);
   }
   a.dst[F.base + lidx<DIM>(Nf, x, y, z)] += e;
+}
+
+// x_f += P e_c (each wave walks several segments of fine points).
+template <typename T, int DIM>
+__global__ __launch_bounds__(kWG) void prolong_add_kernel(const Launch<TransferArgs<T>> L) {
+  TransferArgs<T> a;
+  const int blk = resolve(L, (int)blockIdx.x, a);
+  const int stride = a.nblk * kWavesPerWG;
+  for (int si = blk * kWavesPerWG + (threadIdx.x >> 6); si < a.nseg; si += stride) {
+    const Tile sg = a.segs[si];
+    if (sg.macro >= 0) prolong_segment<T, DIM>(a, sg);
+  }
 }
 
 // Coarse direct solve: x(copies of unknown i) = sum_j Ainv[i][j] b(first copy of j).
