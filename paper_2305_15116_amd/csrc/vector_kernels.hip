@@ -113,12 +113,35 @@ __device__ __forceinline__ int resolve(const Launch<A>& L, int g, A& a) {
 // (weight 1/2) — the fine points whose interpolation uses P — counting only
 // fine points this macro owns, so that the later exchange sums each fine DoF
 // once.  Dirichlet fine points are skipped.
+// Segment and macro records are read-only for the launch: read them through
+// the constant address space (scalar loads, scalar registers).
+__device__ __forceinline__ Tile load_seg(const Tile* segs, int si) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return as_const(segs)[si];
+#else
+  return segs[si];
+#endif
+}
+struct MacroC {
+  int64_t base;
+  int32_t N;
+  uint16_t own_mask, dir_mask;
+};
+__device__ __forceinline__ MacroC load_macro(const MacroDev* md, int m) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const auto* p = as_const(md) + m;
+  return MacroC{p->base, p->N, p->own_mask, p->dir_mask};
+#else
+  return MacroC{md[m].base, md[m].N, md[m].own_mask, md[m].dir_mask};
+#endif
+}
+
 template <typename T, int DIM>
 __device__ __forceinline__ void restrict_segment(const TransferArgs<T>& a, const Tile sg) {
   constexpr StencilTable ST = stencil_table(DIM);
   constexpr int full = DIM == 2 ? 7 : 15;
-  const MacroDev& C = a.mdc[sg.macro];
-  const MacroDev& F = a.mdf[sg.macro];
+  const MacroC C = load_macro(a.mdc, sg.macro);
+  const MacroC F = load_macro(a.mdf, sg.macro);
   const int Nc = C.N, Nf = F.N;
   const int x = sg.x0 + (threadIdx.x & (kWave - 1));
   const int y = sg.y0, z = DIM == 3 ? sg.z : 0;
@@ -144,8 +167,9 @@ __global__ __launch_bounds__(kWG) void restrict_kernel(const Launch<TransferArgs
   TransferArgs<T> a;
   const int blk = resolve(L, (int)blockIdx.x, a);
   const int stride = a.nblk * kWavesPerWG;
-  for (int si = blk * kWavesPerWG + (threadIdx.x >> 6); si < a.nseg; si += stride) {
-    const Tile sg = a.segs[si];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int si = blk * kWavesPerWG + w; si < a.nseg; si += stride) {
+    const Tile sg = load_seg(a.segs, si);
     if (sg.macro >= 0) restrict_segment<T, DIM>(a, sg);
   }
 }
@@ -157,8 +181,8 @@ __global__ __launch_bounds__(kWG) void restrict_kernel(const Launch<TransferArgs
 template <typename T, int DIM>
 __device__ __forceinline__ void prolong_segment(const TransferArgs<T>& a, const Tile sg) {
   constexpr int full = DIM == 2 ? 7 : 15;
-  const MacroDev& C = a.mdc[sg.macro];
-  const MacroDev& F = a.mdf[sg.macro];
+  const MacroC C = load_macro(a.mdc, sg.macro);
+  const MacroC F = load_macro(a.mdf, sg.macro);
   const int Nc = C.N, Nf = F.N;
   const int x = sg.x0 + (threadIdx.x & (kWave - 1));
   const int y = sg.y0, z = DIM == 3 ? sg.z : 0;
@@ -190,8 +214,9 @@ __global__ __launch_bounds__(kWG) void prolong_add_kernel(const Launch<TransferA
   TransferArgs<T> a;
   const int blk = resolve(L, (int)blockIdx.x, a);
   const int stride = a.nblk * kWavesPerWG;
-  for (int si = blk * kWavesPerWG + (threadIdx.x >> 6); si < a.nseg; si += stride) {
-    const Tile sg = a.segs[si];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int si = blk * kWavesPerWG + w; si < a.nseg; si += stride) {
+    const Tile sg = load_seg(a.segs, si);
     if (sg.macro >= 0) prolong_segment<T, DIM>(a, sg);
   }
 }
