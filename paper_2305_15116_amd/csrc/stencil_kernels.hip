@@ -495,6 +495,14 @@ __device__ __forceinline__ int resolve(const Launch<A>& L, int g, A& a) {
   return g - as_const(L.wg0)[r];
 }
 
+// Whether a wave tile has output points on its macro's boundary (x = 0,
+// y = 0, z = 0 or the far face x + y + z = N).
+template <int DIM, int PZ>
+__device__ __forceinline__ bool tile_on_boundary(const Tile& t, int N) {
+  if (DIM == 2) return t.x0 == 0 || t.y0 == 0 || t.x0 + t.y0 + (kTileW - 1) + (kTileH2 - 1) >= N;
+  return t.x0 == 0 || t.y0 == 0 || t.z == 0 || t.x0 + t.y0 + t.z + (kTileW - 1) + (kPenR - 1) + (PZ - 1) >= N;
+}
+
 template <typename T, int DIM, int MODE, int PZ>
 __global__ __launch_bounds__(kWG) void stencil_kernel(const Launch<StencilArgs<T>> L) {
   constexpr bool kPart = has_partials(MODE);
@@ -507,14 +515,24 @@ __global__ __launch_bounds__(kWG) void stencil_kernel(const Launch<StencilArgs<T
   const int ti = n * kWavesPerWG + wv;
   const Tile t = a.tiles[ti];
   __shared__ T wtab[kWavesPerWG][16][16];
-  // the workgroup's four tiles usually share one macro: then one table serves
-  // all waves (one load per thread); otherwise each wave loads its own
+  // The partial-stencil table is only read by tiles that reach the macro's
+  // boundary.  The workgroup's four tiles usually share one macro: then one
+  // table serves all waves (one load per thread), loaded only if one of the
+  // four tiles needs it; otherwise each wave loads its own when it needs it.
   const int m0 = a.tiles[n * kWavesPerWG].macro, m3 = a.tiles[n * kWavesPerWG + kWavesPerWG - 1].macro;
   const bool same = m0 == m3;
   if (same) {
-    if (m0 >= 0) load_wtab<T>(a.md[m0], wtab[0], 0, kWG);
-    __syncthreads();
-  } else if (t.macro >= 0) {
+    bool need = false;
+    if (m0 >= 0) {
+      const int N0 = a.md[m0].N;
+#pragma unroll
+      for (int k = 0; k < kWavesPerWG; ++k) need = need || tile_on_boundary<DIM, PZ>(a.tiles[n * kWavesPerWG + k], N0);
+    }
+    if (need) {
+      load_wtab<T>(a.md[m0], wtab[0], 0, kWG);
+      __syncthreads();
+    }
+  } else if (t.macro >= 0 && tile_on_boundary<DIM, PZ>(t, a.md[t.macro].N)) {
     load_wtab<T>(a.md[t.macro], wtab[wv], wv * kWave, kWave);
     __builtin_amdgcn_wave_barrier();
   }
