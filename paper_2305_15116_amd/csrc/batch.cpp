@@ -344,7 +344,7 @@ void build_plan(mf_batch* B) {
         return true;
       });
     reduce_corr([](const Member& M) {
-      return ReduceArgs{M.w.part, stencil_partials(lev(M, M.level)), M.w.result + 4, nullptr, 0, 0};
+      return ReduceArgs{M.w.part, stencil_partials(lev(M, M.level), MF_F64), M.w.result + 4, nullptr, 0, 0};
     });
     pcg_op(kOpPcgUpdate, MF_F64, [](const Member& M) {
       return pcg_args(lev(M, M.level), M.x, M.w.r64, M.w.p64, M.w.q64, nullptr, nullptr, M.w.result, M.w.part);
@@ -374,7 +374,7 @@ void build_plan(mf_batch* B) {
   {
     std::vector<std::pair<ReduceArgs, int>> ra;
     for (Member* M : fresh)
-      ra.push_back({ReduceArgs{M->w.part, stencil_partials(lev(*M, M->level)), M->w.result, slot(*M) + 2, 0, 0}, 1});
+      ra.push_back({ReduceArgs{M->w.part, stencil_partials(lev(*M, M->level), MF_F64), M->w.result, slot(*M) + 2, 0, 0}, 1});
     reduce_op(P, ra);
   }
   // ---- FP64 residual and its norm: every member (refinement) or the new ones (PCG)
@@ -397,7 +397,7 @@ void build_plan(mf_batch* B) {
   {
     std::vector<std::pair<ReduceArgs, int>> ra;
     for (Member* M : resid)
-      ra.push_back({ReduceArgs{M->w.part, stencil_partials(lev(*M, M->level)), M->w.result, slot(*M), 0, 0}, 1});
+      ra.push_back({ReduceArgs{M->w.part, stencil_partials(lev(*M, M->level), MF_F64), M->w.result, slot(*M), 0, 0}, 1});
     reduce_op(P, ra);
   }
 }

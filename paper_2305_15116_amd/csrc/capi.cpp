@@ -51,7 +51,7 @@ int sync_result(const double* result_dev, double out[2], hipStream_t s) {
 // r = b - A x with partials in `part`; reduces to result_dev and copies back.
 int residual_norm(const mf_mesh* m, const Level& L, int dtype, const void* b, const void* x, void* r, double* part,
                   double* result_dev, double* ss, double* mx, hipStream_t s) {
-  const int64_t np = stencil_partials(L);
+  const int64_t np = stencil_partials(L, dtype);
   int rc = launch_stencil(m, L, dtype, kResidual, x, r, b, 0.0, part, s);
   if (!rc) rc = launch_reduce(part, np, result_dev, s);
   double out[2] = {0.0, 0.0};
@@ -66,7 +66,7 @@ int residual_norm(const mf_mesh* m, const Level& L, int dtype, const void* b, co
 // sum of squares and max |.| of b over unique DoFs
 int vector_norm(const mf_mesh* m, const Level& L, int dtype, const void* b, double* part, double* result_dev,
                 double* ss, double* mx, hipStream_t s) {
-  const int64_t np = stencil_partials(L);
+  const int64_t np = stencil_partials(L, dtype);
   int rc = launch_stencil(m, L, dtype, kNormB, b, nullptr, b, 0.0, part, s);
   if (!rc) rc = launch_reduce(part, np, result_dev, s);
   double out[2] = {0.0, 0.0};
@@ -355,7 +355,7 @@ int vcycle_solve(const mf_mesh* m, int level, const double* b, double* x, void* 
       if (!rc) rc = launch_reduce_shift(w.part, nlin, w.result + 2, s);                // r.z, previous r.z
       if (!rc) rc = launch_pcg_dir(w.p64, w.z64, w.result, L.storage, s);              // p = z + beta p
       if (!rc) rc = launch_stencil(m, L, MF_F64, kApplyDot, w.p64, w.q64, nullptr, 0.0, w.part, s);
-      if (!rc) rc = launch_reduce(w.part, stencil_partials(L), w.result + 4, s);       // p.Ap
+      if (!rc) rc = launch_reduce(w.part, stencil_partials(L, MF_F64), w.result + 4, s);       // p.Ap
       if (!rc) rc = launch_pcg_update(m, L, x, w.r64, w.p64, w.q64, w.result, w.part, s);
       if (!rc) rc = launch_reduce(w.part, nlin, w.result, s);                          // r.r, max|r|
       double out[2] = {0.0, 0.0};

@@ -143,10 +143,15 @@ inline int vec_blocks(int64_t n) {
 // ---------------------------------------------------------------- builders
 // The same records serve single launches and batch tables.
 template <typename T>
+constexpr int dtype_of() { return sizeof(T) == 4 ? MF_F32 : MF_F64; }
+
+template <typename T>
 StencilArgs<T> stencil_args(const Level& L, const void* x, void* y, const void* b, double omega, double* part) {
+  constexpr int dt = dtype_of<T>();
+  const bool f32 = dt == MF_F32 && !L.tiles_f32.empty();
   StencilArgs<T> a;
-  a.tiles = L.dev.tiles;
-  a.ntiles = (int)L.tiles.size();
+  a.tiles = f32 ? L.dev.tiles_f32 : L.dev.tiles;
+  a.ntiles = (int)L.tiles_for(dt).size();
   a.nwg = a.ntiles / kWavesPerWG;
   a.md = L.dev.md;
   a.X = (const T*)x;
@@ -154,7 +159,7 @@ StencilArgs<T> stencil_args(const Level& L, const void* x, void* y, const void* 
   a.B = (const T*)b;
   a.omega = (T)omega;
   a.part = part;
-  a.np = (int)L.n_partials();
+  a.np = (int)L.n_partials(dt);
   return a;
 }
 
@@ -172,8 +177,8 @@ GroupArgs<T> exchange_args(const Level& L, const void* x, void* y, const void* b
   g.Y = (T*)y;
   g.B = (const T*)b;
   g.omega = (T)omega;
-  g.part = part ? part + L.tiles.size() / kWavesPerWG : nullptr;
-  g.np = (int)L.n_partials();
+  g.part = part ? part + L.tiles_for(dtype_of<T>()).size() / kWavesPerWG : nullptr;
+  g.np = (int)L.n_partials(dtype_of<T>());
   return g;
 }
 inline int exchange_blocks(const Level& L) { return (int)L.xgroup_blocks(); }

@@ -17,7 +17,7 @@ namespace mf {
 // kResidual, kNormB.  part (nullable; kResidual / kNormB) receives sums of
 // squares at [0, np) and maxima at [np, 2 np), np = stencil_partials(L)
 // (at most L.n_partials(), which sizes the buffers).
-int64_t stencil_partials(const Level& L);
+int64_t stencil_partials(const Level& L, int dtype);
 int launch_stencil(const mf_mesh* m, const Level& L, int dtype, int mode, const void* x, void* y, const void* b,
                    double omega, double* part, hipStream_t s);
 

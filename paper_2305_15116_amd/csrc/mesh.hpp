@@ -17,6 +17,7 @@ namespace mf {
 struct LevelDev {
   MacroDev* md = nullptr;
   Tile* tiles = nullptr;       // interior wave tiles, padded to a multiple of kWavesPerWG
+  Tile* tiles_f32 = nullptr;   // 2D FP32 wave tiles
   Tile* segs = nullptr;        // row segments of 64 points covering every storage point
   int32_t* grp_ptr = nullptr;  // ngroups + 1
   Copy* copies = nullptr;
@@ -45,6 +46,7 @@ struct Level {
   std::vector<int64_t> base;    // per macro storage offset
   std::vector<MacroDev> md;
   std::vector<Tile> tiles;      // interior wave tiles (natural order, padded)
+  std::vector<Tile> tiles_f32;  // 2D FP32 wave tiles (kTileH2F rows); empty in 3D (same as tiles)
   std::vector<Tile> segs;       // per-point row segments
   std::vector<int32_t> grp_ptr;
   std::vector<Copy> copies;
@@ -57,8 +59,12 @@ struct Level {
   int64_t nxgroups() const { return (int64_t)xgrp_ptr.size() - 1; }
   int64_t iface_blocks() const { return (ngroups() + kIfaceWG - 1) / kIfaceWG; }
   int64_t xgroup_blocks() const { return (nxgroups() + kIfaceWG - 1) / kIfaceWG; }
+  const std::vector<Tile>& tiles_for(int dtype) const {
+    return dtype == MF_F32 && !tiles_f32.empty() ? tiles_f32 : tiles;
+  }
   // norm / dot partials of one stencil pass: one per workgroup of tiles, then one per exchange block
-  int64_t n_partials() const { return (int64_t)tiles.size() / kWavesPerWG + xgroup_blocks(); }
+  int64_t n_partials(int dtype) const { return (int64_t)tiles_for(dtype).size() / kWavesPerWG + xgroup_blocks(); }
+  int64_t n_partials() const { return std::max(n_partials(MF_F64), n_partials(MF_F32)); }  // buffer sizes
   // blocks of the linear (grid-stride) vector kernels with partials
   int64_t lin_blocks() const { return std::min<int64_t>(2048, std::max<int64_t>(1, (storage + 1023) / 1024)); }
   std::vector<uint32_t> own_bits;  // bit i: storage DoF i is its unique DoF's owner copy

@@ -476,6 +476,13 @@ static int build_level(mf_mesh* m, int level, Level& L) {
     }
   }
   while (L.tiles.size() % kWavesPerWG) L.tiles.push_back({-1, 0, 0, 0});
+  L.tiles_f32.clear();
+  if (dim == 2) {
+    for (int64_t c = 0; c < m->nc; ++c)
+      for (int y0 = 0; y0 <= N; y0 += kTileH2F)
+        for (int x0 = 0; x0 + y0 <= N; x0 += kTileW) L.tiles_f32.push_back({(int32_t)c, x0, y0, 0});
+    while (L.tiles_f32.size() % kWavesPerWG) L.tiles_f32.push_back({-1, 0, 0, 0});
+  }
 
   // row segments of 64 points over every storage point
   L.segs.clear();
@@ -497,6 +504,7 @@ int upload_level(mf_mesh* m, Level& L) {
   int rc;
   if ((rc = dev_upload(&D.md, L.md))) return rc;
   if ((rc = dev_upload(&D.tiles, L.tiles))) return rc;
+  if ((rc = dev_upload(&D.tiles_f32, L.tiles_f32))) return rc;
   if ((rc = dev_upload(&D.segs, L.segs))) return rc;
   if ((rc = dev_upload(&D.grp_ptr, L.grp_ptr))) return rc;
   if ((rc = dev_upload(&D.copies, L.copies))) return rc;
@@ -673,7 +681,7 @@ int build_mesh(mf_mesh* m) {
 void free_device(mf_mesh* m) {
   for (auto& L : m->levels) {
     LevelDev& D = L.dev;
-    void* ptrs[] = {D.md, D.tiles, D.segs, D.grp_ptr, D.copies, D.grp_flag, D.xgrp_ptr, D.xcopies, D.xgrp_invdiag,
+    void* ptrs[] = {D.md, D.tiles, D.tiles_f32, D.segs, D.grp_ptr, D.copies, D.grp_flag, D.xgrp_ptr, D.xcopies, D.xgrp_invdiag,
                     D.xgrp_invdiagf,
                     D.part, D.result, D.cinv, D.cinvf, D.cfirst, D.cptr, D.cidx, D.own_bits};
     for (void* p : ptrs)

@@ -23,7 +23,11 @@ constexpr int kTileW = 62;
 #ifndef MF_TILE_H2
 #define MF_TILE_H2 8
 #endif
-constexpr int kTileH2 = MF_TILE_H2;   // rows per 2D wave tile
+constexpr int kTileH2 = MF_TILE_H2;   // rows per 2D wave tile (FP64)
+// FP32 rows carry half the bytes: taller tiles with a deeper load ring keep
+// as many bytes in flight per wave.
+constexpr int kTileH2F = 16;
+constexpr int kRingU2F = 8;
 // 3D: a wave walks a "pencil" of kPenR rows upward through kPenZ slices,
 // keeping the rows of slices z-1, z, z+1 in registers.
 #ifndef MF_PEN_R

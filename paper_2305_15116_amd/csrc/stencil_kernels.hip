@@ -101,6 +101,17 @@ __device__ __forceinline__ int xcd_wg(int nwg) {
 #endif
 constexpr int kU2 = MF_RING_U2;  // rows loaded ahead (2D)
 static_assert(kTileH2 % kU2 == 0, "ring depth must divide the tile height");
+static_assert(kTileH2F % kRingU2F == 0, "ring depth must divide the tile height");
+
+// 2D tile height and load-ring depth per precision.
+template <typename T>
+struct Tile2 {
+  static constexpr int H = kTileH2, U = kU2;
+};
+template <>
+struct Tile2<float> {
+  static constexpr int H = kTileH2F, U = kRingU2F;
+};
 
 // The wave's copy of its macro's partial stencils lives in LDS, so that the
 // per-lane lookups of boundary lanes are LDS reads and never wait on the
@@ -313,7 +324,8 @@ __device__ __forceinline__ void tile2d(const int x0, const int y0, const MacroDe
   const int lane = threadIdx.x & (kWave - 1);
   const int N = M.N;
   const int x = x0 - 1 + lane;
-  const int y1 = min(y0 + kTileH2, N - x0 + 1);  // rows y0 .. y1-1 (x0 + y <= N)
+  constexpr int kH = Tile2<T>::H, kU = Tile2<T>::U;
+  const int y1 = min(y0 + kH, N - x0 + 1);  // rows y0 .. y1-1 (x0 + y <= N)
   X += M.base;
   Y += M.base;
   if (MODE != kApply) B += M.base;
@@ -332,9 +344,9 @@ __device__ __forceinline__ void tile2d(const int x0, const int y0, const MacroDe
   T am = ldrow(X, N, y0 - 1, y1, xc);
   T a0 = ldrow(X, N, y0, y1, xc);
   T am_r = dn1(am), a0_l = up1(a0), a0_r = dn1(a0);
-  T q[kU2], qb[kU2];
+  T q[kU], qb[kU];
 #pragma unroll
-  for (int k = 0; k < kU2; ++k) {
+  for (int k = 0; k < kU; ++k) {
     q[k] = ldrow(X, N, y0 + 1 + k, y1, xc);                    // x rows y0+1 ..
     if (MODE != kApply) qb[k] = ldrow(B, N, y0 + k, y1 - 1, xc);  // b rows = output rows
   }
@@ -344,12 +356,12 @@ __device__ __forceinline__ void tile2d(const int x0, const int y0, const MacroDe
   // the arithmetic (a uniform branch).
   const int nrows = y1 - y0;
 #pragma unroll
-  for (int k = 0; k < kTileH2; ++k) {
+  for (int k = 0; k < kH; ++k) {
     const int yy = y0 + k;
-    const T ap = q[k % kU2];
-    const T bv = MODE != kApply ? qb[k % kU2] : T(0);
-    q[k % kU2] = ldrow(X, N, y0 + 1 + k + kU2, y1, xc);
-    if (MODE != kApply) qb[k % kU2] = ldrow(B, N, y0 + k + kU2, y1 - 1, xc);
+    const T ap = q[k % kU];
+    const T bv = MODE != kApply ? qb[k % kU] : T(0);
+    q[k % kU] = ldrow(X, N, y0 + 1 + k + kU, y1, xc);
+    if (MODE != kApply) qb[k % kU] = ldrow(B, N, y0 + k + kU, y1 - 1, xc);
     if (k >= nrows) continue;
     const T ap_l = up1(ap), ap_r = dn1(ap);
     const T v[7] = {am, am_r, a0_l, a0, a0_r, ap_l, ap};
@@ -497,9 +509,9 @@ __device__ __forceinline__ int resolve(const Launch<A>& L, int g, A& a) {
 
 // Whether a wave tile has output points on its macro's boundary (x = 0,
 // y = 0, z = 0 or the far face x + y + z = N).
-template <int DIM, int PZ>
+template <typename T, int DIM, int PZ>
 __device__ __forceinline__ bool tile_on_boundary(const Tile& t, int N) {
-  if (DIM == 2) return t.x0 == 0 || t.y0 == 0 || t.x0 + t.y0 + (kTileW - 1) + (kTileH2 - 1) >= N;
+  if (DIM == 2) return t.x0 == 0 || t.y0 == 0 || t.x0 + t.y0 + (kTileW - 1) + (Tile2<T>::H - 1) >= N;
   return t.x0 == 0 || t.y0 == 0 || t.z == 0 || t.x0 + t.y0 + t.z + (kTileW - 1) + (kPenR - 1) + (PZ - 1) >= N;
 }
 
@@ -526,13 +538,13 @@ __global__ __launch_bounds__(kWG) void stencil_kernel(const Launch<StencilArgs<T
     if (m0 >= 0) {
       const int N0 = a.md[m0].N;
 #pragma unroll
-      for (int k = 0; k < kWavesPerWG; ++k) need = need || tile_on_boundary<DIM, PZ>(a.tiles[n * kWavesPerWG + k], N0);
+      for (int k = 0; k < kWavesPerWG; ++k) need = need || tile_on_boundary<T, DIM, PZ>(a.tiles[n * kWavesPerWG + k], N0);
     }
     if (need) {
       load_wtab<T>(a.md[m0], wtab[0], 0, kWG);
       __syncthreads();
     }
-  } else if (t.macro >= 0 && tile_on_boundary<DIM, PZ>(t, a.md[t.macro].N)) {
+  } else if (t.macro >= 0 && tile_on_boundary<T, DIM, PZ>(t, a.md[t.macro].N)) {
     load_wtab<T>(a.md[t.macro], wtab[wv], wv * kWave, kWave);
     __builtin_amdgcn_wave_barrier();
   }
@@ -795,7 +807,7 @@ void batch_dispatch(const BatchOp& op, const char* table, hipStream_t s) {
 
 }  // namespace
 
-int64_t stencil_partials(const Level& L) { return L.n_partials(); }
+int64_t stencil_partials(const Level& L, int dtype) { return L.n_partials(dtype); }
 
 int launch_stencil(const mf_mesh* m, const Level& L, int dtype, int mode, const void* x, void* y, const void* b,
                    double omega, double* part, hipStream_t s) {
