@@ -102,10 +102,21 @@ def cpu_baseline(W, budget_s=20.0):
     reps = max(10, min(400, int(budget_s / max(per, 1e-6))))
     t, used = om.time_spmv(nthreads, 0, reps)
     med = float(sorted(t)[len(t) // 2])
+    t1, _ = om.time_spmv(1, 3, 10)
+    med1 = float(sorted(t1)[len(t1) // 2])
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": om.n / med / 1e9, "unit": "GDoF/s", "cores": int(used), "kind": "oracle",
             "sample": f"same affine triangle at level {L} ({om.n} DoFs): CSR row loop y = A x, median of {reps} "
                       f"reps on {used} threads; CSR assembly ({t_build:.1f} s) excluded",
-            "csr_GBps": (om.n * 8 * 2 + om.csr().nnz * 16 + (om.n + 1) * 8) / med / 1e9}
+            "csr_GBps": (om.n * 8 * 2 + om.csr().nnz * 16 + (om.n + 1) * 8) / med / 1e9,
+            "single_thread_GDoF_s": om.n / med1 / 1e9, "cpu_model": model, "nproc": os.cpu_count()}
 
 
 def traffic_for(kernel_hash):
@@ -147,10 +158,14 @@ def solve_bench(P, torch, W, L=8, repeats=10):
             rc, it, rel, sec = P.vcycle_solve(m, L, b, x, ws, mode=mode, rtol=1e-10)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / repeats
-        uh = np.prod(np.sin(np.pi * xyz), axis=1) * (np.pi ** 2 * h ** 2 / 4) / np.sin(np.pi * h / 2) ** 2
-        err = float(np.abs(x.cpu().numpy() - uh).max())
+        us = np.prod(np.sin(np.pi * xyz), axis=1)
+        uh = us * (np.pi ** 2 * h ** 2 / 4) / np.sin(np.pi * h / 2) ** 2
+        xs = x.cpu().numpy()
+        err = float(np.abs(xs - uh).max())
+        err_cont = float(np.abs(xs - us).max())
         out[names[mode]] = {"mode": mode, "status": rc, "iters": it, "rel_res": rel, "ms_per_solve": dt * 1e3,
-                            "solves_per_s": 1.0 / dt, "max_err_vs_discrete_solution": err}
+                            "solves_per_s": 1.0 / dt, "max_err_vs_discrete_solution": err,
+                            "max_err_vs_continuous_solution": err_cont}
         del ws
     P.destroy_macro_mesh(m)
     return out
@@ -198,7 +213,7 @@ def serve_bench(torch, variant, n, util=0.75, budget_gib=200.0, calib_n=40):
         st = serving.latency_stats(infos, t0, t1)
         st.update({"rejected": rejected, "status_counts": {str(k): v for k, v in status.items()},
                    "offered_req_per_s": rate, "achieved_req_per_s": len(infos) / max(t1 - t0, 1e-9),
-                   "gpu_busy_frac": srv.busy_s / max(t1 - t0, 1e-9),
+                   "busy_frac_per_lane": [b / max(t1 - t0, 1e-9) for b in srv.lane_busy_s],
                    "mean_iters": float(np.mean([i["iters"] for i in infos])) if infos else None})
         out[name] = st
     if "p50_ms" in out["plain_fp64_fifo"] and "p50_ms" in out["batched_mixed"]:
@@ -260,10 +275,15 @@ def main():
         extra["apply2d_l14_fp32"] = {"GDoF_s": r32["unique"] / (r32["launch_avg_ms"] * 1e-3) / 1e9,
                                      "GB_s": 8 * r32["unique"] / (r32["launch_avg_ms"] * 1e-3) / 1e9,
                                      "launch_avg_ms": r32["launch_avg_ms"]}
-        for L3 in (8, 9):
-            log(f"apply 3D cube level {L3} fp64")
-            r3 = bench_apply(P, torch, *W.kuhn_cube(), L3, torch.float64, args.steps, args.warmup, 4)
-            extra[f"apply3d_cube_l{L3}_fp64"] = {
+        log("apply 2D reference triangle level 8 fp64 (L2-resident)")
+        r1 = bench_apply(P, torch, *W.unit_triangle(), 8, torch.float64, args.steps, args.warmup, 1)
+        extra["apply2d_unit_l8_fp64"] = {"us_per_apply": r1["launch_avg_ms"] * 1e3, "dofs": r1["unique"]}
+        for L3, order in ((8, "canonical"), (8, "random"), (9, "canonical")):
+            log(f"apply 3D cube level {L3} fp64 ({order} vertex order)")
+            mesh = W.kuhn_cube() if order == "canonical" else W.kuhn_cube("random", 5)
+            r3 = bench_apply(P, torch, *mesh, L3, torch.float64, args.steps, args.warmup, 4)
+            key = f"apply3d_cube_l{L3}_fp64" + ("" if order == "canonical" else "_random_order")
+            extra[key] = {
                 "GDoF_s": r3["unique"] / (r3["launch_avg_ms"] * 1e-3) / 1e9,
                 "GB_s_storage": 16 * r3["storage"] / (r3["launch_avg_ms"] * 1e-3) / 1e9,
                 "launch_avg_ms": r3["launch_avg_ms"], "storage": r3["storage"], "unique": r3["unique"]}

@@ -83,7 +83,8 @@ class Server:
     """
 
     def __init__(self, budget_bytes: int, batched: bool = True, max_batch: int = 64, max_iter: int = 100,
-                 keep_solutions: bool = True, mode: int | None = None):
+                 keep_solutions: bool = True, mode: int | None = None, lanes: int | None = None,
+                 split_dofs: int = 4_000_000):
         import torch
         self.torch = torch
         self.budget = int(budget_bytes)
@@ -98,8 +99,14 @@ class Server:
         self.rejected = 0
         self.completed = 0
         self.busy_s = 0.0
+        # batched: requests below split_dofs storage DoFs and the larger ones
+        # step in separate batches on separate streams (lanes), so that a
+        # small request's iterations are not gated by a large member's
+        self.lanes = (2 if batched else 1) if lanes is None else max(1, lanes)
+        self.split_dofs = split_dofs
         self._pending: collections.deque[Request] = collections.deque()
-        self._ready: collections.deque[Request] = collections.deque()
+        self._ready = [collections.deque() for _ in range(self.lanes)]
+        self.lane_busy_s = [0.0] * self.lanes
         self._inflight = 0  # prepared or being solved
         self._cv = threading.Condition()
         self._stop = False
@@ -108,9 +115,11 @@ class Server:
         self._next = 0
         self._live: dict[int, Request] = {}  # submitted, not finished
         self._prep = threading.Thread(target=self._prep_loop, name="mf-prep", daemon=True)
-        self._work = threading.Thread(target=self._work_loop, name="mf-work", daemon=True)
+        self._work = [threading.Thread(target=self._work_loop, args=(k,), name=f"mf-work{k}", daemon=True)
+                      for k in range(self.lanes)]
         self._prep.start()
-        self._work.start()
+        for t in self._work:
+            t.start()
 
     # ------------------------------------------------------------ client side
     def submit(self, dim, coords, cells, level, rhs_seed, tol=1e-8, t_arrival=None) -> cf.Future:
@@ -142,7 +151,8 @@ class Server:
             self._cv.notify_all()
         if wait:
             self._prep.join()
-            self._work.join()
+            for t in self._work:
+                t.join()
         if self._error is not None:
             raise self._error
 
@@ -174,8 +184,9 @@ class Server:
                     B.mesh_fill_random(r.mesh, r.level, r.rhs_seed, r.b, stream)
                     B.mesh_set_dirichlet(r.mesh, r.level, None, r.b, stream)
                 stream.synchronize()
+                lane = 0 if (self.lanes == 1 or s < self.split_dofs) else self.lanes - 1
                 with self._cv:
-                    self._ready.append(r)
+                    self._ready[lane].append(r)
                     self._cv.notify_all()
         except BaseException as e:  # surfaced by close()
             self._fail(e)
@@ -189,7 +200,8 @@ class Server:
             live = list(self._live.values())
             self._live.clear()
             self._pending.clear()
-            self._ready.clear()
+            for q in self._ready:
+                q.clear()
             self._cv.notify_all()
         for r in live:
             if not r.future.done():
@@ -216,58 +228,65 @@ class Server:
             self._cv.notify_all()
         r.future.set_result((x, info))
 
-    def _work_loop(self):
+    def _work_loop(self, lane: int):
         torch = self.torch
         torch.cuda.set_device(self._dev)
         stream = torch.cuda.Stream()
         try:
             if self.batched:
-                self._batched_loop(stream)
+                self._batched_loop(stream, lane)
             else:
-                self._plain_loop(stream)
+                self._plain_loop(stream, lane)
         except BaseException as e:
             self._fail(e)
 
-    def _take_ready(self, block: bool):
+    def _done_all(self) -> bool:
+        return self._stop and not self._pending and self._inflight == 0
+
+    def _take_ready(self, lane: int, block: bool):
         with self._cv:
-            while block and not self._ready and not (self._stop and not self._pending and self._inflight == 0):
+            while block and not self._ready[lane] and not self._done_all():
                 self._cv.wait(0.05)
-            out = list(self._ready)
-            self._ready.clear()
+            out = list(self._ready[lane])
+            self._ready[lane].clear()
             return out
 
-    def _plain_loop(self, stream):
+    def _plain_loop(self, stream, lane: int):
         while True:
-            rs = self._take_ready(block=True)
+            rs = self._take_ready(lane, block=True)
             if not rs:
                 with self._cv:
-                    if self._stop and not self._pending and self._inflight == 0:
+                    if self._done_all():
                         return
                 continue
-            for i, r in enumerate(rs):
+            for r in rs:
                 t0 = time.perf_counter()
                 rc, it, rel, _ = B.vcycle_solve(r.mesh, r.level, r.b, r.x, r.ws, mode=self.mode, rtol=r.tol,
                                                 max_iter=self.max_iter, stream=stream)
-                self.busy_s += time.perf_counter() - t0
+                dt = time.perf_counter() - t0
+                self.busy_s += dt
+                self.lane_busy_s[lane] += dt
                 self._finish(r, rc, it, rel)
 
-    def _batched_loop(self, stream):
+    def _batched_loop(self, stream, lane: int):
         batch = B.batch_create(self.max_batch, mode=self.mode, max_iter=self.max_iter)
         members: dict[int, Request] = {}
         try:
             while True:
-                rs = self._take_ready(block=not members)
+                rs = self._take_ready(lane, block=not members)
                 for r in rs:
                     B.batch_add(batch, r.mesh, r.level, r.b, r.x, r.ws, r.tol, r.rid)
                     members[r.rid] = r
                 if not members:
                     with self._cv:
-                        if self._stop and not self._pending and self._inflight == 0:
+                        if self._done_all():
                             return
                     continue
                 t0 = time.perf_counter()
                 done = B.batch_step(batch, stream)
-                self.busy_s += time.perf_counter() - t0
+                dt = time.perf_counter() - t0
+                self.busy_s += dt
+                self.lane_busy_s[lane] += dt
                 for tag, st, it, rel, _ in done:
                     self._finish(members.pop(tag), st, it, rel)
         finally:

@@ -29,15 +29,18 @@ def _alone(r, mode, max_iter):
     return rc, it, x
 
 
-@pytest.mark.parametrize("batched", [True, False])
-def test_server_equals_solving_alone(batched):
+@pytest.mark.parametrize("batched,split", [(True, 4_000_000), (True, 3000), (False, 0)])
+def test_server_equals_solving_alone(batched, split):
+    """split: requests of at least that many storage DoFs step in the second lane."""
     reqs = loadgen.requests(n=14, rate=500.0, levels2=(2, 6), levels3=(1, 4), kmax=7, tol=1e-8, seed_arrival=3,
                             seed_req=4)
-    srv = serving.Server(4 << 30, batched=batched, max_batch=6, max_iter=200)
+    srv = serving.Server(4 << 30, batched=batched, max_batch=6, max_iter=200, split_dofs=split)
     futs, _, _ = loadgen.replay(srv, reqs)
     out = [f.result(timeout=100) for f in futs]
     srv.close()
     assert srv.completed == len(reqs) and srv.rejected == 0
+    if batched and split == 3000:
+        assert min(srv.lane_busy_s) > 0.0  # both lanes served requests
     for r, (x, info) in zip(reqs, out):
         rc, it, xa = _alone(r, srv.mode, 200)
         assert (info["status"], info["iters"]) == (rc, it)
