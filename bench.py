@@ -171,12 +171,15 @@ def solve_bench(P, torch, W, L=8, repeats=10):
     return out
 
 
-def serve_bench(torch, variant, n, util=0.75, budget_gib=200.0, calib_n=40):
+def serve_bench(torch, variant, n, util=0.75, budget_gib=None, calib_n=40, servers="both"):
     """Serving workload: Poisson arrivals of solve requests (2D strips of 1-64
     triangles, 3D rows of 1-64 Kuhn tets, seeded affine maps, tol 1e-8).
     capped: 3D levels 5-8 and an arrival rate set to `util` of the plain
     server's measured capacity; full: levels 5-11 at 200 requests/s."""
     from paper_2305_15116_amd import loadgen, serving
+    # device memory the server may commit to requests (HBM is 288 GB; the
+    # allocator's cache and the meshes' metadata need the rest)
+    budget_gib = budget_gib or (200.0 if variant == "capped" else 160.0)
     budget = int(budget_gib * 2 ** 30)
     levels3 = (5, 8) if variant == "capped" else (5, 11)
     out = {"variant": variant, "n": n, "budget_GiB": budget_gib}
@@ -194,11 +197,19 @@ def serve_bench(torch, variant, n, util=0.75, budget_gib=200.0, calib_n=40):
         rate = 200.0
     out["rate_req_per_s"] = rate
     reqs = loadgen.requests(n=n, rate=rate, levels3=levels3)
+    which = {"both": (False, True), "plain": (False,), "batched": (True,)}[servers]
     for name, batched in (("plain_fp64_fifo", False), ("batched_mixed", True)):
+        if batched not in which:
+            continue
         log(f"serving {variant}: {name}, {n} requests at {rate:.1f}/s")
         srv = serving.Server(budget, batched=batched, keep_solutions=False)
         out.setdefault("solver_modes", {})[name] = srv.mode
         futs, t0, _ = loadgen.replay(srv, reqs)
+        import concurrent.futures as cf
+        pending = set(futs)
+        while pending:  # progress lines while the backlog drains
+            _, pending = cf.wait(pending, timeout=20.0)
+            log(f"  {len(futs) - len(pending)}/{len(futs)} requests finished")
         infos, rejected, status = [], 0, {}
         for f in futs:
             try:
@@ -211,7 +222,7 @@ def serve_bench(torch, variant, n, util=0.75, budget_gib=200.0, calib_n=40):
         srv.close()
         t1 = max([i["t_done"] for i in infos], default=t0)
         st = serving.latency_stats(infos, t0, t1)
-        st.update({"rejected": rejected, "status_counts": {str(k): v for k, v in status.items()},
+        st.update({"rejected": srv.rejected, "failed_to_prepare": srv.failed, "status_counts": {str(k): v for k, v in status.items()},
                    "offered_req_per_s": rate, "achieved_req_per_s": len(infos) / max(t1 - t0, 1e-9),
                    "busy_frac_per_lane": [b / max(t1 - t0, 1e-9) for b in srv.lane_busy_s],
                    "mean_iters": float(np.mean([i["iters"] for i in infos])) if infos else None})
@@ -233,6 +244,8 @@ def main():
     ap.add_argument("--serve", choices=["none", "capped", "full"], default="capped",
                     help="serving workload in the extras (full: 2000 requests at 200/s, levels 5-11)")
     ap.add_argument("--serve-n", type=int, default=None, help="requests of the serving run")
+    ap.add_argument("--serve-servers", choices=["both", "plain", "batched"], default="both",
+                    help="which servers the serving run measures")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device copy of 1 GiB (counter calibration for profiles)")
     args = ap.parse_args()
@@ -294,9 +307,10 @@ def main():
         if not args.skip_solve:
             log("solve: mixed vs fp64, cube level 8")
             extra["solve_cube_l8"] = solve_bench(P, torch, W)
-        if args.serve != "none":
-            n = args.serve_n or (200 if args.serve == "capped" else 2000)
-            extra[f"serving_{args.serve}"] = serve_bench(torch, args.serve, n)
+
+    if args.serve != "none":
+        n = args.serve_n or (200 if args.serve == "capped" else 2000)
+        extra[f"serving_{args.serve}"] = serve_bench(torch, args.serve, n, servers=args.serve_servers)
     cpu = None
     if not args.skip_cpu:
         log("cpu baseline (oracle)")

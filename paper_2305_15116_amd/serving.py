@@ -96,7 +96,8 @@ class Server:
         self.max_iter = max_iter
         self.keep = keep_solutions
         self.used = 0
-        self.rejected = 0
+        self.rejected = 0   # footprint above the budget
+        self.failed = 0     # could not be prepared (device memory)
         self.completed = 0
         self.busy_s = 0.0
         # batched: requests below split_dofs storage DoFs and the larger ones
@@ -174,16 +175,24 @@ class Server:
                     self.used += r.footprint
                     self._inflight += 1
                 r.t_admit = time.perf_counter()
-                r.mesh = B.create_macro_mesh(r.coords, r.cells, r.level)
-                s, _ = B.mesh_num_dofs(r.mesh, r.level)
-                with torch.cuda.stream(stream):
-                    r.b = torch.empty(s, dtype=torch.float64, device="cuda")
-                    r.x = torch.zeros(s, dtype=torch.float64, device="cuda")
-                    r.ws = torch.empty(B.mesh_workspace_bytes(r.mesh, r.level, self.mode), dtype=torch.uint8,
-                                       device="cuda")
-                    B.mesh_fill_random(r.mesh, r.level, r.rhs_seed, r.b, stream)
-                    B.mesh_set_dirichlet(r.mesh, r.level, None, r.b, stream)
-                stream.synchronize()
+                err = None
+                for attempt in range(2):
+                    try:
+                        s = self._prepare(r, stream)
+                        err = None
+                        break
+                    except (B.MFError, torch.OutOfMemoryError, RuntimeError) as e:
+                        # device memory beyond the accounting (allocator caching,
+                        # fragmentation): release the cache and retry once
+                        err = e
+                        r.b = r.x = r.ws = None
+                        if r.mesh is not None:
+                            r.mesh.close()
+                            r.mesh = None
+                        torch.cuda.empty_cache()
+                if err is not None:
+                    self._drop(r, err)
+                    continue
                 lane = 0 if (self.lanes == 1 or s < self.split_dofs) else self.lanes - 1
                 with self._cv:
                     self._ready[lane].append(r)
@@ -191,8 +200,38 @@ class Server:
         except BaseException as e:  # surfaced by close()
             self._fail(e)
 
+    def _prepare(self, r: Request, stream) -> int:
+        """Mesh set-up on the host, vectors on the device; returns storage DoFs."""
+        torch = self.torch
+        r.mesh = B.create_macro_mesh(r.coords, r.cells, r.level)
+        s, _ = B.mesh_num_dofs(r.mesh, r.level)
+        with torch.cuda.stream(stream):
+            r.b = torch.empty(s, dtype=torch.float64, device="cuda")
+            r.x = torch.zeros(s, dtype=torch.float64, device="cuda")
+            r.ws = torch.empty(B.mesh_workspace_bytes(r.mesh, r.level, self.mode), dtype=torch.uint8,
+                               device="cuda")
+            B.mesh_fill_random(r.mesh, r.level, r.rhs_seed, r.b, stream)
+            B.mesh_set_dirichlet(r.mesh, r.level, None, r.b, stream)
+        stream.synchronize()
+        return s
+
+    def _drop(self, r: Request, e: BaseException):
+        """A request that could not be prepared fails alone (counted in `failed`)."""
+        with self._cv:
+            self.used -= r.footprint
+            self._inflight -= 1
+            self.failed += 1
+            self._live.pop(r.rid, None)
+            self._cv.notify_all()
+        if isinstance(e, B.MFError):
+            r.future.set_exception(e)
+        else:
+            r.future.set_exception(B.MFError(B.MF_ENOMEM, f"preparing the request failed: {e!r}"))
+
     def _fail(self, e: BaseException):
         """A thread died: every unfinished request fails with the error."""
+        import sys
+        print(f"serving: thread failed: {e!r}", file=sys.stderr, flush=True)
         with self._cv:
             if self._error is None:
                 self._error = e
@@ -241,7 +280,7 @@ class Server:
             self._fail(e)
 
     def _done_all(self) -> bool:
-        return self._stop and not self._pending and self._inflight == 0
+        return (self._stop and not self._pending and self._inflight == 0) or self._error is not None
 
     def _take_ready(self, lane: int, block: bool):
         with self._cv:
