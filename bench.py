@@ -227,7 +227,8 @@ def serve_bench(torch, variant, n, util=0.75, budget_gib=None, calib_n=40, serve
                    "busy_frac_per_lane": [b / max(t1 - t0, 1e-9) for b in srv.lane_busy_s],
                    "mean_iters": float(np.mean([i["iters"] for i in infos])) if infos else None})
         out[name] = st
-    if "p50_ms" in out["plain_fp64_fifo"] and "p50_ms" in out["batched_mixed"]:
+        log(f"serving {variant} {name}: " + json.dumps(st))
+    if "p50_ms" in out.get("plain_fp64_fifo", {}) and "p50_ms" in out.get("batched_mixed", {}):
         out["p50_speedup"] = out["plain_fp64_fifo"]["p50_ms"] / out["batched_mixed"]["p50_ms"]
         out["p99_speedup"] = out["plain_fp64_fifo"]["p99_ms"] / out["batched_mixed"]["p99_ms"]
     return out
