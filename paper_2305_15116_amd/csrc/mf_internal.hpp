@@ -42,7 +42,10 @@ constexpr int kPenZ = MF_PEN_Z;
 // slice loads, and with few waves in flight its length sets the kernel time.
 constexpr int kPenZSmall = 4;
 constexpr int kPenZSmallBelowN = 128;  // pencil depth kPenZSmall when N < this
-constexpr int kWavesPerWG = 4;
+#ifndef MF_WAVES_PER_WG
+#define MF_WAVES_PER_WG 4
+#endif
+constexpr int kWavesPerWG = MF_WAVES_PER_WG;
 constexpr int kWG = kWave * kWavesPerWG;
 constexpr int kIfaceWG = 256;  // groups per interface workgroup
 constexpr int kXCD = 8;        // MI355X: 8 accelerator complex dies, workgroups dealt round-robin

@@ -568,8 +568,14 @@ __global__ __launch_bounds__(kWG) void stencil_kernel(const Launch<StencilArgs<T
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-      a.part[n] = (s_ss[0] + s_ss[1]) + (s_ss[2] + s_ss[3]);
-      a.part[a.np + n] = fmax(fmax(s_mx[0], s_mx[1]), fmax(s_mx[2], s_mx[3]));
+      double p = s_ss[0], q = s_mx[0];
+#pragma unroll
+      for (int k = 1; k < kWavesPerWG; ++k) {
+        p += s_ss[k];
+        q = fmax(q, s_mx[k]);
+      }
+      a.part[n] = p;
+      a.part[a.np + n] = q;
     }
   }
 }
