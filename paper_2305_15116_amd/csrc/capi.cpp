@@ -191,7 +191,7 @@ int mesh_dof_index(const mf_mesh* m, int level, int64_t n, const int64_t* ml, in
     const int64_t c = ml[i * d1], x = ml[i * d1 + 1], y = ml[i * d1 + 2], z = m->dim == 3 ? ml[i * d1 + 3] : 0;
     if (c < 0 || c >= m->nc || x < 0 || y < 0 || z < 0 || x + y + z > L.N)
       return set_error(MF_EINVAL, "point " + std::to_string(i) + " outside its macro");
-    index[i] = L.base[c] + (m->dim == 2 ? idx2(L.N, x, y) : idx3(L.N, x, y, z));
+    index[i] = L.base[c] + (m->dim == 2 ? idx2(L.N, (int)x, (int)y) : idx3(L.N, (int)x, (int)y, (int)z));
   }
   return MF_OK;
 }

@@ -89,12 +89,19 @@ MF_HD int64_t tet_count(int64_t n) { return n * (n + 1) * (n + 2) / 6; }
 MF_HD int64_t tri_count(int64_t n) { return n * (n + 1) / 2; }
 // storage points of one macro
 MF_HD int64_t macro_points(int dim, int64_t N) { return dim == 2 ? tri_count(N + 1) : tet_count(N + 1); }
-// first index of slice z (3D)
-MF_HD int64_t slice_base(int64_t N, int64_t z) { return tet_count(N + 1) - tet_count(N + 1 - z); }
-// start of row y in a triangle of side M
-MF_HD int64_t row_start(int64_t M, int64_t y) { return y * (M + 2) - y * (y + 1) / 2; }
-MF_HD int64_t idx2(int64_t N, int64_t x, int64_t y) { return row_start(N, y) + x; }
-MF_HD int64_t idx3(int64_t N, int64_t x, int64_t y, int64_t z) { return slice_base(N, z) + row_start(N - z, y) + x; }
+// Tet(n) for 0 <= n < 2^16 with 32-bit divisions by constants only (device
+// index math runs on the scalar unit, where 64-bit division is a long
+// sequence): n(n+1)/2 is an integer, and one of n, n+1, n+2 is a multiple of 3.
+MF_HD int64_t tet_count_small(int n) {
+  const uint32_t t = (uint32_t)n * (uint32_t)(n + 1) / 2u;
+  return (n % 3 == 1) ? (int64_t)t * (int64_t)((n + 2) / 3) : (int64_t)(t / 3u) * (int64_t)(n + 2);
+}
+// first index of slice z (3D, N <= 2048)
+MF_HD int64_t slice_base(int N, int z) { return tet_count_small(N + 1) - tet_count_small(N + 1 - z); }
+// start of row y in a triangle of side M (M < 2^15: fits 32 bits)
+MF_HD int32_t row_start(int M, int y) { return y * (M + 2) - ((y * (y + 1)) >> 1); }
+MF_HD int64_t idx2(int N, int x, int y) { return (int64_t)row_start(N, y) + x; }
+MF_HD int64_t idx3(int N, int x, int y, int z) { return slice_base(N, z) + row_start(N - z, y) + x; }
 
 // ---------------------------------------------------------------- micro-elements
 // Index-space vertex offsets of the micro-element types (Bey's refinement in

@@ -145,21 +145,24 @@ __device__ __forceinline__ void restrict_segment(const TransferArgs<T>& a, const
   const int Nc = C.N, Nf = F.N;
   const int x = sg.x0 + (threadIdx.x & (kWave - 1));
   const int y = sg.y0, z = DIM == 3 ? sg.z : 0;
-  if (x + y + z > Nc) return;
+  const bool live = x + y + z <= Nc;
+  // branch-free: every lane takes all offsets; fine points outside the macro
+  // read the centre instead and contribute nothing
   T acc = T(0);
 #pragma unroll
   for (int s = 0; s < ST.n; ++s) {
     const int fx = 2 * x + ST.off[s][0], fy = 2 * y + ST.off[s][1], fz = DIM == 3 ? 2 * z + ST.off[s][2] : 0;
-    if (fx < 0 || fy < 0 || fz < 0 || fx + fy + fz > Nf) continue;
+    const bool in = live && fx >= 0 && fy >= 0 && fz >= 0 && fx + fy + fz <= Nf;
     const int mask = support_mask(DIM, Nf, fx, fy, fz);
     const bool owned = mask == full || ((F.own_mask >> mask) & 1);
     const bool dir = mask != full && ((F.dir_mask >> mask) & 1);
-    if (owned && !dir) {
-      const T r = a.src[F.base + lidx<DIM>(Nf, fx, fy, fz)];
-      acc += (s == ST.centre) ? r : T(0.5) * r;
-    }
+    const bool use = in && owned && !dir;
+    const int64_t i = in ? lidx<DIM>(Nf, fx, fy, fz) : 0;
+    const T r = a.src[F.base + i];
+    const T w = s == ST.centre ? T(1) : T(0.5);
+    acc += use ? w * r : T(0);
   }
-  a.dst[C.base + lidx<DIM>(Nc, x, y, z)] = acc;
+  if (live) a.dst[C.base + lidx<DIM>(Nc, x, y, z)] = acc;
 }
 
 template <typename T, int DIM>
@@ -186,26 +189,23 @@ __device__ __forceinline__ void prolong_segment(const TransferArgs<T>& a, const 
   const int Nc = C.N, Nf = F.N;
   const int x = sg.x0 + (threadIdx.x & (kWave - 1));
   const int y = sg.y0, z = DIM == 3 ? sg.z : 0;
-  if (x + y + z > Nf) return;
+  const bool live = x + y + z <= Nf;
   const int mask = support_mask(DIM, Nf, x, y, z);
-  if (mask != full && ((F.dir_mask >> mask) & 1)) return;
-  const int px = x & 1, py = y & 1, pz = z & 1;
-  T e;
-  if (!(px | py | pz)) {
-    e = a.src[C.base + lidx<DIM>(Nc, x >> 1, y >> 1, z >> 1)];
-  } else {
-    // direction s of the bisected coarse edge: equal to the parity pattern,
-    // except that of two or three odd coordinates the middle ones flip sign
-    int sx = px, sy = py, sz = pz;
-    if (px && py && !pz) sy = -1;        // (1,1,0) -> e1 - e2
-    else if (px && !py && pz) sz = -1;   // (1,0,1) -> e1 - e3
-    else if (!px && py && pz) sz = -1;   // (0,1,1) -> e2 - e3
-    else if (px && py && pz) sy = -1;    // (1,1,1) -> e1 - e2 + e3
-    const T u = a.src[C.base + lidx<DIM>(Nc, (x - sx) >> 1, (y - sy) >> 1, (z - sz) >> 1)];
-    const T v = a.src[C.base + lidx<DIM>(Nc, (x + sx) >> 1, (y + sy) >> 1, (z + sz) >> 1)];
-    e = T(0.5) * (u + v);
-  }
-  a.dst[F.base + lidx<DIM>(Nf, x, y, z)] += e;
+  const bool dir = mask != full && ((F.dir_mask >> mask) & 1);
+  // direction s of the coarse micro-edge the point bisects: the parity
+  // pattern, with the middle odd coordinate negated for two or three odd
+  // coordinates ((1,1,0) -> e1 - e2, (1,0,1) -> e1 - e3, (0,1,1) -> e2 - e3,
+  // (1,1,1) -> e1 - e2 + e3); even points have s = 0 and take the coarse
+  // value itself (the two reads coincide)
+  // (lanes past the macro's far face read the coarse point (0, 0, 0))
+  const int xl = live ? x : 0, yl = live ? y : 0, zl = live ? z : 0;
+  const int px = xl & 1, py = yl & 1, pz = zl & 1;
+  const int sx = px;
+  const int sy = (px && py) ? -1 : py;
+  const int sz = (pz && (px ^ py)) ? -1 : pz;
+  const T u = a.src[C.base + lidx<DIM>(Nc, (xl - sx) >> 1, (yl - sy) >> 1, (zl - sz) >> 1)];
+  const T v = a.src[C.base + lidx<DIM>(Nc, (xl + sx) >> 1, (yl + sy) >> 1, (zl + sz) >> 1)];
+  if (live && !dir) a.dst[F.base + lidx<DIM>(Nf, x, y, z)] += T(0.5) * (u + v);
 }
 
 // x_f += P e_c (each wave walks several segments of fine points).
