@@ -48,21 +48,23 @@ struct Prec<float> {
 
 // Cross-lane neighbours through DPP wavefront shifts (a VALU op, no LDS
 // traffic): wave_shr:1 gives each lane the value of lane - 1, wave_shl:1 that
-// of lane + 1 (lanes 0 and 63 receive their own value; they are halo lanes).
+// of lane + 1.  Lanes 0 and 63, which have no source, receive 0 (bound_ctrl);
+// they are halo lanes whose results are never stored.  Without an `old`
+// operand the move needs no register copy of its source.
 constexpr int kDppWaveShl1 = 0x130;
 constexpr int kDppWaveShr1 = 0x138;
 
 template <int CTRL>
 __device__ __forceinline__ float dpp_move(float v) {
   const int i = __builtin_bit_cast(int, v);
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(i, i, CTRL, 0xF, 0xF, false));
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(i, CTRL, 0xF, 0xF, true));
 }
 template <int CTRL>
 __device__ __forceinline__ double dpp_move(double v) {
   const long long l = __builtin_bit_cast(long long, v);
   const int lo = (int)(l & 0xffffffffLL), hi = (int)(l >> 32);
-  const int rlo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
-  const int rhi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
+  const int rlo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, true);
+  const int rhi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, true);
   return __builtin_bit_cast(double, ((long long)rhi << 32) | (long long)(unsigned)rlo);
 }
 template <typename T>
@@ -376,6 +378,78 @@ __device__ __forceinline__ void tile2d(const int x0, const int y0, const MacroDe
   }
 }
 
+// Interior 2D tile: every row y0-1 .. y0+H exists and holds every column
+// x0-1 .. x0+62, and no output point lies on the macro's boundary.  Row
+// addresses are then advanced incrementally (row y+1 starts N+1-y entries
+// after row y) with no clamping, and every output lane takes the interior
+// finish.
+template <typename T>
+__device__ __forceinline__ bool tile2d_inner(int x0, int y0, int N) {
+  return x0 >= 1 && y0 >= 1 && x0 + y0 + kTileW + Tile2<T>::H <= N;
+}
+
+template <typename T, int MODE>
+__device__ __forceinline__ void tile2d_fast(const int x0, const int y0, const MacroDev& M, const T* __restrict__ X,
+                                            T* __restrict__ Y, const T* __restrict__ B, T omega, double& ss,
+                                            double& mx) {
+  constexpr int kH = Tile2<T>::H, kU = Tile2<T>::U;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int N = M.N;
+  const bool out_lane = (unsigned)(lane - 1) < (unsigned)kTileW;
+  const unsigned col = (unsigned)(x0 - 1 + lane) * (unsigned)sizeof(T);
+  T wi[7];
+#pragma unroll
+  for (int o = 0; o < 7; ++o) wi[o] = Prec<T>::w(M, full_mask(2), o);
+  // cursors: byte address of the next row and the byte step to the one after
+  const char* px = (const char*)(X + M.base + rs32(N, y0 - 1));
+  int sx = (N + 2 - y0) * (int)sizeof(T);
+  char* py = (char*)(Y + M.base + rs32(N, y0));
+  int sy = (N + 1 - y0) * (int)sizeof(T);
+  const char* pb = MODE != kApply ? (const char*)(B + M.base + rs32(N, y0)) : nullptr;
+  int sb = sy;
+  auto ldx = [&]() -> T {
+    const T v = *(const T*)(px + col);
+    px += sx;
+    sx -= (int)sizeof(T);
+    return v;
+  };
+  auto ldb = [&]() -> T {
+    const T v = *(const T*)(pb + col);
+    pb += sb;
+    sb -= (int)sizeof(T);
+    return v;
+  };
+  T am = ldx();
+  T a0 = ldx();
+  T am_r = dn1(am), a0_l = up1(a0), a0_r = dn1(a0);
+  T q[kU], qb[kU];
+#pragma unroll
+  for (int k = 0; k < kU; ++k) {
+    q[k] = ldx();
+    if (MODE != kApply) qb[k] = ldb();
+  }
+#pragma unroll
+  for (int k = 0; k < kH; ++k) {
+    const T ap = q[k % kU];
+    const T bv = MODE != kApply ? qb[k % kU] : T(0);
+    if (k + 1 + kU <= kH) q[k % kU] = ldx();
+    if (MODE != kApply && k + kU < kH) qb[k % kU] = ldb();
+    const T ap_l = up1(ap), ap_r = dn1(ap);
+    const T v[7] = {am, am_r, a0_l, a0, a0_r, ap_l, ap};
+    T acc = wi[0] * v[0];
+#pragma unroll
+    for (int o = 1; o < 7; ++o) acc = fma(wi[o], v[o], acc);
+    if (out_lane) finish_interior<T, MODE>(M, acc, a0, bv, omega, (T*)(py + col), ss, mx);
+    py += sy;
+    sy -= (int)sizeof(T);
+    am = a0;
+    am_r = a0_r;
+    a0 = ap;
+    a0_l = ap_l;
+    a0_r = ap_r;
+  }
+}
+
 // ------------------------------------------------------------------ 3D pencil
 // Slice z of a tetrahedral macro is a triangle of side S = N - z.  Output row
 // y of slice z reads rows y, y+1 of slice z-1, rows y-1..y+1 of slice z and
@@ -552,7 +626,9 @@ __global__ __launch_bounds__(kWG) void stencil_kernel(const Launch<StencilArgs<T
   if (t.macro >= 0) {
     const MacroDev& M = a.md[t.macro];
     WTab<T> W = wtab[same ? 0 : wv];
-    if (DIM == 2)
+    if (DIM == 2 && tile2d_inner<T>(t.x0, t.y0, M.N))
+      tile2d_fast<T, MODE>(t.x0, t.y0, M, a.X, a.Y, a.B, a.omega, ss, mx);
+    else if (DIM == 2)
       tile2d<T, MODE>(t.x0, t.y0, M, W, a.X, a.Y, a.B, a.omega, ss, mx);
     else
       pencil3d<T, MODE, PZ>(t.x0, t.y0, t.z, M, W, a.X, a.Y, a.B, a.omega, ss, mx);
