@@ -1,4 +1,4 @@
-// Oracle for the P1 matrix-free operator — TEST INFRASTRUCTURE ONLY.
+// Oracle for the P1 (and 2D P2) matrix-free operators — TEST INFRASTRUCTURE ONLY.
 //
 // Plain, slow, obviously correct CPU FP64 code.  Only the test-suite, the
 // smoke check and the CPU-baseline leg of the benchmark may load this library;
@@ -31,7 +31,8 @@
 //  5. Dirichlet boundary: DoFs on macro facets with exactly one adjacent cell
 //     get identity rows; other rows keep their boundary columns.
 //  6. y = A x as a row loop.
-// Also: the same rows evaluated for a sample of points without a global
+// Also: the 2D P2 stiffness matrix (vertex and edge DoFs) by the same steps
+// with quadratic elements, the same rows evaluated for a sample of points without a global
 // build (for full-size checks), the P1 prolongation between two levels, the
 // lumped mass vector, and the keyed SplitMix64 input generator.
 
@@ -476,6 +477,101 @@ int64_t or_assemble(or_mesh* m, int dirichlet) {
     m->rowptr[u + 1] = (int64_t)m->cols.size();
   }
   m->csr_dirichlet = dirichlet ? 1 : 0;
+  return (int64_t)m->cols.size();
+}
+
+// ---- P2 (quadratic) elements in 2D: the paper's own discretisation, with a
+// DoF at every vertex and every edge midpoint of the micro-triangles (section
+// comparing matrix-free and sparse storage: vertex and edge DoF counts, the
+// 19-entry vertex stencil and the 9-entry edge stencils).  The micro-triangles
+// of refinement level l have their vertices and edge midpoints exactly at the
+// lattice points of level l+1, so the or_mesh built at level l+1 supplies the
+// keys, unique ids and Dirichlet flags of the P2 DoFs.
+//
+// Element matrix K_ij = integral over T of grad phi_i . grad phi_j, local order
+// (v0, v1, v2, m01, m12, m02), with phi = lambda_i (2 lambda_i - 1) at vertex i
+// and 4 lambda_a lambda_b at the midpoint of edge ab.  Each integrand is a
+// polynomial of degree 2, so the rule with weight |T|/3 at the three edge
+// midpoints integrates it exactly.
+namespace {
+bool p2_element(const double E[3][3], double K[6][6]) {
+  const double det = E[0][0] * E[1][1] - E[0][1] * E[1][0];
+  if (det == 0.0) return false;
+  // grad lambda_1, grad lambda_2 = rows of E^{-1}; grad lambda_0 = -(sum)
+  double G[3][2];
+  G[1][0] = E[1][1] / det;  G[1][1] = -E[0][1] / det;
+  G[2][0] = -E[1][0] / det; G[2][1] = E[0][0] / det;
+  G[0][0] = -(G[1][0] + G[2][0]);
+  G[0][1] = -(G[1][1] + G[2][1]);
+  const double area = std::fabs(det) / 2.0;
+  const int ea[3] = {0, 1, 0}, eb[3] = {1, 2, 2};  // edges m01, m12, m02
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) K[i][j] = 0.0;
+  for (int q = 0; q < 3; ++q) {
+    double lam[3] = {0.0, 0.0, 0.0};  // quadrature point: midpoint of edge q
+    lam[ea[q]] = 0.5;
+    lam[eb[q]] = 0.5;
+    double g[6][2];
+    for (int i = 0; i < 3; ++i)
+      for (int r = 0; r < 2; ++r) g[i][r] = (4.0 * lam[i] - 1.0) * G[i][r];
+    for (int e = 0; e < 3; ++e)
+      for (int r = 0; r < 2; ++r) g[3 + e][r] = 4.0 * (lam[eb[e]] * G[ea[e]][r] + lam[ea[e]] * G[eb[e]][r]);
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) K[i][j] += (area / 3.0) * (g[i][0] * g[j][0] + g[i][1] * g[j][1]);
+  }
+  return true;
+}
+}  // namespace
+
+// P2 stiffness matrix of level m->level - 1 on the DoFs of `m` (built at that
+// level + 1), assembled like or_assemble: COO -> CSR with duplicates summed,
+// identity rows at Dirichlet DoFs when dirichlet != 0.  Returns nnz, or -1.
+int64_t or_assemble_p2(or_mesh* m, int dirichlet) {
+  if (m->dim != 2 || m->level < 1) { g_err = "P2 needs a 2D mesh built at level >= 1"; return -1; }
+  const int64_t Nc = m->N / 2;  // intervals of the P2 level per macro edge
+  std::vector<std::vector<std::pair<int64_t, double>>> rows(m->nu);
+  bool bad = false;
+  for (int64_t c = 0; c < m->nc; ++c) {
+    const int64_t* cv = &m->cells[c * 3];
+    const int64_t* L = &m->lat[c * m->lat_stride];
+    const int64_t lo[3] = {0, 0, 0}, hi[3] = {Nc, Nc, 0};
+    for_each_element(2, Nc, lo, hi, [&](int64_t (*v)[3]) {
+      // the six P2 points on the level-(l+1) lattice: doubled vertices, then midpoints
+      int64_t f[6][3];
+      for (int k = 0; k < 3; ++k)
+        for (int r = 0; r < 3; ++r) f[k][r] = 2 * v[k][r];
+      const int ea[3] = {0, 1, 0}, eb[3] = {1, 2, 2};
+      for (int e = 0; e < 3; ++e)
+        for (int r = 0; r < 3; ++r) f[3 + e][r] = v[ea[e]][r] + v[eb[e]][r];
+      double E[3][3], K[6][6];
+      edge_matrix(2, m->coords.data(), cv, m->N, f, E);
+      if (!p2_element(E, K)) { bad = true; return; }
+      int64_t ids[6];
+      for (int k = 0; k < 6; ++k) ids[k] = L[lat_index(2, m->N, f[k])];
+      for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) rows[ids[i]].push_back({ids[j], K[i][j]});
+    });
+  }
+  if (bad) { g_err = "degenerate micro-element"; return -1; }
+  m->rowptr.assign(m->nu + 1, 0);
+  m->cols.clear();
+  m->vals.clear();
+  for (int64_t u = 0; u < m->nu; ++u) {
+    if (dirichlet && m->bnd[u]) {
+      m->cols.push_back(u);
+      m->vals.push_back(1.0);
+    } else {
+      auto& row = rows[u];
+      std::stable_sort(row.begin(), row.end(),
+                       [](const std::pair<int64_t, double>& a, const std::pair<int64_t, double>& b) { return a.first < b.first; });
+      for (size_t k = 0; k < row.size(); ++k) {
+        if (k > 0 && row[k].first == row[k - 1].first) m->vals.back() += row[k].second;
+        else { m->cols.push_back(row[k].first); m->vals.push_back(row[k].second); }
+      }
+    }
+    m->rowptr[u + 1] = (int64_t)m->cols.size();
+  }
+  m->csr_dirichlet = dirichlet ? 3 : 2;
   return (int64_t)m->cols.size();
 }
 

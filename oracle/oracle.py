@@ -1,7 +1,7 @@
 """Python face of the oracle (test infrastructure only).
 
 Wraps oracle/liboracle.so (plain C++ FP64 CSR assembly and SpMV, written from
-the definition of the P1 stiffness matrix) and adds the two solves the tests
+the definition of the P1 stiffness matrix, and of the 2D P2 one) and adds the two solves the tests
 need: a dense solve at tiny levels and conjugate gradients on the interior
 block, both textbook routines on the oracle's own CSR.
 """
@@ -46,6 +46,8 @@ def lib():
         L.or_elements.argtypes = [C.c_void_p, C.c_void_p]
         L.or_assemble.restype = C.c_int64
         L.or_assemble.argtypes = [C.c_void_p, C.c_int]
+        L.or_assemble_p2.restype = C.c_int64
+        L.or_assemble_p2.argtypes = [C.c_void_p, C.c_int]
         L.or_get_csr.argtypes = [C.c_void_p, i64p, i64p, f64p]
         L.or_spmv.argtypes = [C.c_void_p, f64p, f64p]
         L.or_apply_elementwise.restype = C.c_int
@@ -135,6 +137,35 @@ class OracleMesh:
             self._native_state = bool(dirichlet)
             self._native_nnz = int(nnz)
         return self._native_nnz
+
+    def csr_p2(self, dirichlet: bool = True) -> sp.csr_matrix:
+        """P2 stiffness matrix of level self.level - 1 (2D) on this mesh's DoFs:
+        the vertices and edge midpoints of that level's micro-triangles are the
+        lattice points of this level."""
+        key = ("p2", bool(dirichlet))
+        if key not in self._csr:
+            nnz = lib().or_assemble_p2(self._h, int(dirichlet))
+            if nnz < 0:
+                raise ValueError(_err())
+            self._native_state = key
+            rp = np.empty(self.n + 1, np.int64)
+            ci = np.empty(nnz, np.int64)
+            va = np.empty(nnz)
+            lib().or_get_csr(self._h, rp, ci, va)
+            self._csr[key] = sp.csr_matrix((va, ci, rp), shape=(self.n, self.n))
+        return self._csr[key]
+
+    def spmv_p2(self, x, dirichlet: bool = True):
+        """y = A x for the P2 matrix of csr_p2, with the oracle's own CSR row loop."""
+        key = ("p2", bool(dirichlet))
+        if self._native_state != key:
+            if lib().or_assemble_p2(self._h, int(dirichlet)) < 0:
+                raise ValueError(_err())
+            self._native_state = key
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.empty(self.n)
+        lib().or_spmv(self._h, x, y)
+        return y
 
     def csr(self, dirichlet: bool = True) -> sp.csr_matrix:
         key = bool(dirichlet)
