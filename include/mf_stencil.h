@@ -128,6 +128,17 @@ int mesh_set_dirichlet(const mf_mesh* mesh, int level, int dtype, const void* b_
  * overwritten and must not alias x.  Asynchronous. */
 int apply_stencil(const mf_mesh* mesh, int level, int dtype, const void* x_dev, void* y_dev, void* stream);
 
+/* y = A x for the P2 (quadratic) Laplace operator of a 2D mesh refined
+ * `level` times: DoFs at the vertices and edge midpoints of the
+ * micro-triangles (the paper's P2 discretisation, with its vertex-to-vertex,
+ * edge-to-vertex, vertex-to-edge and edge-to-edge kernels of the
+ * Performance Modeling section fused into one pass).  These DoFs are the
+ * lattice points of level + 1, so x and y use the storage layout of level + 1
+ * (mesh_num_dofs / mesh_dof_keys at level + 1); needs level + 1 <= max_level.
+ * Rows: the assembled P2 stiffness matrix; Dirichlet rows give y = x.  y is
+ * overwritten and must not alias x.  MF_ENOTSUP for a 3D mesh.  Asynchronous. */
+int apply_p2(const mf_mesh* mesh, int level, int dtype, const void* x_dev, void* y_dev, void* stream);
+
 /* `sweeps` weighted-Jacobi sweeps x <- x + omega D^-1 (b - A x) (the
  * multigrid smoother the paper names as a code-generated operation,
  * Performance Modeling section).  D is the assembled diagonal.  Dirichlet DoFs

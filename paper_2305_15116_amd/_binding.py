@@ -23,7 +23,7 @@ MF_FLAG_DIRICHLET, MF_FLAG_HOST_ONLY = 1, 2
 #: every symbol include/mf_stencil.h declares
 EXPORTS = ["mf_last_error", "create_macro_mesh", "destroy_macro_mesh", "mesh_info", "mesh_num_dofs",
            "mesh_dof_keys", "mesh_dof_index", "mesh_stencil", "mesh_workspace_bytes", "mesh_fill_random",
-           "mesh_set_dirichlet", "apply_stencil", "smooth", "residual", "restrict_residual", "prolong_add",
+           "mesh_set_dirichlet", "apply_stencil", "apply_p2", "smooth", "residual", "restrict_residual", "prolong_add",
            "vcycle_solve", "batch_create", "batch_destroy", "batch_size", "batch_add", "batch_step"]
 
 
@@ -197,6 +197,13 @@ def mesh_set_dirichlet(mesh: Mesh, level: int, b, y, stream=None):
 def apply_stencil(mesh: Mesh, level: int, x, y, stream=None):
     _check(lib().apply_stencil(mesh, level, _dtype_code(x), C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
                                _stream(stream)))
+
+
+def apply_p2(mesh: Mesh, level: int, x, y, stream=None):
+    """y = A x for the 2D P2 operator of `level`; x and y have the storage
+    layout of level + 1 (its lattice holds the vertex and edge-midpoint DoFs)."""
+    _check(lib().apply_p2(mesh, level, _dtype_code(x), C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                          _stream(stream)))
 
 
 def smooth(mesh: Mesh, level: int, omega: float, sweeps: int, b, x, tmp, stream=None):

@@ -241,6 +241,19 @@ int apply_stencil(const mf_mesh* m, int level, int dtype, const void* x, void* y
   return launch_stencil(m, L, dtype, kApply, x, y, nullptr, 0.0, nullptr, s);
 }
 
+int apply_p2(const mf_mesh* m, int level, int dtype, const void* x, void* y, void* stream) {
+  if (!m) return set_error(MF_EINVAL, "NULL mesh");
+  if (m->dim != 2) return set_error(MF_ENOTSUP, "the P2 operator is built for 2D meshes");
+  if (level < 0 || level + 1 > m->max_level)
+    return set_error(MF_EINVAL, "P2 level must satisfy 0 <= level < max_level (it uses the lattice of level + 1)");
+  int rc = check_mesh(m, level + 1, true);
+  if (!rc) rc = check_dtype(dtype);
+  if (rc) return rc;
+  if (!x || !y) return set_error(MF_EINVAL, "NULL vector");
+  if (x == y) return set_error(MF_EINVAL, "y must not alias x");
+  return launch_p2_apply(m, level, dtype, x, y, (hipStream_t)stream);
+}
+
 int smooth(const mf_mesh* m, int level, int dtype, double omega, int sweeps, const void* b, void* x, void* tmp,
            void* stream) {
   int rc = check_mesh(m, level, true);

@@ -26,6 +26,15 @@ int launch_stencil(const mf_mesh* m, const Level& L, int dtype, int mode, const 
 int launch_iface(const mf_mesh* m, const Level& L, int dtype, int mode, const void* x, void* y, const void* b,
                  hipStream_t s);
 
+// 2D only: y at every shared, non-Dirichlet DoF of L = the sum of its copies'
+// partial rows, written to every copy (the exchange step of an apply).
+int launch_exchange_apply(const Level& L, int dtype, void* y, hipStream_t s);
+
+// P2 operator of a 2D mesh at `level` (vector layout: storage of level + 1):
+// interior rows by fused wave tiles, macro-boundary rows from the element
+// matrices (identity at Dirichlet DoFs), then the exchange.
+int launch_p2_apply(const mf_mesh* m, int level, int dtype, const void* x, void* y, hipStream_t s);
+
 // result[0] = sum part[0..np), result[1] = max part[np..2np), fixed order.
 int launch_reduce(const double* part, int64_t np, double* result, hipStream_t s);
 

@@ -1,6 +1,8 @@
 // Host-side macro mesh and per-level metadata.
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <algorithm>
 #include <array>
 #include <cstdint>
@@ -10,6 +12,7 @@
 
 #include "mf_internal.hpp"
 #include "mf_stencil.h"
+#include "p2.hpp"
 
 namespace mf {
 
@@ -36,6 +39,7 @@ struct LevelDev {
   int32_t* cptr = nullptr;     // copies of each coarse unknown
   int64_t* cidx = nullptr;
   uint32_t* own_bits = nullptr;
+  Tile* p2_tiles = nullptr;  // P2 walk tiles over this level's lattice (2D, level >= 1)
 };
 
 struct Level {
@@ -68,6 +72,7 @@ struct Level {
   // blocks of the linear (grid-stride) vector kernels with partials
   int64_t lin_blocks() const { return std::min<int64_t>(2048, std::max<int64_t>(1, (storage + 1023) / 1024)); }
   std::vector<uint32_t> own_bits;  // bit i: storage DoF i is its unique DoF's owner copy
+  std::vector<Tile> p2_tiles;      // P2 of level - 1 on this lattice (2D): wave tiles, natural order, padded
   // coarse direct solve
   int64_t ncoarse = 0;          // unknowns (unique non-Dirichlet DoFs); 0 = not prepared
   std::vector<double> cinv;     // ncoarse^2 inverse of the interior block
@@ -101,6 +106,8 @@ struct mf_mesh {
   std::vector<uint16_t> own_mask, dir_mask, shared_mask;  // per macro
   std::vector<mf::Prim> prims;                            // macro-boundary primitives, sorted by vertex ids
   std::vector<mf::Level> levels;
+  std::vector<mf::P2Macro> p2;       // 2D: P2 constants per macro (level-independent)
+  mf::P2Macro* p2_dev = nullptr;
   std::mutex norm_mutex;  // serialises residual() calls that return a norm
 };
 
@@ -110,11 +117,25 @@ namespace mf {
 int set_error(int code, const std::string& msg);
 const char* last_error();
 
+// Device copy of a host vector (nullptr for an empty one).
+template <class T>
+int dev_upload(T** dst, const std::vector<T>& src) {
+  *dst = nullptr;
+  if (src.empty()) return MF_OK;
+  hipError_t e = hipMalloc((void**)dst, sizeof(T) * src.size());
+  if (e != hipSuccess) return set_error(e == hipErrorOutOfMemory ? MF_ENOMEM : MF_EDEVICE, hipGetErrorString(e));
+  e = hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return set_error(MF_EDEVICE, hipGetErrorString(e));
+  return MF_OK;
+}
+
 // Host set-up (mesh_setup.cpp).
 int build_mesh(mf_mesh* m);
 int build_coarse_solver(mf_mesh* m, int level);
 void free_device(mf_mesh* m);
 int upload_level(mf_mesh* m, Level& L);
+// 2D P2 constants and tiles (p2_setup.cpp); called by build_mesh after the levels.
+int build_p2(mf_mesh* m);
 
 // Keys of every storage point of a level, (dim+1) pairs each.
 void storage_keys(const mf_mesh* m, int level, int64_t* vids, int32_t* wts);

@@ -165,17 +165,6 @@ void parallel_for(size_t n, int64_t work, F&& fn) {
   for (auto& t : th) t.join();
 }
 
-template <class T>
-int dev_upload(T** dst, const std::vector<T>& src) {
-  *dst = nullptr;
-  if (src.empty()) return MF_OK;
-  hipError_t e = hipMalloc((void**)dst, sizeof(T) * src.size());
-  if (e != hipSuccess) return set_error(e == hipErrorOutOfMemory ? MF_ENOMEM : MF_EDEVICE, hipGetErrorString(e));
-  e = hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return set_error(MF_EDEVICE, hipGetErrorString(e));
-  return MF_OK;
-}
-
 }  // namespace
 
 // ---------------------------------------------------------------- topology
@@ -675,7 +664,7 @@ int build_mesh(mf_mesh* m) {
     for (int l = 0; l <= m->max_level; ++l)
       if ((rc = upload_level(m, m->levels[l]))) return rc;
   }
-  return MF_OK;
+  return build_p2(m);
 }
 
 void free_device(mf_mesh* m) {
@@ -683,12 +672,14 @@ void free_device(mf_mesh* m) {
     LevelDev& D = L.dev;
     void* ptrs[] = {D.md, D.tiles, D.tiles_f32, D.segs, D.grp_ptr, D.copies, D.grp_flag, D.xgrp_ptr, D.xcopies, D.xgrp_invdiag,
                     D.xgrp_invdiagf,
-                    D.part, D.result, D.cinv, D.cinvf, D.cfirst, D.cptr, D.cidx, D.own_bits};
+                    D.part, D.result, D.cinv, D.cinvf, D.cfirst, D.cptr, D.cidx, D.own_bits, D.p2_tiles};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
     if (D.host_result) (void)hipHostFree(D.host_result);
     D = LevelDev{};
   }
+  if (m->p2_dev) (void)hipFree(m->p2_dev);
+  m->p2_dev = nullptr;
 }
 
 void storage_keys(const mf_mesh* m, int level, int64_t* vids, int32_t* wts) {

@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include "launch.hpp"
+#include "wave.hpp"
 
 namespace mf {
 
@@ -46,31 +47,9 @@ struct Prec<float> {
   static __device__ __forceinline__ float ginv(const double*, const float* f, int g) { return f[g]; }
 };
 
-// Cross-lane neighbours through DPP wavefront shifts (a VALU op, no LDS
-// traffic): wave_shr:1 gives each lane the value of lane - 1, wave_shl:1 that
-// of lane + 1.  Lanes 0 and 63, which have no source, receive 0 (bound_ctrl);
-// they are halo lanes whose results are never stored.  Without an `old`
-// operand the move needs no register copy of its source.
-constexpr int kDppWaveShl1 = 0x130;
-constexpr int kDppWaveShr1 = 0x138;
-
-template <int CTRL>
-__device__ __forceinline__ float dpp_move(float v) {
-  const int i = __builtin_bit_cast(int, v);
-  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(i, CTRL, 0xF, 0xF, true));
-}
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double v) {
-  const long long l = __builtin_bit_cast(long long, v);
-  const int lo = (int)(l & 0xffffffffLL), hi = (int)(l >> 32);
-  const int rlo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, true);
-  const int rhi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, true);
-  return __builtin_bit_cast(double, ((long long)rhi << 32) | (long long)(unsigned)rlo);
-}
-template <typename T>
-__device__ __forceinline__ T up1(T v) { return dpp_move<kDppWaveShr1>(v); }  // value of lane - 1
-template <typename T>
-__device__ __forceinline__ T dn1(T v) { return dpp_move<kDppWaveShl1>(v); }  // value of lane + 1
+using wave::dn1;
+using wave::up1;
+using wave::xcd_wg;
 
 // Ordinary (write-back) stores: partial lines at wave boundaries merge in L2.
 template <typename T>
@@ -85,17 +64,6 @@ __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
   return v;
-}
-
-// Maps this block to its natural workgroup index so that each of the 8 XCDs
-// (which receive blocks round-robin) works through one contiguous chunk of
-// the natural order: neighbouring strips then share that XCD's L2.
-__device__ __forceinline__ int xcd_wg(int nwg) {
-  const int chunk = (nwg + kXCD - 1) / kXCD;
-  const int k = blockIdx.x % kXCD, j = blockIdx.x / kXCD;
-  if (j >= chunk) return -1;
-  const int n = k * chunk + j;
-  return n < nwg ? n : -1;
 }
 
 #ifndef MF_RING_U2
@@ -780,7 +748,7 @@ int check_launch() {
   return MF_OK;
 }
 
-inline int stencil_grid(int nwg) { return kXCD * ((nwg + kXCD - 1) / kXCD); }
+inline int stencil_grid(int nwg) { return wave::xcd_grid(nwg); }
 
 template <class A>
 Launch<A> single(const A& a, int nwg) {
@@ -899,6 +867,18 @@ int launch_stencil(const mf_mesh* m, const Level& L, int dtype, int mode, const 
 int launch_iface(const mf_mesh* m, const Level& L, int dtype, int mode, const void* x, void* y, const void* b,
                  hipStream_t s) {
   return launch(m, L, dtype, mode, x, y, b, 0.0, nullptr, s);
+}
+
+int launch_exchange_apply(const Level& L, int dtype, void* y, hipStream_t s) {
+  const int nblk = exchange_blocks(L);
+  if (nblk == 0) return MF_OK;
+  if (dtype == MF_F64)
+    hipLaunchKernelGGL((exchange_kernel<double, 2, kApply>), dim3(nblk), dim3(kIfaceWG), 0, s,
+                       single(exchange_args<double>(L, nullptr, y, nullptr, 0.0, nullptr), nblk));
+  else
+    hipLaunchKernelGGL((exchange_kernel<float, 2, kApply>), dim3(nblk), dim3(kIfaceWG), 0, s,
+                       single(exchange_args<float>(L, nullptr, y, nullptr, 0.0, nullptr), nblk));
+  return check_launch();
 }
 
 int launch_reduce(const double* part, int64_t np, double* result, hipStream_t s) {
