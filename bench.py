@@ -11,7 +11,9 @@ job.  roofline: algorithmic bytes (16 B/DoF: x read once, y written once)
 per launch / average launch time (HIP events on the launch stream), against
 the 8 TB/s HBM3E peak.  cpu_baseline: the oracle's CSR row loop on the host
 cores for a bounded sample.  extra: the FP32 apply, the 3D 6-tet cube apply,
-a device copy for reference, and the mixed-precision vs FP64 V-cycle solve.
+the fused 2D P2 apply (vertex and edge DoFs, level 13: the same 134,242,305
+DoFs), a device copy for reference, and the mixed-precision vs FP64 V-cycle
+solve.
 """
 from __future__ import annotations
 
@@ -37,21 +39,25 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def bench_apply(P, torch, co, ce, L, dtype, steps, warmup, seed):
-    m = P.create_macro_mesh(co, ce, L)
-    s, u = P.mesh_num_dofs(m, L)
+def bench_apply(P, torch, co, ce, L, dtype, steps, warmup, seed, p2=False):
+    """Times the P1 apply of level L, or (p2=True) the P2 apply of level L,
+    whose vectors have the layout of level L + 1."""
+    Lv = L + 1 if p2 else L
+    m = P.create_macro_mesh(co, ce, Lv)
+    s, u = P.mesh_num_dofs(m, Lv)
     x = torch.empty(s, dtype=dtype, device="cuda")
-    P.mesh_fill_random(m, L, seed, x)
+    P.mesh_fill_random(m, Lv, seed, x)
     y = torch.empty_like(x)
     stream = torch.cuda.current_stream()
+    apply = P.apply_p2 if p2 else P.apply_stencil
     for _ in range(warmup):
-        P.apply_stencil(m, L, x, y, stream)
+        apply(m, L, x, y, stream)
     torch.cuda.synchronize()
     # whole timed region: `steps` back-to-back applies
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(steps):
-        P.apply_stencil(m, L, x, y, stream)
+        apply(m, L, x, y, stream)
     e1.record(stream)
     torch.cuda.synchronize()
     total_ms = e0.elapsed_time(e1)
@@ -59,7 +65,7 @@ def bench_apply(P, torch, co, ce, L, dtype, steps, warmup, seed):
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     for a, b in ev:
         a.record(stream)
-        P.apply_stencil(m, L, x, y, stream)
+        apply(m, L, x, y, stream)
         b.record(stream)
     torch.cuda.synchronize()
     per = sorted(a.elapsed_time(b) for a, b in ev)
@@ -301,6 +307,15 @@ def main():
                 "GDoF_s": r3["unique"] / (r3["launch_avg_ms"] * 1e-3) / 1e9,
                 "GB_s_storage": 16 * r3["storage"] / (r3["launch_avg_ms"] * 1e-3) / 1e9,
                 "launch_avg_ms": r3["launch_avg_ms"], "storage": r3["storage"], "unique": r3["unique"]}
+        for dt, bpd in ((torch.float64, 16), (torch.float32, 8)):
+            tag = "fp64" if dt == torch.float64 else "fp32"
+            log(f"P2 apply 2D level 13 {tag} (vertex and edge DoFs, one fused pass)")
+            rp = bench_apply(P, torch, co, ce, 13, dt, args.steps, args.warmup, 3, p2=True)
+            extra[f"apply2d_p2_l13_{tag}"] = {
+                "GDoF_s": rp["unique"] / (rp["launch_avg_ms"] * 1e-3) / 1e9,
+                "GB_s": bpd * rp["unique"] / (rp["launch_avg_ms"] * 1e-3) / 1e9,
+                "launch_avg_ms": rp["launch_avg_ms"], "dofs": rp["unique"],
+                "algorithmic_B_per_dof": bpd, "paper_four_kernel_B_per_dof": 2 * bpd}
         log("device copy reference")
         cbw = copy_bandwidth(torch)
         extra["device_copy_GBps"] = cbw

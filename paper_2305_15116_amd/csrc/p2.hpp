@@ -44,7 +44,10 @@ struct P2Macro {
 // Wave tiles of the P2 walk: each lane owns two adjacent fine columns
 // (an even one and the next), lanes 1..62 produce output, so a tile spans
 // 124 fine columns and kP2H fine rows.
-constexpr int kP2H = 8;
+#ifndef MF_P2_H
+#define MF_P2_H 8
+#endif
+constexpr int kP2H = MF_P2_H;
 constexpr int kP2TileW = 2 * kTileW;
 static_assert(kP2H % 2 == 0, "P2 tiles start on even rows");
 

@@ -54,6 +54,20 @@ __device__ __forceinline__ Row<T> row_of(T a, T b) {
   return Row<T>{a, b, up1(a), dn1(a), up1(b)};
 }
 
+// Two adjacent entries, loaded or stored as one 16-byte (FP64) access; rows
+// start at any entry, so only the element alignment is assumed (gfx950
+// global memory accesses need dword alignment only).
+template <typename T>
+struct Pair;
+template <>
+struct Pair<double> {
+  typedef double V __attribute__((ext_vector_type(2), aligned(8)));
+};
+template <>
+struct Pair<float> {
+  typedef float V __attribute__((ext_vector_type(2), aligned(4)));
+};
+
 // Columns xa and xa + 1 of row r of the fine triangle (side M), with the row
 // clamped to [0, last] and the columns into the row: a valid point for every
 // lane (clamped values only feed halo lanes and points that are not stored).
@@ -62,8 +76,17 @@ __device__ __forceinline__ void ld_pair(const T* __restrict__ X, int M, int r, i
   const int rr = min(max(r, 0), last);
   const int S = M - rr;
   const T* row = X + row_start(M, rr);
-  a = row[min(max(xa, 0), S)];
-  b = row[min(max(xa + 1, 0), S)];
+  if (S >= 1) {
+    // one 2-element load at a start kept inside the row; a lane past the row
+    // end takes the last element, a lane before its start the first
+    const int st = min(max(xa, 0), S - 1);
+    const typename Pair<T>::V v = *(const typename Pair<T>::V*)(row + st);
+    a = xa >= S ? v.y : v.x;
+    b = xa < 0 ? v.x : v.y;
+  } else {
+    a = row[0];
+    b = a;
+  }
 }
 
 constexpr int kP2U = 4;  // rows loaded ahead
@@ -140,8 +163,17 @@ __device__ __forceinline__ void p2_tile(int x0, int y0, const MacroDev& Md, cons
       }
       // interior points only: X >= 1, Y >= 1, X + Y <= M - 1
       T* yrow = Y + row_start(M, yy);
-      if (lane_out && yy >= 1 && xa >= 1 && xa + yy <= M - 1) yrow[xa] = oa;
-      if (lane_out && yy >= 1 && xa + 1 + yy <= M - 1) yrow[xa + 1] = ob;
+      const bool va = lane_out && yy >= 1 && xa >= 1 && xa + yy <= M - 1;
+      const bool vb = lane_out && yy >= 1 && xa + 1 + yy <= M - 1;
+      if (va && vb) {
+        typename Pair<T>::V v;
+        v.x = oa;
+        v.y = ob;
+        *(typename Pair<T>::V*)(yrow + xa) = v;
+      } else {
+        if (va) yrow[xa] = oa;
+        if (vb) yrow[xa + 1] = ob;
+      }
     }
     r0 = r1;
     r1 = r2;
