@@ -32,7 +32,7 @@
 //     get identity rows; other rows keep their boundary columns.
 //  6. y = A x as a row loop.
 // Also: the 2D P2 stiffness matrix (vertex and edge DoFs) by the same steps
-// with quadratic elements, the same rows evaluated for a sample of points without a global
+// with quadratic elements, the variable-coefficient P1 matrix, the same rows evaluated for a sample of points without a global
 // build (for full-size checks), the P1 prolongation between two levels, the
 // lumped mass vector, and the keyed SplitMix64 input generator.
 
@@ -477,6 +477,54 @@ int64_t or_assemble(or_mesh* m, int dirichlet) {
     m->rowptr[u + 1] = (int64_t)m->cols.size();
   }
   m->csr_dirichlet = dirichlet ? 1 : 0;
+  return (int64_t)m->cols.size();
+}
+
+// ---- Variable coefficient (the survey's "on-the-fly stencils" row; the
+// paper notes that varying weights can be computed on the fly, trading
+// memory traffic for computation, comparison of matrix-free and sparse
+// storage).  Operator: a(u, v) = integral of k grad u . grad v with k the P1
+// interpolant of nodal values; grad u . grad v is constant on a P1 element,
+// so the element matrix is exactly (mean of k over the element's vertices)
+// times the constant-coefficient element matrix.  k is given per unique DoF.
+// Same assembly as or_assemble otherwise.  Returns nnz, or -1.
+int64_t or_assemble_varcoef(or_mesh* m, int dirichlet, const double* k) {
+  const int d1 = m->dim + 1;
+  std::vector<std::vector<std::pair<int64_t, double>>> rows(m->nu);
+  bool bad = false;
+  for (int64_t c = 0; c < m->nc; ++c) {
+    for_each_cell_element(m, c, [&](int64_t (*v)[3]) {
+      double E[3][3], K[MAXV][MAXV], vol;
+      int64_t ids[MAXV];
+      element_data(m, c, v, E, ids);
+      if (!element_stiffness(m->dim, E, K, &vol)) { bad = true; return; }
+      double kt = 0.0;
+      for (int i = 0; i < d1; ++i) kt += k[ids[i]];
+      kt /= (double)d1;
+      for (int i = 0; i < d1; ++i)
+        for (int j = 0; j < d1; ++j) rows[ids[i]].push_back({ids[j], kt * K[i][j]});
+    });
+  }
+  if (bad) { g_err = "degenerate micro-element"; return -1; }
+  m->rowptr.assign(m->nu + 1, 0);
+  m->cols.clear();
+  m->vals.clear();
+  for (int64_t u = 0; u < m->nu; ++u) {
+    if (dirichlet && m->bnd[u]) {
+      m->cols.push_back(u);
+      m->vals.push_back(1.0);
+    } else {
+      auto& row = rows[u];
+      std::stable_sort(row.begin(), row.end(),
+                       [](const std::pair<int64_t, double>& a, const std::pair<int64_t, double>& b) { return a.first < b.first; });
+      for (size_t q = 0; q < row.size(); ++q) {
+        if (q > 0 && row[q].first == row[q - 1].first) m->vals.back() += row[q].second;
+        else { m->cols.push_back(row[q].first); m->vals.push_back(row[q].second); }
+      }
+    }
+    m->rowptr[u + 1] = (int64_t)m->cols.size();
+  }
+  m->csr_dirichlet = dirichlet ? 5 : 4;
   return (int64_t)m->cols.size();
 }
 

@@ -46,6 +46,8 @@ def lib():
         L.or_elements.argtypes = [C.c_void_p, C.c_void_p]
         L.or_assemble.restype = C.c_int64
         L.or_assemble.argtypes = [C.c_void_p, C.c_int]
+        L.or_assemble_varcoef.restype = C.c_int64
+        L.or_assemble_varcoef.argtypes = [C.c_void_p, C.c_int, f64p]
         L.or_assemble_p2.restype = C.c_int64
         L.or_assemble_p2.argtypes = [C.c_void_p, C.c_int]
         L.or_get_csr.argtypes = [C.c_void_p, i64p, i64p, f64p]
@@ -137,6 +139,20 @@ class OracleMesh:
             self._native_state = bool(dirichlet)
             self._native_nnz = int(nnz)
         return self._native_nnz
+
+    def csr_varcoef(self, k, dirichlet: bool = True) -> sp.csr_matrix:
+        """Stiffness matrix of -div(k grad u), k the P1 interpolant of the
+        nodal values k (one per unique DoF)."""
+        k = np.ascontiguousarray(k, dtype=np.float64)
+        nnz = lib().or_assemble_varcoef(self._h, int(dirichlet), k)
+        if nnz < 0:
+            raise ValueError(_err())
+        self._native_state = ("varcoef", None)
+        rp = np.empty(self.n + 1, np.int64)
+        ci = np.empty(nnz, np.int64)
+        va = np.empty(nnz)
+        lib().or_get_csr(self._h, rp, ci, va)
+        return sp.csr_matrix((va, ci, rp), shape=(self.n, self.n))
 
     def csr_p2(self, dirichlet: bool = True) -> sp.csr_matrix:
         """P2 stiffness matrix of level self.level - 1 (2D) on this mesh's DoFs:
