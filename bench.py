@@ -12,8 +12,9 @@ per launch / average launch time (HIP events on the launch stream), against
 the 8 TB/s HBM3E peak.  cpu_baseline: the oracle's CSR row loop on the host
 cores for a bounded sample.  extra: the FP32 apply, the 3D 6-tet cube apply,
 the fused 2D P2 apply (vertex and edge DoFs, level 13: the same 134,242,305
-DoFs), a device copy for reference, and the mixed-precision vs FP64 V-cycle
-solve.
+DoFs), the variable-coefficient apply (weights formed on the fly from a nodal
+coefficient, level 14), a device copy for reference, and the mixed-precision
+vs FP64 V-cycle solve.
 """
 from __future__ import annotations
 
@@ -73,6 +74,32 @@ def bench_apply(P, torch, co, ce, L, dtype, steps, warmup, seed, p2=False):
     P.destroy_macro_mesh(m)
     return {"storage": s, "unique": u, "ms_per_step": total_ms / steps, "launch_avg_ms": sum(per) / len(per),
             "launch_median_ms": per[len(per) // 2]}
+
+
+def bench_varcoef(P, torch, co, ce, L, dtype, steps, warmup):
+    """Per-launch HIP-event times of apply_varcoef (k in [0.5, 2.5) from the
+    keyed generator)."""
+    m = P.create_macro_mesh(co, ce, L)
+    s, u = P.mesh_num_dofs(m, L)
+    x = torch.empty(s, dtype=dtype, device="cuda")
+    k = torch.empty_like(x)
+    P.mesh_fill_random(m, L, 3, x)
+    P.mesh_fill_random(m, L, 4, k)
+    k += 1.5
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        P.apply_varcoef(m, L, k, x, y, stream)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        a.record(stream)
+        P.apply_varcoef(m, L, k, x, y, stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    per = sorted(a.elapsed_time(b) for a, b in ev)
+    del x, y, k
+    P.destroy_macro_mesh(m)
+    return {"storage": s, "unique": u, "launch_avg_ms": sum(per) / len(per), "launch_median_ms": per[len(per) // 2]}
 
 
 def copy_bandwidth(torch, nbytes=2 * 1024 ** 3, reps=20):
@@ -316,6 +343,14 @@ def main():
                 "GB_s": bpd * rp["unique"] / (rp["launch_avg_ms"] * 1e-3) / 1e9,
                 "launch_avg_ms": rp["launch_avg_ms"], "dofs": rp["unique"],
                 "algorithmic_B_per_dof": bpd, "paper_four_kernel_B_per_dof": 2 * bpd}
+        for dt, bpd in ((torch.float64, 24), (torch.float32, 12)):
+            tag = "fp64" if dt == torch.float64 else "fp32"
+            log(f"variable-coefficient apply 2D level 14 {tag} (weights formed on the fly)")
+            rv = bench_varcoef(P, torch, co, ce, 14, dt, args.steps, args.warmup)
+            extra[f"apply2d_varcoef_l14_{tag}"] = {
+                "GDoF_s": rv["unique"] / (rv["launch_avg_ms"] * 1e-3) / 1e9,
+                "GB_s": bpd * rv["unique"] / (rv["launch_avg_ms"] * 1e-3) / 1e9,
+                "launch_avg_ms": rv["launch_avg_ms"], "dofs": rv["unique"], "algorithmic_B_per_dof": bpd}
         log("device copy reference")
         cbw = copy_bandwidth(torch)
         extra["device_copy_GBps"] = cbw

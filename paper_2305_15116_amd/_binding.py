@@ -23,7 +23,7 @@ MF_FLAG_DIRICHLET, MF_FLAG_HOST_ONLY = 1, 2
 #: every symbol include/mf_stencil.h declares
 EXPORTS = ["mf_last_error", "create_macro_mesh", "destroy_macro_mesh", "mesh_info", "mesh_num_dofs",
            "mesh_dof_keys", "mesh_dof_index", "mesh_stencil", "mesh_workspace_bytes", "mesh_fill_random",
-           "mesh_set_dirichlet", "apply_stencil", "apply_p2", "smooth", "residual", "restrict_residual", "prolong_add",
+           "mesh_set_dirichlet", "apply_stencil", "apply_p2", "apply_varcoef", "smooth", "residual", "restrict_residual", "prolong_add",
            "vcycle_solve", "batch_create", "batch_destroy", "batch_size", "batch_add", "batch_step"]
 
 
@@ -197,6 +197,14 @@ def mesh_set_dirichlet(mesh: Mesh, level: int, b, y, stream=None):
 def apply_stencil(mesh: Mesh, level: int, x, y, stream=None):
     _check(lib().apply_stencil(mesh, level, _dtype_code(x), C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
                                _stream(stream)))
+
+
+def apply_varcoef(mesh: Mesh, level: int, k, x, y, stream=None):
+    """y = A(k) x for -div(k grad u) (2D P1, k nodal, same layout and dtype as x)."""
+    if k.dtype != x.dtype:
+        raise MFError(MF_EINVAL, "k and x must have the same dtype")
+    _check(lib().apply_varcoef(mesh, level, _dtype_code(x), C.c_void_p(k.data_ptr()), C.c_void_p(x.data_ptr()),
+                               C.c_void_p(y.data_ptr()), _stream(stream)))
 
 
 def apply_p2(mesh: Mesh, level: int, x, y, stream=None):

@@ -241,6 +241,16 @@ int apply_stencil(const mf_mesh* m, int level, int dtype, const void* x, void* y
   return launch_stencil(m, L, dtype, kApply, x, y, nullptr, 0.0, nullptr, s);
 }
 
+int apply_varcoef(const mf_mesh* m, int level, int dtype, const void* k, const void* x, void* y, void* stream) {
+  int rc = check_mesh(m, level, true);
+  if (!rc) rc = check_dtype(dtype);
+  if (rc) return rc;
+  if (m->dim != 2) return set_error(MF_ENOTSUP, "the variable-coefficient apply is built for 2D meshes");
+  if (!k || !x || !y) return set_error(MF_EINVAL, "NULL vector");
+  if (x == y || k == y) return set_error(MF_EINVAL, "y must not alias x or k");
+  return launch_varcoef_apply(m, m->levels[level], dtype, k, x, y, (hipStream_t)stream);
+}
+
 int apply_p2(const mf_mesh* m, int level, int dtype, const void* x, void* y, void* stream) {
   if (!m) return set_error(MF_EINVAL, "NULL mesh");
   if (m->dim != 2) return set_error(MF_ENOTSUP, "the P2 operator is built for 2D meshes");

@@ -35,6 +35,11 @@ int launch_exchange_apply(const Level& L, int dtype, void* y, hipStream_t s);
 // matrices (identity at Dirichlet DoFs), then the exchange.
 int launch_p2_apply(const mf_mesh* m, int level, int dtype, const void* x, void* y, hipStream_t s);
 
+// Variable-coefficient 2D apply y = A(k) x (k: nodal coefficient, same
+// layout as x), including the exchange of shared DoFs.
+int launch_varcoef_apply(const mf_mesh* m, const Level& L, int dtype, const void* k, const void* x, void* y,
+                         hipStream_t s);
+
 // result[0] = sum part[0..np), result[1] = max part[np..2np), fixed order.
 int launch_reduce(const double* part, int64_t np, double* result, hipStream_t s);
 
