@@ -76,7 +76,11 @@ __device__ __forceinline__ void ld_pair(const T* __restrict__ X, int M, int r, i
   const int rr = min(max(r, 0), last);
   const int S = M - rr;
   const T* row = X + row_start(M, rr);
-  if (S >= 1) {
+  if (sizeof(T) == 4) {
+    // FP32: two 4-byte loads measured faster than one 8-byte pair load
+    a = row[min(max(xa, 0), S)];
+    b = row[min(max(xa + 1, 0), S)];
+  } else if (S >= 1) {
     // one 2-element load at a start kept inside the row; a lane past the row
     // end takes the last element, a lane before its start the first
     const int st = min(max(xa, 0), S - 1);
