@@ -132,3 +132,31 @@ def test_3d_level8_cube(order):
         torch.cuda.synchronize()
         h = 1.0 / N
         assert float((y - torch.where(y == 1.0, y, torch.zeros_like(y))).abs().max()) <= 1e-12 * 12 * h
+
+
+def test_2d_level15_largest_supported_level():
+    """Level 15 (537,001,985 DoFs, 4.3 GB per FP64 vector) is the largest 2D
+    level: row offsets inside a macro reach 2^29, near the 32-bit index limit.
+    Sampled rows against the oracle's row evaluator, and A 1 on every row."""
+    co, ce = W.affine_triangle(2)
+    L = 15
+    N = 1 << L
+    m = P.create_macro_mesh(co, ce, L)
+    s, u = P.mesh_num_dofs(m, L)
+    assert s == u == (N + 1) * (N + 2) // 2
+    x = torch.empty(s, dtype=torch.float64, device="cuda")
+    P.mesh_fill_random(m, L, 8, x)
+    y = torch.empty_like(x)
+    P.apply_stencil(m, L, x, y)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(44)
+    pts = _samples_2d(N, rng, n=2000)
+    ml = np.hstack([np.zeros((len(pts), 1), np.int64), pts])
+    err, scale, _ = _check_sampled(co, ce, m, L, y, 8, ml, None)
+    assert err.max() <= 1e-12 * scale
+    x.fill_(1.0)
+    P.apply_stencil(m, L, x, y)
+    torch.cuda.synchronize()
+    wsum = np.abs(P.mesh_stencil(m, L, 0)).sum()
+    y[y == 1.0] = 0.0  # Dirichlet rows
+    assert float(y.abs().max()) <= 1e-12 * wsum

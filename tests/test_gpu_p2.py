@@ -119,9 +119,10 @@ def _lattice(M):
     return X, Y
 
 
-@pytest.mark.parametrize("level", [6, 13])
+@pytest.mark.parametrize("level", [6, 13, 14])
 def test_p2_full_size_quadratic_rows(level):
-    """Benchmark size (level 13): the whole output checked against the closed form."""
+    """Benchmark size (level 13) and the largest level (14, on the level-15
+    lattice): the whole output checked against the closed form."""
     co, ce = W.affine_triangle(2)
     m = P.create_macro_mesh(co, ce, level + 1)
     M = 1 << (level + 1)
