@@ -160,3 +160,32 @@ def test_2d_level15_largest_supported_level():
     wsum = np.abs(P.mesh_stencil(m, L, 0)).sum()
     y[y == 1.0] = 0.0  # Dirichlet rows
     assert float(y.abs().max()) <= 1e-12 * wsum
+
+
+def test_3d_level11_largest_supported_level():
+    """Level 11 (one tetrahedron: 1,435,853,825 DoFs, 11.5 GB per FP64 vector)
+    is the largest 3D level: slice offsets exceed 2^30.  Sampled rows against
+    the oracle's row evaluator, and A 1 on every row."""
+    co, ce = W.unit_tet()
+    J, t = W.random_affine(3, 7)
+    co = W.apply_affine(co, J, t)
+    L = 11
+    N = 1 << L
+    m = P.create_macro_mesh(co, ce, L)
+    s, u = P.mesh_num_dofs(m, L)
+    assert s == u == (N + 1) * (N + 2) * (N + 3) // 6
+    x = torch.empty(s, dtype=torch.float64, device="cuda")
+    P.mesh_fill_random(m, L, 9, x)
+    y = torch.empty_like(x)
+    P.apply_stencil(m, L, x, y)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(45)
+    ml = _samples_3d(N, 1, rng, n=2000)
+    err, scale, _ = _check_sampled(co, ce, m, L, y, 9, ml, None)
+    assert err.max() <= 1e-12 * scale
+    x.fill_(1.0)
+    P.apply_stencil(m, L, x, y)
+    torch.cuda.synchronize()
+    wsum = np.abs(P.mesh_stencil(m, L, 0)).sum()
+    y[y == 1.0] = 0.0  # Dirichlet rows
+    assert float(y.abs().max()) <= 1e-12 * wsum
