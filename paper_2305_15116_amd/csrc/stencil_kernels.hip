@@ -774,12 +774,15 @@ void run_stencil(const Level& L, const void* x, void* y, const void* b, double o
                  hipStream_t s) {
   const StencilArgs<T> a = stencil_args<T>(L, x, y, b, omega, part);
   if (a.nwg > 0) {
-    if (DIM == 3 && L.pen_z == kPenZSmall)
-      hipLaunchKernelGGL((stencil_kernel<T, DIM, MODE, kPenZSmall>), dim3(stencil_grid(a.nwg)), dim3(kWG), 0, s,
-                         single(a, a.nwg));
-    else
+    // the pencil depth is a 3D notion: 2D uses one instance
+    if (DIM == 3 && L.pen_z == kPenZSmall) {
+      if constexpr (DIM == 3)
+        hipLaunchKernelGGL((stencil_kernel<T, DIM, MODE, kPenZSmall>), dim3(stencil_grid(a.nwg)), dim3(kWG), 0, s,
+                           single(a, a.nwg));
+    } else {
       hipLaunchKernelGGL((stencil_kernel<T, DIM, MODE, kPenZ>), dim3(stencil_grid(a.nwg)), dim3(kWG), 0, s,
                          single(a, a.nwg));
+    }
   }
   const int nblk = exchange_blocks(L);
   if (nblk == 0) return;
@@ -824,10 +827,11 @@ int launch(const mf_mesh* m, const Level& L, int dtype, int mode, const void* x,
 // ---------------------------------------------------------------- batched
 template <typename T, int DIM, int MODE>
 void batch_stencil(const BatchOp& op, const char* table, hipStream_t s) {
-  if (op.kind == kOpStencil && DIM == 3 && op.variant == kPenZSmall)
-    hipLaunchKernelGGL((stencil_kernel<T, DIM, MODE, kPenZSmall>), dim3(stencil_grid(op.nwg)), dim3(kWG), 0, s,
-                       batched<StencilArgs<T>>(op, table));
-  else if (op.kind == kOpStencil)
+  if (op.kind == kOpStencil && DIM == 3 && op.variant == kPenZSmall) {
+    if constexpr (DIM == 3)
+      hipLaunchKernelGGL((stencil_kernel<T, DIM, MODE, kPenZSmall>), dim3(stencil_grid(op.nwg)), dim3(kWG), 0, s,
+                         batched<StencilArgs<T>>(op, table));
+  } else if (op.kind == kOpStencil)
     hipLaunchKernelGGL((stencil_kernel<T, DIM, MODE, kPenZ>), dim3(stencil_grid(op.nwg)), dim3(kWG), 0, s,
                        batched<StencilArgs<T>>(op, table));
   else
