@@ -32,7 +32,8 @@
 //     get identity rows; other rows keep their boundary columns.
 //  6. y = A x as a row loop.
 // Also: the 2D P2 stiffness matrix (vertex and edge DoFs) by the same steps
-// with quadratic elements, the variable-coefficient P1 matrix, the same rows evaluated for a sample of points without a global
+// with quadratic elements, the variable-coefficient P1 matrix, the P1 matrix
+// of blended (non-affine) 2D macros, the same rows evaluated for a sample of points without a global
 // build (for full-size checks), the P1 prolongation between two levels, the
 // lumped mass vector, and the keyed SplitMix64 input generator.
 
@@ -525,6 +526,68 @@ int64_t or_assemble_varcoef(or_mesh* m, int dirichlet, const double* k) {
     m->rowptr[u + 1] = (int64_t)m->cols.size();
   }
   m->csr_dirichlet = dirichlet ? 5 : 4;
+  return (int64_t)m->cols.size();
+}
+
+// ---- Blended (non-affine) macros in 2D (the survey's on-the-fly-stencil
+// row: geometry that varies inside a macro, so no two rows share a stencil).
+// Reading: macro c maps reference coordinates xi (lattice point / N) by
+//   F(xi) = P0 + (P1 - P0) xi1 + (P2 - P0) xi2 + xi0 xi1 xi2 d_c,
+// xi0 = 1 - xi1 - xi2, with a per-macro vector d_c.  The cubic bubble
+// vanishes on the macro's edges, so neighbouring macros agree on every shared
+// point.  Micro-triangles are the straight triangles on the mapped lattice
+// points; the operator is the P1 stiffness matrix of that micro mesh.
+// d holds nc x 2 values.  Returns nnz, or -1.
+int64_t or_assemble_blended(or_mesh* m, int dirichlet, const double* d) {
+  if (m->dim != 2) { g_err = "blended macros are 2D"; return -1; }
+  const int64_t N = m->N;
+  std::vector<std::vector<std::pair<int64_t, double>>> rows(m->nu);
+  bool bad = false;
+  for (int64_t c = 0; c < m->nc; ++c) {
+    const int64_t* cv = &m->cells[c * 3];
+    const int64_t* L = &m->lat[c * m->lat_stride];
+    const double* P0 = &m->coords[cv[0] * 2];
+    const double* P1 = &m->coords[cv[1] * 2];
+    const double* P2 = &m->coords[cv[2] * 2];
+    auto map = [&](const int64_t* p, double out[2]) {
+      const double a = (double)p[0] / (double)N, b = (double)p[1] / (double)N;
+      const double bub = (1.0 - a - b) * a * b;
+      for (int r = 0; r < 2; ++r) out[r] = P0[r] + (P1[r] - P0[r]) * a + (P2[r] - P0[r]) * b + bub * d[c * 2 + r];
+    };
+    for_each_cell_element(m, c, [&](int64_t (*v)[3]) {
+      double X[3][2];
+      for (int i = 0; i < 3; ++i) map(v[i], X[i]);
+      double E[3][3] = {{0}};
+      for (int k = 0; k < 2; ++k)
+        for (int r = 0; r < 2; ++r) E[r][k] = X[k + 1][r] - X[0][r];
+      double K[MAXV][MAXV], vol;
+      if (!element_stiffness(2, E, K, &vol)) { bad = true; return; }
+      int64_t ids[3];
+      for (int i = 0; i < 3; ++i) ids[i] = L[lat_index(2, N, v[i])];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) rows[ids[i]].push_back({ids[j], K[i][j]});
+    });
+  }
+  if (bad) { g_err = "degenerate micro-element"; return -1; }
+  m->rowptr.assign(m->nu + 1, 0);
+  m->cols.clear();
+  m->vals.clear();
+  for (int64_t u = 0; u < m->nu; ++u) {
+    if (dirichlet && m->bnd[u]) {
+      m->cols.push_back(u);
+      m->vals.push_back(1.0);
+    } else {
+      auto& row = rows[u];
+      std::stable_sort(row.begin(), row.end(),
+                       [](const std::pair<int64_t, double>& a, const std::pair<int64_t, double>& b) { return a.first < b.first; });
+      for (size_t q = 0; q < row.size(); ++q) {
+        if (q > 0 && row[q].first == row[q - 1].first) m->vals.back() += row[q].second;
+        else { m->cols.push_back(row[q].first); m->vals.push_back(row[q].second); }
+      }
+    }
+    m->rowptr[u + 1] = (int64_t)m->cols.size();
+  }
+  m->csr_dirichlet = dirichlet ? 7 : 6;
   return (int64_t)m->cols.size();
 }
 

@@ -46,6 +46,8 @@ def lib():
         L.or_elements.argtypes = [C.c_void_p, C.c_void_p]
         L.or_assemble.restype = C.c_int64
         L.or_assemble.argtypes = [C.c_void_p, C.c_int]
+        L.or_assemble_blended.restype = C.c_int64
+        L.or_assemble_blended.argtypes = [C.c_void_p, C.c_int, f64p]
         L.or_assemble_varcoef.restype = C.c_int64
         L.or_assemble_varcoef.argtypes = [C.c_void_p, C.c_int, f64p]
         L.or_assemble_p2.restype = C.c_int64
@@ -139,6 +141,20 @@ class OracleMesh:
             self._native_state = bool(dirichlet)
             self._native_nnz = int(nnz)
         return self._native_nnz
+
+    def csr_blended(self, d, dirichlet: bool = True) -> sp.csr_matrix:
+        """P1 stiffness matrix of the micro mesh whose lattice points macro c
+        maps by F_c(xi) = affine(xi) + xi0 xi1 xi2 d[c] (2D; d: n_cells x 2)."""
+        d = np.ascontiguousarray(d, dtype=np.float64).reshape(-1)
+        nnz = lib().or_assemble_blended(self._h, int(dirichlet), d)
+        if nnz < 0:
+            raise ValueError(_err())
+        self._native_state = ("blended", None)
+        rp = np.empty(self.n + 1, np.int64)
+        ci = np.empty(nnz, np.int64)
+        va = np.empty(nnz)
+        lib().or_get_csr(self._h, rp, ci, va)
+        return sp.csr_matrix((va, ci, rp), shape=(self.n, self.n))
 
     def csr_varcoef(self, k, dirichlet: bool = True) -> sp.csr_matrix:
         """Stiffness matrix of -div(k grad u), k the P1 interpolant of the
