@@ -139,6 +139,19 @@ int apply_stencil(const mf_mesh* mesh, int level, int dtype, const void* x_dev, 
 int apply_varcoef(const mf_mesh* mesh, int level, int dtype, const void* k_dev, const void* x_dev, void* y_dev,
                   void* stream);
 
+/* y = A x on blended (non-affine) 2D macros, FP64: macro c maps its lattice
+ * by F_c(xi) = P0 + (P1 - P0) xi1 + (P2 - P0) xi2 + xi0 xi1 xi2 d_c (xi =
+ * lattice point / 2^level, xi0 = 1 - xi1 - xi2, P0..P2 its vertices in cell
+ * order), a cubic bubble that vanishes on macro edges, so shared points
+ * agree.  A is the P1 stiffness matrix of the straight micro-triangles on
+ * the mapped points, with every element matrix formed on the fly (no two
+ * rows share a stencil; the paper's remark that varying stencils can be
+ * computed on the fly, comparison of matrix-free and sparse storage).
+ * bubble_dev: n_macros x 2 doubles on the device (d_c).  Dirichlet rows give
+ * y = x.  y must not alias x.  MF_ENOTSUP for a 3D mesh.  Asynchronous. */
+int apply_blended(const mf_mesh* mesh, int level, const double* bubble_dev, const double* x_dev, double* y_dev,
+                  void* stream);
+
 /* y = A x for the P2 (quadratic) Laplace operator of a 2D mesh refined
  * `level` times: DoFs at the vertices and edge midpoints of the
  * micro-triangles (the paper's P2 discretisation, with its vertex-to-vertex,

@@ -23,7 +23,7 @@ MF_FLAG_DIRICHLET, MF_FLAG_HOST_ONLY = 1, 2
 #: every symbol include/mf_stencil.h declares
 EXPORTS = ["mf_last_error", "create_macro_mesh", "destroy_macro_mesh", "mesh_info", "mesh_num_dofs",
            "mesh_dof_keys", "mesh_dof_index", "mesh_stencil", "mesh_workspace_bytes", "mesh_fill_random",
-           "mesh_set_dirichlet", "apply_stencil", "apply_p2", "apply_varcoef", "smooth", "residual", "restrict_residual", "prolong_add",
+           "mesh_set_dirichlet", "apply_stencil", "apply_p2", "apply_varcoef", "apply_blended", "smooth", "residual", "restrict_residual", "prolong_add",
            "vcycle_solve", "batch_create", "batch_destroy", "batch_size", "batch_add", "batch_step"]
 
 
@@ -204,6 +204,14 @@ def apply_varcoef(mesh: Mesh, level: int, k, x, y, stream=None):
     if k.dtype != x.dtype:
         raise MFError(MF_EINVAL, "k and x must have the same dtype")
     _check(lib().apply_varcoef(mesh, level, _dtype_code(x), C.c_void_p(k.data_ptr()), C.c_void_p(x.data_ptr()),
+                               C.c_void_p(y.data_ptr()), _stream(stream)))
+
+
+def apply_blended(mesh: Mesh, level: int, bubble, x, y, stream=None):
+    """y = A x on blended 2D macros (FP64); bubble: (n_macros, 2) float64 on the device."""
+    if bubble.dtype != x.dtype or _dtype_code(x) != MF_F64:
+        raise MFError(MF_EINVAL, "apply_blended takes float64 bubble, x and y")
+    _check(lib().apply_blended(mesh, level, C.c_void_p(bubble.data_ptr()), C.c_void_p(x.data_ptr()),
                                C.c_void_p(y.data_ptr()), _stream(stream)))
 
 

@@ -251,6 +251,15 @@ int apply_varcoef(const mf_mesh* m, int level, int dtype, const void* k, const v
   return launch_varcoef_apply(m, m->levels[level], dtype, k, x, y, (hipStream_t)stream);
 }
 
+int apply_blended(const mf_mesh* m, int level, const double* bubble, const double* x, double* y, void* stream) {
+  int rc = check_mesh(m, level, true);
+  if (rc) return rc;
+  if (m->dim != 2) return set_error(MF_ENOTSUP, "blended macros are built for 2D meshes");
+  if (!bubble || !x || !y) return set_error(MF_EINVAL, "NULL vector");
+  if (x == y) return set_error(MF_EINVAL, "y must not alias x");
+  return launch_blended_apply(m, m->levels[level], bubble, x, y, (hipStream_t)stream);
+}
+
 int apply_p2(const mf_mesh* m, int level, int dtype, const void* x, void* y, void* stream) {
   if (!m) return set_error(MF_EINVAL, "NULL mesh");
   if (m->dim != 2) return set_error(MF_ENOTSUP, "the P2 operator is built for 2D meshes");

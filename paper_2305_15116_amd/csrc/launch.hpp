@@ -40,6 +40,10 @@ int launch_p2_apply(const mf_mesh* m, int level, int dtype, const void* x, void*
 int launch_varcoef_apply(const mf_mesh* m, const Level& L, int dtype, const void* k, const void* x, void* y,
                          hipStream_t s);
 
+// Blended-macro 2D apply (FP64): bubble holds n_macros x 2 doubles (device).
+int launch_blended_apply(const mf_mesh* m, const Level& L, const double* bubble, const double* x, double* y,
+                         hipStream_t s);
+
 // result[0] = sum part[0..np), result[1] = max part[np..2np), fixed order.
 int launch_reduce(const double* part, int64_t np, double* result, hipStream_t s);
 

@@ -92,6 +92,13 @@ struct Prim {
   bool dirichlet = false;
 };
 
+// Geometry of a 2D macro: its first vertex and the edge vectors to the other two.
+struct Geo2 {
+  double p0[2];
+  double e1[2];
+  double e2[2];
+};
+
 }  // namespace mf
 
 struct mf_mesh {
@@ -108,6 +115,8 @@ struct mf_mesh {
   std::vector<mf::Level> levels;
   std::vector<mf::P2Macro> p2;       // 2D: P2 constants per macro (level-independent)
   mf::P2Macro* p2_dev = nullptr;
+  std::vector<mf::Geo2> geo2;        // 2D: macro vertex and edge vectors (blended maps)
+  mf::Geo2* geo2_dev = nullptr;
   std::mutex norm_mutex;  // serialises residual() calls that return a norm
 };
 
@@ -134,8 +143,9 @@ int build_mesh(mf_mesh* m);
 int build_coarse_solver(mf_mesh* m, int level);
 void free_device(mf_mesh* m);
 int upload_level(mf_mesh* m, Level& L);
-// 2D P2 constants and tiles (p2_setup.cpp); called by build_mesh after the levels.
-int build_p2(mf_mesh* m);
+// 2D tables (p2_setup.cpp): P2 constants and tiles, macro geometry; called by
+// build_mesh after the levels.
+int build_2d_tables(mf_mesh* m);
 
 // Keys of every storage point of a level, (dim+1) pairs each.
 void storage_keys(const mf_mesh* m, int level, int64_t* vids, int32_t* wts);

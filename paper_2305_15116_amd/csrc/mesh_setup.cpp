@@ -664,7 +664,7 @@ int build_mesh(mf_mesh* m) {
     for (int l = 0; l <= m->max_level; ++l)
       if ((rc = upload_level(m, m->levels[l]))) return rc;
   }
-  return build_p2(m);
+  return build_2d_tables(m);
 }
 
 void free_device(mf_mesh* m) {
@@ -680,6 +680,8 @@ void free_device(mf_mesh* m) {
   }
   if (m->p2_dev) (void)hipFree(m->p2_dev);
   m->p2_dev = nullptr;
+  if (m->geo2_dev) (void)hipFree(m->geo2_dev);
+  m->geo2_dev = nullptr;
 }
 
 void storage_keys(const mf_mesh* m, int level, int64_t* vids, int32_t* wts) {

@@ -1,5 +1,6 @@
-// Host set-up of the 2D P2 operator: per-macro element matrix and interior
-// stencils, and the wave tiles of the fused walk.
+// Host set-up of the 2D-only operators: the P2 operator's per-macro element
+// matrix, interior stencils and wave tiles, and the macro geometry the
+// blended apply maps its lattice with.
 //
 // The paper's P2 discretisation (vertex and edge-midpoint DoFs) is applied in
 // HyTeG by four kernels (vertex-to-vertex, edge-to-vertex, vertex-to-edge,
@@ -142,8 +143,19 @@ int fill_class(const std::map<std::pair<int, int>, double>& st, int first, int n
 
 }  // namespace
 
-int build_p2(mf_mesh* m) {
+int build_2d_tables(mf_mesh* m) {
   if (m->dim != 2) return MF_OK;
+  m->geo2.assign(m->nc, Geo2{});
+  for (int64_t c = 0; c < m->nc; ++c) {
+    const double* P0 = &m->coords[m->cells[c * 3] * 2];
+    const double* P1 = &m->coords[m->cells[c * 3 + 1] * 2];
+    const double* P2 = &m->coords[m->cells[c * 3 + 2] * 2];
+    for (int r = 0; r < 2; ++r) {
+      m->geo2[c].p0[r] = P0[r];
+      m->geo2[c].e1[r] = P1[r] - P0[r];
+      m->geo2[c].e2[r] = P2[r] - P0[r];
+    }
+  }
   m->p2.assign(m->nc, P2Macro{});
   for (int64_t c = 0; c < m->nc; ++c) {
     const double* P0 = &m->coords[m->cells[c * 3] * 2];
@@ -188,6 +200,7 @@ int build_p2(mf_mesh* m) {
   }
   if (m->host_only) return MF_OK;
   int rc = dev_upload(&m->p2_dev, m->p2);
+  if (!rc) rc = dev_upload(&m->geo2_dev, m->geo2);
   if (rc) return rc;
   for (Level& L : m->levels)
     if ((rc = dev_upload(&L.dev.p2_tiles, L.p2_tiles))) return rc;
