@@ -76,6 +76,21 @@ def bench_apply(P, torch, co, ce, L, dtype, steps, warmup, seed, p2=False):
             "launch_median_ms": per[len(per) // 2]}
 
 
+def _launch_times(torch, stream, call, steps, warmup):
+    """Average and median of `steps` launches of call(stream), each bracketed
+    by its own HIP events on that stream."""
+    for _ in range(warmup):
+        call(stream)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        a.record(stream)
+        call(stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    per = sorted(a.elapsed_time(b) for a, b in ev)
+    return {"launch_avg_ms": sum(per) / len(per), "launch_median_ms": per[len(per) // 2]}
+
+
 def bench_varcoef(P, torch, co, ce, L, dtype, steps, warmup):
     """Per-launch HIP-event times of apply_varcoef (k in [0.5, 2.5) from the
     keyed generator)."""
@@ -87,19 +102,25 @@ def bench_varcoef(P, torch, co, ce, L, dtype, steps, warmup):
     P.mesh_fill_random(m, L, 4, k)
     k += 1.5
     y = torch.empty_like(x)
-    stream = torch.cuda.current_stream()
-    for _ in range(warmup):
-        P.apply_varcoef(m, L, k, x, y, stream)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-    for a, b in ev:
-        a.record(stream)
-        P.apply_varcoef(m, L, k, x, y, stream)
-        b.record(stream)
-    torch.cuda.synchronize()
-    per = sorted(a.elapsed_time(b) for a, b in ev)
+    r = _launch_times(torch, torch.cuda.current_stream(), lambda st: P.apply_varcoef(m, L, k, x, y, st), steps, warmup)
     del x, y, k
     P.destroy_macro_mesh(m)
-    return {"storage": s, "unique": u, "launch_avg_ms": sum(per) / len(per), "launch_median_ms": per[len(per) // 2]}
+    return {"storage": s, "unique": u, **r}
+
+
+def bench_blended(P, torch, co, ce, L, steps, warmup):
+    """Per-launch HIP-event times of apply_blended (FP64; every macro's bubble
+    vector (0.45, -0.3), which keeps the mapped micro triangles valid)."""
+    m = P.create_macro_mesh(co, ce, L)
+    s, u = P.mesh_num_dofs(m, L)
+    x = torch.empty(s, dtype=torch.float64, device="cuda")
+    P.mesh_fill_random(m, L, 3, x)
+    y = torch.empty_like(x)
+    d = torch.tensor([[0.45, -0.3]] * len(ce), dtype=torch.float64, device="cuda")
+    r = _launch_times(torch, torch.cuda.current_stream(), lambda st: P.apply_blended(m, L, d, x, y, st), steps, warmup)
+    del x, y
+    P.destroy_macro_mesh(m)
+    return {"storage": s, "unique": u, **r}
 
 
 def copy_bandwidth(torch, nbytes=2 * 1024 ** 3, reps=20):
@@ -351,6 +372,12 @@ def main():
                 "GDoF_s": rv["unique"] / (rv["launch_avg_ms"] * 1e-3) / 1e9,
                 "GB_s": bpd * rv["unique"] / (rv["launch_avg_ms"] * 1e-3) / 1e9,
                 "launch_avg_ms": rv["launch_avg_ms"], "dofs": rv["unique"], "algorithmic_B_per_dof": bpd}
+        log("blended (non-affine) apply 2D level 14 fp64 (element matrices formed on the fly)")
+        rb = bench_blended(P, torch, co, ce, 14, args.steps, args.warmup)
+        extra["apply2d_blended_l14_fp64"] = {
+            "GDoF_s": rb["unique"] / (rb["launch_avg_ms"] * 1e-3) / 1e9,
+            "GB_s": 16 * rb["unique"] / (rb["launch_avg_ms"] * 1e-3) / 1e9,
+            "launch_avg_ms": rb["launch_avg_ms"], "dofs": rb["unique"], "algorithmic_B_per_dof": 16}
         log("device copy reference")
         cbw = copy_bandwidth(torch)
         extra["device_copy_GBps"] = cbw

@@ -211,6 +211,8 @@ def apply_blended(mesh: Mesh, level: int, bubble, x, y, stream=None):
     """y = A x on blended 2D macros (FP64); bubble: (n_macros, 2) float64 on the device."""
     if bubble.dtype != x.dtype or _dtype_code(x) != MF_F64:
         raise MFError(MF_EINVAL, "apply_blended takes float64 bubble, x and y")
+    if bubble.numel() != 2 * mesh.n_macros or not bubble.is_contiguous():
+        raise MFError(MF_EINVAL, f"apply_blended needs a contiguous ({mesh.n_macros}, 2) bubble")
     _check(lib().apply_blended(mesh, level, C.c_void_p(bubble.data_ptr()), C.c_void_p(x.data_ptr()),
                                C.c_void_p(y.data_ptr()), _stream(stream)))
 

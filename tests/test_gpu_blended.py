@@ -82,6 +82,8 @@ def test_blended_rejects_bad_calls():
         P.apply_blended(m2, 3, d, x, x)
     with pytest.raises(P.MFError, match=r"\[-1\]"):
         P.apply_blended(m2, 3, d.float(), x.float(), x.float())
+    with pytest.raises(P.MFError, match=r"\[-1\]"):
+        P.apply_blended(m2, 3, torch.zeros(4, dtype=torch.float64, device="cuda"), x, torch.empty_like(x))
     torch.cuda.synchronize()
 
 
