@@ -6,16 +6,24 @@
 // two rows share a stencil, so every element matrix is formed on the fly from
 // the mapped coordinates: the paper's remark that varying weights can be
 // computed on the fly at an arithmetic cost, here taken to the point where
-// the arithmetic (about 120 FP64 operations per DoF) rivals the 16 B/DoF of
-// memory traffic.
+// the arithmetic (about 85 vector instructions per DoF, most of them FP64)
+// outweighs the 16 B/DoF of memory traffic.
 //
-// Walk: the constant-coefficient 2D tiles.  Per lane and band of two rows,
-// the element matrices of the band's up triangle U(x,b) = {(x,b), (x+1,b),
-// (x,b+1)} and down triangle D(x,b) = {(x+1,b), (x+1,b+1), (x,b+1)} are
-// formed once (K = (1 / 2|det E|) adj(E^T E) on the two edge vectors, the
-// vertex-0 row and column from zero row sums) and serve the two rows that
-// border the band; the neighbouring lane's triangles come by DPP shifts.
-// Boundary handling as in the variable-coefficient walk.
+// Walk: the constant-coefficient 2D tiles, in edge form.  A P1 element
+// matrix has zero row sums, so a row is y_i = sum_j w_ij (x_i - x_j) over
+// the six lattice edges at i, where w_ij sums -K_ij over the (up to two)
+// micro-triangles that share the edge, and -K_ij = cot(theta_k) / 2 with
+// theta_k the angle opposite the edge: (e_ki . e_kj) / (2 |det|).  Per lane
+// and band of two rows, the up triangle U = {C, R, C1} and the down triangle
+// D = {R, R1, C1} (C = (x,b), R = (x+1,b), C1 = (x,b+1), R1 = (x+1,b+1))
+// give their three cotangent weights from five edge vectors; the band then
+// holds the lane's vertical edge weight (x,b)-(x,b+1) (U's plus the left
+// lane's D's) and diagonal edge weight (x+1,b)-(x,b+1) (U's plus D's), and
+// the horizontal edge (x,b+1)-(x+1,b+1) collects D's weight now and the next
+// band's U's.  A row then needs two weights from the left lane (DPP) and the
+// two carried from the band below.  Triangles outside the macro get zero
+// weights on tiles that touch the macro boundary; Dirichlet points copy x and
+// the exchange kernel completes shared DoFs.
 
 #include <hip/hip_runtime.h>
 
@@ -29,54 +37,58 @@ namespace {
 using wave::dn1;
 using wave::up1;
 
-constexpr int kBlH = kTileH2, kBlU = 4;  // rows per tile, rows loaded ahead
+// rows per tile (the walk runs on the 16-row tiles of the FP32 passes, which
+// halves the extra band each tile forms below its first row), rows loaded ahead
+constexpr int kBlH = kTileH2F, kBlU = 4;
 
-// Symmetric P1 element matrix of the triangle (X0, X1, X2).
-struct TriK {
-  double k00, k01, k02, k11, k12, k22;
+struct V2 {
+  double x, y;
 };
-__device__ __forceinline__ TriK tri_k(double x0, double y0, double x1, double y1, double x2, double y2) {
-  const double e1x = x1 - x0, e1y = y1 - y0, e2x = x2 - x0, e2y = y2 - y0;
-  const double m11 = e1x * e1x + e1y * e1y, m12 = e1x * e2x + e1y * e2y, m22 = e2x * e2x + e2y * e2y;
-  // 1 / (2 |det E|): the hardware reciprocal estimate refined by two Newton
-  // steps s <- s + s (1 - t s) (each squares the relative error), which is
-  // cheaper than the IEEE division sequence and within an ulp of it
-  const double t = 2.0 * fabs(e1x * e2y - e1y * e2x);
+__device__ __forceinline__ V2 operator-(V2 a, V2 b) { return {a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ double dot(V2 a, V2 b) { return fma(a.x, b.x, a.y * b.y); }
+__device__ __forceinline__ double cross(V2 a, V2 b) { return fma(a.x, b.y, -(a.y * b.x)); }
+__device__ __forceinline__ V2 dn1v(V2 a) { return {dn1(a.x), dn1(a.y)}; }
+
+// 1 / (2 |d|): the hardware reciprocal estimate refined by two Newton steps
+// s <- s + s (1 - t s) (each squares the relative error), cheaper than the
+// IEEE division sequence and within an ulp of it
+__device__ __forceinline__ double half_inv_abs(double d) {
+  const double t = 2.0 * fabs(d);
   double s = __builtin_amdgcn_rcp(t);
   s = fma(s, fma(-t, s, 1.0), s);
-  s = fma(s, fma(-t, s, 1.0), s);
-  TriK k;
-  k.k11 = m22 * s;
-  k.k22 = m11 * s;
-  k.k12 = -m12 * s;
-  k.k01 = -(k.k11 + k.k12);
-  k.k02 = -(k.k12 + k.k22);
-  k.k00 = -(k.k01 + k.k02);
-  return k;
+  return fma(s, fma(-t, s, 1.0), s);
 }
 
-// A band's two element matrices and the entries of the neighbouring lane's
-// (lane - 1) ones that the rows use.
+// What one band leaves for the rows above it.
 struct Band {
-  TriK u, d;
-  double u01l, u11l, u12l;              // U(x-1, b): row of its vertex 1
-  double d00l, d01l, d02l, d11l, d12l;  // D(x-1, b): rows of its vertices 0 and 1
+  V2 c, r, h;     // mapped points (x, b+1), (x+1, b+1) and their difference
+  double u_cr;    // U's -K on the horizontal edge (x,b)-(x+1,b)
+  double wv, wd;  // weights of the edges (x,b)-(x,b+1) and (x+1,b)-(x,b+1)
+  double d_top;   // D's -K on the horizontal edge (x,b+1)-(x+1,b+1)
 };
 
-__device__ __forceinline__ Band make_band(double cx, double cy, double cx1, double cy1) {
-  // (cx, cy): this lane's point in row b; (cx1, cy1): in row b + 1
-  const double rx = dn1(cx), ry = dn1(cy), rx1 = dn1(cx1), ry1 = dn1(cy1);
+// Band b from the points of row b (c, r = right neighbour, h = r - c) and
+// c1 = F(x, b+1).  in_u / in_d: whether U(x,b) / D(x,b) lie in the macro.
+__device__ __forceinline__ Band make_band(V2 c, V2 r, V2 h, V2 c1, bool in_u, bool in_d) {
   Band B;
-  B.u = tri_k(cx, cy, rx, ry, cx1, cy1);
-  B.d = tri_k(rx, ry, rx1, ry1, cx1, cy1);
-  B.u01l = up1(B.u.k01);
-  B.u11l = up1(B.u.k11);
-  B.u12l = up1(B.u.k12);
-  B.d00l = up1(B.d.k00);
-  B.d01l = up1(B.d.k01);
-  B.d02l = up1(B.d.k02);
-  B.d11l = up1(B.d.k11);
-  B.d12l = up1(B.d.k12);
+  const V2 r1 = dn1v(c1);
+  const V2 h1 = r1 - c1, v = c1 - c, g = c1 - r, f = r1 - r;
+  // one reciprocal for both triangles: 1 / (2 |det U| |det D|); a triangle
+  // outside the macro enters as 1, so a degenerate one cannot spoil the other
+  const double tu = in_u ? fabs(cross(h, v)) : 1.0, td = in_d ? fabs(cross(f, g)) : 1.0;
+  const double sp = half_inv_abs(tu * td);
+  const double su = sp * td, sd = sp * tu;
+  // -K per edge of U and D (cotangent of the opposite angle over two)
+  const double u_cr = dot(v, g) * su, u_cc1 = -dot(h, g) * su, u_rc1 = dot(h, v) * su;
+  const double d_rr1 = -dot(g, h1) * sd, d_rc1 = dot(f, h1) * sd, d_r1c1 = dot(f, g) * sd;
+  B.u_cr = in_u ? u_cr : 0.0;
+  const double d_rr1m = in_d ? d_rr1 : 0.0;
+  B.wv = (in_u ? u_cc1 : 0.0) + up1(d_rr1m);
+  B.wd = (in_u ? u_rc1 : 0.0) + (in_d ? d_rc1 : 0.0);
+  B.d_top = in_d ? d_r1c1 : 0.0;
+  B.c = c1;
+  B.r = r1;
+  B.h = h1;
   return B;
 }
 
@@ -97,18 +109,20 @@ __device__ __forceinline__ void bl_tile(int x0, int y0, const MacroDev& M, const
   Y += M.base;
   const double invN = 1.0 / (double)N;  // exact: N is a power of two
   const double a = (double)x * invN;
-  auto map = [&](int r, double& fx, double& fy) {
+  const double ax = fma(G.e1[0], a, G.p0[0]), ay = fma(G.e1[1], a, G.p0[1]);
+  auto map = [&](int r) -> V2 {
     const double b = (double)r * invN;
     const double bub = (1.0 - a - b) * a * b;
-    fx = G.p0[0] + G.e1[0] * a + G.e2[0] * b + bub * bx;
-    fy = G.p0[1] + G.e1[1] * a + G.e2[1] * b + bub * by;
+    return {fma(bub, bx, fma(G.e2[0], b, ax)), fma(bub, by, fma(G.e2[1], b, ay))};
   };
-  double cx, cy, cx1, cy1;
-  map(y0 - 1, cx, cy);
-  map(y0, cx1, cy1);
-  Band bm = make_band(cx, cy, cx1, cy1);  // band y0-1
-  cx = cx1;
-  cy = cy1;
+  // triangles U(x,b) and D(x,b) inside the macro (always, on interior tiles)
+  auto in_u = [&](int b) { return INNER || (x >= 0 && b >= 0 && x + b <= N - 1); };
+  auto in_d = [&](int b) { return INNER || (x >= 0 && b >= 0 && x + b <= N - 2); };
+  Band bm;  // band y0-1
+  {
+    const V2 c = map(y0 - 1), r = dn1v(c);
+    bm = make_band(c, r, r - c, map(y0), in_u(y0 - 1), in_d(y0 - 1));
+  }
   double xm = ld_row(X, N, y0 - 1, y1, xc), x0v = ld_row(X, N, y0, y1, xc);
   double q[kBlU];
 #pragma unroll
@@ -119,38 +133,19 @@ __device__ __forceinline__ void bl_tile(int x0, int y0, const MacroDev& M, const
     const int yy = y0 + j;
     const double xp = q[j % kBlU];
     q[j % kBlU] = ld_row(X, N, y0 + 1 + j + kBlU, y1, xc);
-    if (j >= nrows) continue;
-    map(yy + 1, cx1, cy1);
-    const Band bp = make_band(cx, cy, cx1, cy1);  // band y
-    const double xE = dn1(x0v), xW = up1(x0v), xNW = up1(xp), xSE = dn1(xm);
-    // the six triangles around (x, y), each with this point's row of its matrix
-    const double t1 = bp.u.k00 * x0v + bp.u.k01 * xE + bp.u.k02 * xp;      // U(x, y), vertex 0
-    const double t2 = bp.u01l * xW + bp.u11l * x0v + bp.u12l * xNW;         // U(x-1, y), vertex 1
-    const double t3 = bm.u.k02 * xm + bm.u.k12 * xSE + bm.u.k22 * x0v;      // U(x, y-1), vertex 2
-    const double t4 = bp.d00l * x0v + bp.d01l * xp + bp.d02l * xNW;         // D(x-1, y), vertex 0
-    const double t5 = bm.d01l * xm + bm.d11l * x0v + bm.d12l * xW;          // D(x-1, y-1), vertex 1
-    const double t6 = bm.d.k02 * xSE + bm.d.k12 * xE + bm.d.k22 * x0v;      // D(x, y-1), vertex 2
+    if (!INNER && j >= nrows) break;  // interior tiles always have kBlH rows
+    const Band bp = make_band(bm.c, bm.r, bm.h, map(yy + 1), in_u(yy), in_d(yy));  // band y
+    const double wh = bp.u_cr + bm.d_top;                                          // edge (x,y)-(x+1,y)
+    const double acc = ((wh * (x0v - dn1(x0v)) + up1(wh) * (x0v - up1(x0v))) +
+                        (bp.wv * (x0v - xp) + bm.wv * (x0v - xm))) +
+                       (up1(bp.wd) * (x0v - up1(xp)) + bm.wd * (x0v - dn1(xm)));
     const bool inside = lane >= 1 && lane <= kTileW && x + yy <= N;
-    double acc;
-    if (INNER) {
-      acc = ((t1 + t2) + (t3 + t4)) + (t5 + t6);
-      if (inside) Y[row_start(N, yy) + xc] = acc;
-    } else {
-      const bool in1 = x + yy <= N - 1, in2 = x >= 1, in3 = yy >= 1;
-      const bool in4 = x >= 1 && x + yy <= N - 1, in5 = x >= 1 && yy >= 1, in6 = yy >= 1 && x + yy <= N - 1;
-      const double s12 = (in1 ? t1 : 0.0) + (in2 ? t2 : 0.0);
-      const double s34 = (in3 ? t3 : 0.0) + (in4 ? t4 : 0.0);
-      const double s56 = (in5 ? t5 : 0.0) + (in6 ? t6 : 0.0);
-      acc = (s12 + s34) + s56;
-      if (inside) {
-        const bool dir = (M.dir_mask >> support_mask(2, N, x, yy, 0)) & 1;
-        Y[row_start(N, yy) + xc] = dir ? x0v : acc;
-      }
+    if (inside) {
+      const bool dir = !INNER && ((M.dir_mask >> support_mask(2, N, x, yy, 0)) & 1);
+      Y[row_start(N, yy) + xc] = dir ? x0v : acc;
     }
     xm = x0v;
     x0v = xp;
-    cx = cx1;
-    cy = cy1;
     bm = bp;
   }
 }
@@ -176,9 +171,10 @@ __global__ __launch_bounds__(kWG) void blended_kernel(const Tile* __restrict__ t
 
 int launch_blended_apply(const mf_mesh* m, const Level& L, const double* bubble, const double* x, double* y,
                          hipStream_t s) {
-  const int nwg = (int)(L.tiles.size() / kWavesPerWG);
+  static_assert(kBlH == kTileH2F, "the walk runs on the FP32 tile list");
+  const int nwg = (int)(L.tiles_f32.size() / kWavesPerWG);
   if (nwg > 0)
-    hipLaunchKernelGGL(blended_kernel, dim3(wave::xcd_grid(nwg)), dim3(kWG), 0, s, L.dev.tiles, nwg, L.dev.md,
+    hipLaunchKernelGGL(blended_kernel, dim3(wave::xcd_grid(nwg)), dim3(kWG), 0, s, L.dev.tiles_f32, nwg, L.dev.md,
                        m->geo2_dev, bubble, x, y);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_error(MF_EDEVICE, hipGetErrorString(e));
