@@ -163,11 +163,39 @@ void vector_op(PlanBuilder& P, const std::vector<Member*>& ms, int dim, int kind
   P.add(kind, dtype, dim, 0, va);
 }
 
-// Jacobi sweeps at the members' cycle level (ping-pong x <-> t), as jacobi_sweeps does.
+// First sweep from a zero iterate: t = omega D^-1 b, as jacobi_sweeps_from_zero.
+template <typename T, class LevelOf>
+void jacobi0_op(PlanBuilder& P, const std::vector<Member*>& ms, int dim, const mf_solve_opts& o, LevelOf lof) {
+  std::vector<std::pair<Jacobi0Args<T>, int>> ja;
+  for (Member* M : ms) {
+    if (M->m->dim != dim) continue;
+    const int l = lof(*M);
+    if (l < 0) continue;
+    const Jacobi0Args<T> a = jacobi0_args<T>(lev(*M, l), M->w.b[l], M->w.t[l], o.omega);
+    ja.push_back({a, jacobi0_blocks(a)});
+  }
+  P.add(kOpJacobi0, dtype_of<T>(), dim, 0, ja);
+}
+
+// Jacobi sweeps at the members' cycle level (ping-pong x <-> t), as
+// jacobi_sweeps does, or (from_zero) as jacobi_sweeps_from_zero.
 template <class LevelOf>
 void jacobi_stage(PlanBuilder& P, const std::vector<Member*>& ms, int dim, int vdt, const mf_solve_opts& o,
-                  int sweeps, LevelOf lof) {
-  for (int i = 0; i < sweeps; ++i) {
+                  int sweeps, LevelOf lof, bool from_zero = false) {
+  if (from_zero && sweeps == 0) {
+    vector_op(P, ms, dim, kOpFill, vdt, [&](const Member& M, VecArgs& a) {
+      const int l = lof(M);
+      if (l < 0) return false;
+      a = vec_args(M.w.x[l], nullptr, nullptr, lev(M, l).storage, 0.0);
+      return true;
+    });
+    return;
+  }
+  if (from_zero) {
+    if (vdt == MF_F64) jacobi0_op<double>(P, ms, dim, o, lof);
+    else jacobi0_op<float>(P, ms, dim, o, lof);
+  }
+  for (int i = from_zero ? 1 : 0; i < sweeps; ++i) {
     stencil_op(P, ms, dim, vdt, kJacobi, o.omega, [&](const Member& M, Pass& p) {
       const int l = lof(M);
       if (l < 0) return false;
@@ -253,14 +281,11 @@ void build_plan(mf_batch* B) {
         return true;
       });
     }
-    vector_op(P, corr, dim, kOpFill, vdt, [](const Member& M, VecArgs& a) {
-      a = vec_args(M.w.x[M.level], nullptr, nullptr, lev(M, M.level).storage, 0.0);
-      return true;
-    });
-    // descent: stage dl works at level lc + dl of every member deep enough
+    // descent: stage dl works at level lc + dl of every member deep enough;
+    // each level's iterate starts at zero (first sweep from zero)
     for (int dl = dmax; dl >= 1; --dl) {
       auto lof = [dl](const Member& M) { return M.level - M.lc >= dl ? M.lc + dl : -1; };
-      jacobi_stage(P, corr, dim, vdt, o, o.pre, lof);
+      jacobi_stage(P, corr, dim, vdt, o, o.pre, lof, true);
       stencil_op(P, corr, dim, vdt, kResidual, 0.0, [&](const Member& M, Pass& p) {
         const int l = lof(M);
         if (l < 0) return false;
@@ -273,12 +298,6 @@ void build_plan(mf_batch* B) {
       });
       if (vdt == MF_F64) transfer_op<double>(P, corr, dim, vdt, true, dl);
       else transfer_op<float>(P, corr, dim, vdt, true, dl);
-      vector_op(P, corr, dim, kOpFill, vdt, [&](const Member& M, VecArgs& a) {
-        const int l = lof(M);
-        if (l < 0) return false;
-        a = vec_args(M.w.x[l - 1], nullptr, nullptr, lev(M, l - 1).storage, 0.0);
-        return true;
-      });
     }
     // coarse level
     vector_op(P, corr, dim, kOpFill, vdt, [](const Member& M, VecArgs& a) {

@@ -91,14 +91,31 @@ int jacobi_sweeps(const mf_mesh* m, const Level& L, int dtype, double omega, int
   return MF_OK;
 }
 
+// Jacobi sweeps from a zero iterate: the first sweep is y = omega D^-1 b (one
+// pass, no exchange), bitwise what a full sweep gives from x = 0; the rest as
+// jacobi_sweeps.  x need not be initialised.
+int jacobi_sweeps_from_zero(const mf_mesh* m, const Level& L, int dtype, double omega, int sweeps, const void* b,
+                            void* x, void* tmp, hipStream_t s) {
+  if (sweeps == 0) return launch_fill(dtype, x, 0.0, L.storage, s);
+  int rc = launch_jacobi0(m, L, dtype, omega, b, tmp, s);
+  void* cur = tmp;
+  void* oth = x;
+  for (int i = 1; i < sweeps && !rc; ++i) {
+    rc = launch_stencil(m, L, dtype, kJacobi, cur, oth, b, omega, nullptr, s);
+    std::swap(cur, oth);
+  }
+  if (!rc && cur != x) rc = launch_copy(dtype, x, cur, L.storage, s);
+  return rc;
+}
+
+// One V-cycle on b[l] from the zero iterate; the correction lands in x[l].
 int vcycle(const mf_mesh* m, int l, int lc, int dtype, const Workspace& w, const mf_solve_opts& o, hipStream_t s) {
   const Level& L = m->levels[l];
   if (l == lc) return launch_coarse_solve(L, dtype, w.b[l], w.x[l], s);
-  int rc = jacobi_sweeps(m, L, dtype, o.omega, o.pre, w.b[l], w.x[l], w.t[l], s);
+  int rc = jacobi_sweeps_from_zero(m, L, dtype, o.omega, o.pre, w.b[l], w.x[l], w.t[l], s);
   if (rc) return rc;
   rc = launch_stencil(m, L, dtype, kResidual, w.x[l], w.t[l], w.b[l], 0.0, nullptr, s);
   if (!rc) rc = launch_restrict(m, L, m->levels[l - 1], dtype, w.t[l], w.b[l - 1], s);
-  if (!rc) rc = launch_fill(dtype, w.x[l - 1], 0.0, m->levels[l - 1].storage, s);
   if (!rc) rc = vcycle(m, l - 1, lc, dtype, w, o, s);
   if (!rc) rc = launch_prolong_add(m, L, m->levels[l - 1], dtype, w.x[l - 1], w.x[l], s);
   if (!rc) rc = jacobi_sweeps(m, L, dtype, o.omega, o.post, w.b[l], w.x[l], w.t[l], s);
@@ -370,9 +387,6 @@ int vcycle_solve(const mf_mesh* m, int level, const double* b, double* x, void* 
     if (f32) {
       // scale r by its max norm before the cast so FP32 keeps its relative precision
       rc = launch_scale_to_f32(w.r64, (float*)w.b[level], w.result, L.storage, s);
-      if (!rc) rc = launch_fill(MF_F32, w.x[level], 0.0, L.storage, s);
-    } else {
-      rc = launch_fill(MF_F64, w.x[level], 0.0, L.storage, s);
     }
     if (!rc) rc = vcycle(m, level, lc, vdt, w, o, s);
     if (rc) return rc;

@@ -93,6 +93,27 @@ struct CoarseArgs {
   T* X;
 };
 
+// jacobi0_kernel: the first Jacobi sweep of a V-cycle level, whose iterate is
+// zero.  Blocks [0, nblk_pts) walk the level's point segments; blocks
+// [nblk_pts, nblk_pts + nblk_grp) take the shared non-Dirichlet DoFs (the
+// exchange list), one group per thread.
+template <typename T>
+struct Jacobi0Args {
+  const Tile* segs;
+  int nseg;
+  int nblk_pts;
+  int ngroups;
+  int nblk_grp;
+  const int32_t* gptr;
+  const Copy* copies;
+  const double* ginv;
+  const float* ginvf;
+  const MacroDev* md;
+  const T* B;
+  T* Y;
+  T omega;
+};
+
 // Plain vector kernels (fill, copy, axpy and the FP32 <-> FP64 pair of the
 // mixed solver, whose scale comes from a device norm result).
 struct VecArgs {
@@ -234,6 +255,27 @@ inline CoarseArgs<float> coarse_args<float>(const Level& L, const void* b, void*
 }
 inline int coarse_blocks(const Level& L) { return (int)((L.ncoarse + kWavesPerWG - 1) / kWavesPerWG); }
 
+template <typename T>
+Jacobi0Args<T> jacobi0_args(const Level& L, const void* b, void* y, double omega) {
+  Jacobi0Args<T> a;
+  a.segs = L.dev.segs;
+  a.nseg = (int)L.segs.size();
+  a.nblk_pts = transfer_blocks(a.nseg);
+  a.ngroups = (int)L.nxgroups();
+  a.nblk_grp = (a.ngroups + kWG - 1) / kWG;
+  a.gptr = L.dev.xgrp_ptr;
+  a.copies = L.dev.xcopies;
+  a.ginv = L.dev.xgrp_invdiag;
+  a.ginvf = L.dev.xgrp_invdiagf;
+  a.md = L.dev.md;
+  a.B = (const T*)b;
+  a.Y = (T*)y;
+  a.omega = (T)omega;
+  return a;
+}
+template <typename T>
+int jacobi0_blocks(const Jacobi0Args<T>& a) { return a.nblk_pts + a.nblk_grp; }
+
 inline VecArgs vec_args(void* y, const void* x, const double* res, int64_t n, double a) {
   return VecArgs{y, x, res, n, a, vec_blocks(n)};
 }
@@ -261,6 +303,7 @@ enum OpKind : int {
   kOpPcgZDot,      // PcgArgs, dtype = type of e: z = s e, partials of r . z
   kOpPcgDir,       // VecArgs: y = x + beta y, beta = res[2] / res[3] (0 if res[3] == 0)
   kOpPcgUpdate,    // PcgArgs: x += alpha p, r -= alpha q, alpha = res[2] / res[4]; partials of r . r
+  kOpJacobi0,      // Jacobi0Args<T>: y = omega D^-1 b (the first sweep from a zero iterate)
 };
 
 // One batched launch: a table of nseg argument records at args_off and nseg+1

@@ -53,6 +53,10 @@ int launch_restrict(const mf_mesh* m, const Level& fine, const Level& coarse, in
 int launch_prolong_add(const mf_mesh* m, const Level& fine, const Level& coarse, int dtype, const void* ec,
                        void* xf, hipStream_t s);
 int launch_coarse_solve(const Level& L, int dtype, const void* b, void* x, hipStream_t s);
+// y = omega D^-1 b at every storage DoF (0 at Dirichlet DoFs): a Jacobi sweep
+// whose iterate is zero, bitwise equal to launch_stencil(kJacobi) with x = 0.
+int launch_jacobi0(const mf_mesh* m, const Level& L, int dtype, double omega, const void* b, void* y,
+                   hipStream_t s);
 
 // Plain vector kernels over n entries.
 int launch_fill(int dtype, void* x, double v, int64_t n, hipStream_t s);

@@ -221,6 +221,68 @@ __global__ __launch_bounds__(kWG) void prolong_add_kernel(const Launch<TransferA
   }
 }
 
+// First Jacobi sweep of a V-cycle level.  The iterate is zero there, so
+// x' = x + omega D^-1 (b - A x) reduces to omega D^-1 b, with D the diagonal
+// of the row the sweep would finish: the macro's interior centre weight, the
+// partial stencil's centre at a boundary point no other macro shares, the
+// assembled diagonal of a shared DoF (exchange list), and x' = x = 0 at
+// Dirichlet DoFs.  The arithmetic is that of the stencil and exchange
+// kernels with x = 0 (fma(omega d, b - 0, 0)), so the result is bitwise
+// the same, in one pass that reads b once and needs no exchange.
+template <typename T>
+__device__ __forceinline__ T centre_inv(const MacroDev& M, int mask, int full, int centre) {
+  if constexpr (sizeof(T) == 8) return mask == full ? M.inv_diag : 1.0 / M.wm[mask][centre];
+  else return mask == full ? M.inv_diagf : 1.0f / M.wmf[mask][centre];
+}
+
+template <typename T, int DIM>
+__device__ __forceinline__ void jacobi0_segment(const Jacobi0Args<T>& a, const Tile sg) {
+  constexpr int full = DIM == 2 ? 7 : 15;
+  constexpr int centre = stencil_table(DIM).centre;
+  const MacroDev& M = a.md[sg.macro];
+  const MacroC C = load_macro(a.md, sg.macro);
+  const int N = C.N;
+  const int x = sg.x0 + (threadIdx.x & (kWave - 1));
+  const int y = sg.y0, z = DIM == 3 ? sg.z : 0;
+  if (x + y + z > N) return;
+  const int mask = support_mask(DIM, N, x, y, z);
+  const bool dir = mask != full && ((C.dir_mask >> mask) & 1);
+  const bool shared = mask != full && !dir && ((M.shared_mask >> mask) & 1);
+  if (shared) return;  // finished by the group part
+  const int64_t i = C.base + lidx<DIM>(N, x, y, z);
+  a.Y[i] = dir ? T(0) : fma(a.omega * centre_inv<T>(M, mask, full, centre), a.B[i], T(0));
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(kWG) void jacobi0_kernel(const Launch<Jacobi0Args<T>> L) {
+  Jacobi0Args<T> a;
+  const int blk = resolve(L, (int)blockIdx.x, a);
+  if (blk < a.nblk_pts) {
+    const int stride = a.nblk_pts * kWavesPerWG;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int si = blk * kWavesPerWG + w; si < a.nseg; si += stride) {
+      const Tile sg = load_seg(a.segs, si);
+      if (sg.macro >= 0) jacobi0_segment<T, DIM>(a, sg);
+    }
+    return;
+  }
+  const int g = (blk - a.nblk_pts) * kWG + (int)threadIdx.x;
+  if (g >= a.ngroups) return;
+  const int c0 = a.gptr[g], c1 = a.gptr[g + 1];
+  const Copy& f = a.copies[c0];
+  const MacroDev& M0 = a.md[f.macro];
+  const T b = a.B[M0.base + lidx<DIM>(M0.N, f.x, f.y, f.z)];
+  T d;
+  if constexpr (sizeof(T) == 8) d = a.ginv[g];
+  else d = a.ginvf[g];
+  const T out = fma(a.omega * d, b, T(0));
+  for (int c = c0; c < c1; ++c) {
+    const Copy& k = a.copies[c];
+    const MacroDev& Mk = a.md[k.macro];
+    a.Y[Mk.base + lidx<DIM>(Mk.N, k.x, k.y, k.z)] = out;
+  }
+}
+
 // Coarse direct solve: x(copies of unknown i) = sum_j Ainv[i][j] b(first copy of j).
 // One wavefront per unknown; x must be zero elsewhere beforehand.
 template <typename T>
@@ -409,6 +471,28 @@ int launch_prolong_add(const mf_mesh* m, const Level& F, const Level& C, int dty
   return check_launch();
 }
 
+namespace {
+template <typename T>
+void run_jacobi0(int dim, const Launch<Jacobi0Args<T>>& l, hipStream_t s) {
+  if (dim == 2) hipLaunchKernelGGL((jacobi0_kernel<T, 2>), dim3(l.nwg), dim3(kWG), 0, s, l);
+  else hipLaunchKernelGGL((jacobi0_kernel<T, 3>), dim3(l.nwg), dim3(kWG), 0, s, l);
+}
+}  // namespace
+
+int launch_jacobi0(const mf_mesh* m, const Level& L, int dtype, double omega, const void* b, void* y,
+                   hipStream_t s) {
+  if (dtype == MF_F64) {
+    const Jacobi0Args<double> a = jacobi0_args<double>(L, b, y, omega);
+    const int nwg = jacobi0_blocks(a);
+    if (nwg > 0) run_jacobi0<double>(m->dim, single(a, nwg), s);
+  } else {
+    const Jacobi0Args<float> a = jacobi0_args<float>(L, b, y, omega);
+    const int nwg = jacobi0_blocks(a);
+    if (nwg > 0) run_jacobi0<float>(m->dim, single(a, nwg), s);
+  }
+  return check_launch();
+}
+
 int launch_coarse_solve(const Level& L, int dtype, const void* b, void* x, hipStream_t s) {
   int rc = launch_fill(dtype, x, 0.0, L.storage, s);
   if (rc) return rc;
@@ -510,6 +594,10 @@ int launch_vector_batch(const BatchOp& op, const char* table, hipStream_t s) {
     case kOpPcgUpdate: run_pcg_point<kOpPcgUpdate>(op.dim, MF_F64, batched<PcgArgs>(op, table), s); return check_launch();
     case kOpPcgDir:
       hipLaunchKernelGGL(pcg_dir_kernel, dim3(op.nwg), dim3(256), 0, s, batched<VecArgs>(op, table));
+      return check_launch();
+    case kOpJacobi0:
+      if (op.dtype == MF_F64) run_jacobi0<double>(op.dim, batched<Jacobi0Args<double>>(op, table), s);
+      else run_jacobi0<float>(op.dim, batched<Jacobi0Args<float>>(op, table), s);
       return check_launch();
     default: return set_error(MF_EINVAL, "unknown batch op");
   }
