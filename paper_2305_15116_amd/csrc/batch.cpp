@@ -40,6 +40,7 @@ struct Member {
   int64_t tag = 0;
   const mf_mesh* m = nullptr;
   int level = 0, lc = 0;
+  int tail = 0;  // levels lc .. lc + tail - 1 run in one workgroup launch (tail_levels)
   const double* b = nullptr;
   double* x = nullptr;
   Workspace w;
@@ -221,7 +222,7 @@ void transfer_op(PlanBuilder& P, const std::vector<Member*>& ms, int dim, int dt
   std::vector<std::pair<TransferArgs<T>, int>> ta;
   std::vector<std::pair<GroupArgs<T>, int>> ia;
   for (Member* M : ms) {
-    if (M->m->dim != dim || M->level - M->lc < dl) continue;
+    if (M->m->dim != dim || M->level - M->lc < dl || dl < M->tail) continue;
     const int l = M->lc + dl;
     const Level& F = lev(*M, l);
     const Level& C = lev(*M, l - 1);
@@ -240,11 +241,22 @@ template <typename T>
 void coarse_op(PlanBuilder& P, const std::vector<Member*>& ms, int dim, int dtype) {
   std::vector<std::pair<CoarseArgs<T>, int>> ca;
   for (Member* M : ms) {
-    if (M->m->dim != dim) continue;
+    if (M->m->dim != dim || M->tail > 0) continue;
     const Level& L = lev(*M, M->lc);
     ca.push_back({coarse_args<T>(L, M->w.b[M->lc], M->w.x[M->lc]), coarse_blocks(L)});
   }
   P.add(kOpCoarse, dtype, dim, 0, ca);
+}
+
+// The bottom of the cycle of members with a tail: one workgroup each.
+template <typename T>
+void tail_op(PlanBuilder& P, const std::vector<Member*>& ms, int dim, const mf_solve_opts& o) {
+  std::vector<std::pair<TailArgs<T>, int>> ta;
+  for (Member* M : ms) {
+    if (M->m->dim != dim || M->tail == 0) continue;
+    ta.push_back({tail_args<T>(M->m, M->lc, M->tail, o.pre, o.post, o.omega, M->w.b, M->w.x, M->w.t), 1});
+  }
+  P.add(kOpTail, dtype_of<T>(), dim, 0, ta);
 }
 
 void reduce_op(PlanBuilder& P, const std::vector<std::pair<ReduceArgs, int>>& ra) { P.add(kOpReduce, MF_F64, 0, 0, ra); }
@@ -284,7 +296,7 @@ void build_plan(mf_batch* B) {
     // descent: stage dl works at level lc + dl of every member deep enough;
     // each level's iterate starts at zero (first sweep from zero)
     for (int dl = dmax; dl >= 1; --dl) {
-      auto lof = [dl](const Member& M) { return M.level - M.lc >= dl ? M.lc + dl : -1; };
+      auto lof = [dl](const Member& M) { return M.level - M.lc >= dl && dl >= M.tail ? M.lc + dl : -1; };
       jacobi_stage(P, corr, dim, vdt, o, o.pre, lof, true);
       stencil_op(P, corr, dim, vdt, kResidual, 0.0, [&](const Member& M, Pass& p) {
         const int l = lof(M);
@@ -299,16 +311,22 @@ void build_plan(mf_batch* B) {
       if (vdt == MF_F64) transfer_op<double>(P, corr, dim, vdt, true, dl);
       else transfer_op<float>(P, corr, dim, vdt, true, dl);
     }
-    // coarse level
+    // coarse level, or the one-workgroup tail of members that have one
     vector_op(P, corr, dim, kOpFill, vdt, [](const Member& M, VecArgs& a) {
+      if (M.tail > 0) return false;
       a = vec_args(M.w.x[M.lc], nullptr, nullptr, lev(M, M.lc).storage, 0.0);
       return true;
     });
-    if (vdt == MF_F64) coarse_op<double>(P, corr, dim, vdt);
-    else coarse_op<float>(P, corr, dim, vdt);
+    if (vdt == MF_F64) {
+      coarse_op<double>(P, corr, dim, vdt);
+      tail_op<double>(P, corr, dim, o);
+    } else {
+      coarse_op<float>(P, corr, dim, vdt);
+      tail_op<float>(P, corr, dim, o);
+    }
     // ascent
     for (int dl = 1; dl <= dmax; ++dl) {
-      auto lof = [dl](const Member& M) { return M.level - M.lc >= dl ? M.lc + dl : -1; };
+      auto lof = [dl](const Member& M) { return M.level - M.lc >= dl && dl >= M.tail ? M.lc + dl : -1; };
       if (vdt == MF_F64) transfer_op<double>(P, corr, dim, vdt, false, dl);
       else transfer_op<float>(P, corr, dim, vdt, false, dl);
       jacobi_stage(P, corr, dim, vdt, o, o.post, lof);
@@ -528,6 +546,7 @@ int batch_add(mf_batch* B, const mf_mesh* m, int level, const double* b, double*
   M.m = m;
   M.level = level;
   M.lc = lc;
+  M.tail = tail_levels(m, level, lc);
   M.b = b;
   M.x = x;
   M.w = carve(m, level, B->o.mode, 0, (char*)workspace);

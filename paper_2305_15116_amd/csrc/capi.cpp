@@ -109,14 +109,18 @@ int jacobi_sweeps_from_zero(const mf_mesh* m, const Level& L, int dtype, double 
 }
 
 // One V-cycle on b[l] from the zero iterate; the correction lands in x[l].
-int vcycle(const mf_mesh* m, int l, int lc, int dtype, const Workspace& w, const mf_solve_opts& o, hipStream_t s) {
+// Levels lc .. lc + tail - 1 (tail = tail_levels(...), 0 for none) run in one
+// workgroup launch.
+int vcycle(const mf_mesh* m, int l, int lc, int tail, int dtype, const Workspace& w, const mf_solve_opts& o,
+           hipStream_t s) {
   const Level& L = m->levels[l];
+  if (tail > 0 && l == lc + tail - 1) return launch_vcycle_tail(m, lc, tail, dtype, o.pre, o.post, o.omega, w.b, w.x, w.t, s);
   if (l == lc) return launch_coarse_solve(L, dtype, w.b[l], w.x[l], s);
   int rc = jacobi_sweeps_from_zero(m, L, dtype, o.omega, o.pre, w.b[l], w.x[l], w.t[l], s);
   if (rc) return rc;
   rc = launch_stencil(m, L, dtype, kResidual, w.x[l], w.t[l], w.b[l], 0.0, nullptr, s);
   if (!rc) rc = launch_restrict(m, L, m->levels[l - 1], dtype, w.t[l], w.b[l - 1], s);
-  if (!rc) rc = vcycle(m, l - 1, lc, dtype, w, o, s);
+  if (!rc) rc = vcycle(m, l - 1, lc, tail, dtype, w, o, s);
   if (!rc) rc = launch_prolong_add(m, L, m->levels[l - 1], dtype, w.x[l - 1], w.x[l], s);
   if (!rc) rc = jacobi_sweeps(m, L, dtype, o.omega, o.post, w.b[l], w.x[l], w.t[l], s);
   return rc;
@@ -355,6 +359,7 @@ int vcycle_solve(const mf_mesh* m, int level, const double* b, double* x, void* 
     rc = build_coarse_solver(const_cast<mf_mesh*>(m), lc);
   }
   if (rc) return rc;
+  const int tail = tail_levels(m, level, lc);
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t s = (hipStream_t)stream;
   const Level& L = m->levels[level];
@@ -388,7 +393,7 @@ int vcycle_solve(const mf_mesh* m, int level, const double* b, double* x, void* 
       // scale r by its max norm before the cast so FP32 keeps its relative precision
       rc = launch_scale_to_f32(w.r64, (float*)w.b[level], w.result, L.storage, s);
     }
-    if (!rc) rc = vcycle(m, level, lc, vdt, w, o, s);
+    if (!rc) rc = vcycle(m, level, lc, tail, vdt, w, o, s);
     if (rc) return rc;
     if (!pcg) {
       // iterative refinement: x += e, then the new residual

@@ -114,6 +114,54 @@ struct Jacobi0Args {
   T omega;
 };
 
+// vcycle_tail_kernel: the bottom of a V-cycle — the coarse solve and up to
+// kTailLevels - 1 levels above it, each of at most kTailMaxPoints storage
+// points — run by one workgroup of kTailWG threads with barriers between the
+// steps, instead of about a dozen launches per level whose time is latency.
+// The point limit is where one CU stops beating the whole chip: measured on
+// cube and triangle solves, 3D levels of 990 points gain and of 5,814 points
+// lose (the single CU's load bandwidth), 2D levels of 2,145 points gain.
+#ifndef MF_TAIL_LEVELS
+#define MF_TAIL_LEVELS 4
+#endif
+#ifndef MF_TAIL_MAX_POINTS
+#define MF_TAIL_MAX_POINTS 4096
+#endif
+constexpr int kTailLevels = MF_TAIL_LEVELS;
+constexpr int kTailWG = 1024;
+constexpr int64_t kTailMaxPoints = MF_TAIL_MAX_POINTS;
+constexpr int kTailMaxCoarse = 256;  // coarse unknowns (the dense solve runs on one CU)
+
+template <typename T>
+struct TailLevel {
+  const Tile* segs;  // point segments of the level
+  int nseg;
+  int nx;  // exchange list: shared non-Dirichlet DoFs
+  const int32_t* xptr;
+  const Copy* xcopies;
+  const double* xinv;
+  const float* xinvf;
+  int ng;  // all macro-boundary DoFs
+  const int32_t* gptr;
+  const Copy* copies;
+  const uint8_t* gflag;
+  const MacroDev* md;
+  int64_t storage;  // nmac macros of side N, stored one after the other
+  int N, nmac;
+  T* b;  // right-hand side, iterate and ping-pong vector of the cycle
+  T* x;
+  T* t;
+};
+
+template <typename T>
+struct TailArgs {
+  int nlev;  // levels lc .. lc + nlev - 1 in lv[0 .. nlev)
+  int pre, post;
+  T omega;
+  CoarseArgs<T> coarse;
+  TailLevel<T> lv[kTailLevels];
+};
+
 // Plain vector kernels (fill, copy, axpy and the FP32 <-> FP64 pair of the
 // mixed solver, whose scale comes from a device norm result).
 struct VecArgs {
@@ -276,6 +324,38 @@ Jacobi0Args<T> jacobi0_args(const Level& L, const void* b, void* y, double omega
 template <typename T>
 int jacobi0_blocks(const Jacobi0Args<T>& a) { return a.nblk_pts + a.nblk_grp; }
 
+template <typename T>
+TailLevel<T> tail_level(const Level& L, void* b, void* x, void* t) {
+  TailLevel<T> v;
+  v.segs = L.dev.segs;
+  v.nseg = (int)L.segs.size();
+  v.nx = (int)L.nxgroups();
+  v.xptr = L.dev.xgrp_ptr;
+  v.xcopies = L.dev.xcopies;
+  v.xinv = L.dev.xgrp_invdiag;
+  v.xinvf = L.dev.xgrp_invdiagf;
+  v.ng = (int)L.ngroups();
+  v.gptr = L.dev.grp_ptr;
+  v.copies = L.dev.copies;
+  v.gflag = L.dev.grp_flag;
+  v.md = L.dev.md;
+  v.storage = L.storage;
+  v.N = L.N;
+  v.nmac = (int)L.base.size();
+  v.b = (T*)b;
+  v.x = (T*)x;
+  v.t = (T*)t;
+  return v;
+}
+
+// Levels the tail of a V-cycle from `level` down to lc takes (0: none).
+inline int tail_levels(const mf_mesh* m, int level, int lc) {
+  if (kTailLevels < 1 || m->levels[lc].ncoarse > kTailMaxCoarse || m->levels[lc].storage > kTailMaxPoints) return 0;
+  int n = 1;
+  while (n < kTailLevels && lc + n <= level && m->levels[lc + n].storage <= kTailMaxPoints) ++n;
+  return n;
+}
+
 inline VecArgs vec_args(void* y, const void* x, const double* res, int64_t n, double a) {
   return VecArgs{y, x, res, n, a, vec_blocks(n)};
 }
@@ -304,6 +384,7 @@ enum OpKind : int {
   kOpPcgDir,       // VecArgs: y = x + beta y, beta = res[2] / res[3] (0 if res[3] == 0)
   kOpPcgUpdate,    // PcgArgs: x += alpha p, r -= alpha q, alpha = res[2] / res[4]; partials of r . r
   kOpJacobi0,      // Jacobi0Args<T>: y = omega D^-1 b (the first sweep from a zero iterate)
+  kOpTail,         // TailArgs<T>: the V-cycle below a level, one workgroup per request
 };
 
 // One batched launch: a table of nseg argument records at args_off and nseg+1

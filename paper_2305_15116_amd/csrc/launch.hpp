@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "kargs.hpp"
 #include "mesh.hpp"
@@ -57,6 +58,17 @@ int launch_coarse_solve(const Level& L, int dtype, const void* b, void* x, hipSt
 // whose iterate is zero, bitwise equal to launch_stencil(kJacobi) with x = 0.
 int launch_jacobi0(const mf_mesh* m, const Level& L, int dtype, double omega, const void* b, void* y,
                    hipStream_t s);
+
+// The V-cycle below level lc + nlev - 1 (nlev = tail_levels(...) >= 1) in one
+// workgroup: vectors per level as in the solver workspace (b, x, t indexed
+// by level).  Same steps and arithmetic as vcycle() on those levels.
+template <typename T>
+TailArgs<T> tail_args(const mf_mesh* m, int lc, int nlev, int pre, int post, double omega,
+                      const std::vector<void*>& b, const std::vector<void*>& x, const std::vector<void*>& t);
+int launch_vcycle_tail(const mf_mesh* m, int lc, int nlev, int dtype, int pre, int post, double omega,
+                       const std::vector<void*>& b, const std::vector<void*>& x, const std::vector<void*>& t,
+                       hipStream_t s);
+int launch_tail_batch(const BatchOp& op, const char* table, hipStream_t s);
 
 // Plain vector kernels over n entries.
 int launch_fill(int dtype, void* x, double v, int64_t n, hipStream_t s);

@@ -1,0 +1,337 @@
+// Device helpers shared by the stencil, transfer and V-cycle tail kernels:
+// precision-specific macro constants, the per-point partial stencil sum and
+// row finish of the stencil kernels, argument resolution of batched
+// launches, and the per-segment transfer and zero-iterate Jacobi steps.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kargs.hpp"
+
+namespace mf {
+
+template <typename T>
+struct Prec;
+
+template <>
+struct Prec<double> {
+  static __device__ __forceinline__ double w(const MacroDev& M, int mask, int i) { return M.wm[mask][i]; }
+  static __device__ __forceinline__ double invd(const MacroDev& M) { return M.inv_diag; }
+  static __device__ __forceinline__ double ginv(const double* d, const float*, int g) { return d[g]; }
+};
+
+template <>
+struct Prec<float> {
+  static __device__ __forceinline__ float w(const MacroDev& M, int mask, int i) { return M.wmf[mask][i]; }
+  static __device__ __forceinline__ float invd(const MacroDev& M) { return M.inv_diagf; }
+  static __device__ __forceinline__ float ginv(const double*, const float* f, int g) { return f[g]; }
+};
+
+// Ordinary (write-back) stores: partial lines at wave boundaries merge in L2.
+template <typename T>
+__device__ __forceinline__ void st(T* p, T v) { *p = v; }
+
+// A macro's 16 x 16 partial-stencil table (row = support mask).  The stencil
+// kernels keep a copy in LDS, so that the per-lane lookups of boundary lanes
+// are LDS reads and never wait on the vector-memory counter that paces the
+// row loads in flight; the V-cycle tail reads the macro record directly.
+template <typename T>
+using WTab = T (*)[16];
+
+// Partial stencil sum for a point with support `mask`: neighbours outside
+// the macro (whose values in v are clamped stand-ins) are dropped by
+// selects, so the code is branch-free.
+template <typename T, int DIM>
+__device__ __forceinline__ T partial_sum(const WTab<T> W, int mask, int N, int x, int y, int z, const T* v) {
+  constexpr StencilTable ST = stencil_table(DIM);
+  T acc = T(0);
+#pragma unroll
+  for (int o = 0; o < ST.n; ++o) {
+    const int nx = x + ST.off[o][0], ny = y + ST.off[o][1], nz = z + ST.off[o][2];
+    const bool in = nx >= 0 && ny >= 0 && nz >= 0 && nx + ny + nz <= N;
+    acc = fma(W[mask][o], in ? v[o] : T(0), acc);
+  }
+  return acc;
+}
+
+// Norm / dot partials of one finished row value `out` (xc = the point's x).
+template <typename T, int MODE>
+__device__ __forceinline__ void accum(double& ss, double& mx, T out, T xc) {
+  if (MODE == kResidual || MODE == kNormB) {
+    ss += (double)out * (double)out;
+    mx = fmax(mx, fabs((double)out));
+  } else if (MODE == kApplyDot) {
+    ss += (double)xc * (double)out;
+    mx = fmax(mx, fabs((double)out));
+  }
+}
+
+// Finish the row of one point.  acc is its (partial) stencil value, xc and bv
+// its x and b entries.  Interior points, Dirichlet points (identity rows) and
+// points no other macro shares are finished here; shared non-Dirichlet points
+// get their partial row for the exchange.  Norm partials count each unique
+// DoF once (Dirichlet DoFs on shared primitives only in their owner).
+template <typename T, int DIM, int MODE>
+__device__ __forceinline__ void finish(const MacroDev& M, const WTab<T> W, int mask, T acc, T xc, T bv, T omega,
+                                       T* yp, double& ss, double& mx) {
+  constexpr int FM = full_mask(DIM);
+  constexpr StencilTable ST = stencil_table(DIM);
+  const bool full = mask == FM;
+  const bool dir = !full && ((M.dir_mask >> mask) & 1);
+  const bool shared = !full && ((M.shared_mask >> mask) & 1);
+  if (dir) {
+    const T out = MODE == kResidual ? bv - xc : (MODE == kNormB ? bv : xc);
+    if (MODE != kNormB) st(yp, out);
+    if ((M.own_mask >> mask) & 1) accum<T, MODE>(ss, mx, out, xc);
+  } else if (full || !shared) {
+    T out;
+    if (MODE == kApply || MODE == kApplyDot) out = acc;
+    else if (MODE == kJacobi) out = fma(omega * (full ? Prec<T>::invd(M) : T(1) / W[mask][ST.centre]), bv - acc, xc);
+    else if (MODE == kResidual) out = bv - acc;
+    else out = bv;
+    if (MODE != kNormB) st(yp, out);
+    accum<T, MODE>(ss, mx, out, xc);
+  } else if (MODE != kNormB) {
+    st(yp, acc);
+  }
+}
+
+// Argument tables are read-only for the whole launch: reading them through
+// the constant address space lets the compiler use scalar loads, so the
+// request's arguments stay in scalar registers as a by-value argument does.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T* as_const(const T* p) {
+  return (const __attribute__((address_space(4))) T*)p;
+}
+
+__device__ __forceinline__ int find_seg_c(const int32_t* wg0, int nseg, int g) {
+  const auto* w = as_const(wg0);
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (w[mid] <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Resolves workgroup g of a launch to its request's arguments and the
+// workgroup index inside that request.
+template <class A>
+__device__ __forceinline__ int resolve(const Launch<A>& L, int g, A& a) {
+  if (L.nseg == 0) {
+    a = L.one;
+    return g;
+  }
+  const int r = find_seg_c(L.wg0, L.nseg, g);
+#if defined(__HIP_DEVICE_COMPILE__)
+  a = as_const(L.many)[r];
+#else
+  a = L.many[r];  // the host pass only type-checks device code
+#endif
+  return g - as_const(L.wg0)[r];
+}
+
+template <int DIM>
+__device__ __forceinline__ int64_t lidx(int N, int x, int y, int z) {
+  return DIM == 2 ? idx2(N, x, y) : idx3(N, x, y, z);
+}
+
+// Restriction r_c = P^T r_f on one macro: a coarse point P gathers the fine
+// point 2P (weight 1) and the fine points 2P + d for the stencil offsets d
+// (weight 1/2) — the fine points whose interpolation uses P — counting only
+// fine points this macro owns, so that the later exchange sums each fine DoF
+// once.  Dirichlet fine points are skipped.
+// Segment and macro records are read-only for the launch: read them through
+// the constant address space (scalar loads, scalar registers).
+__device__ __forceinline__ Tile load_seg(const Tile* segs, int si) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return as_const(segs)[si];
+#else
+  return segs[si];
+#endif
+}
+
+struct MacroC {
+  int64_t base;
+  int32_t N;
+  uint16_t own_mask, dir_mask;
+};
+
+__device__ __forceinline__ MacroC load_macro(const MacroDev* md, int m) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const auto* p = as_const(md) + m;
+  return MacroC{p->base, p->N, p->own_mask, p->dir_mask};
+#else
+  return MacroC{md[m].base, md[m].N, md[m].own_mask, md[m].dir_mask};
+#endif
+}
+
+template <typename T, int DIM>
+__device__ __forceinline__ void restrict_point(const TransferArgs<T>& a, int macro, int x, int y, int z) {
+  constexpr StencilTable ST = stencil_table(DIM);
+  constexpr int full = DIM == 2 ? 7 : 15;
+  const MacroC C = load_macro(a.mdc, macro);
+  const MacroC F = load_macro(a.mdf, macro);
+  const int Nc = C.N, Nf = F.N;
+  const bool live = x + y + z <= Nc;
+  // branch-free: every lane takes all offsets; fine points outside the macro
+  // read the centre instead and contribute nothing
+  T acc = T(0);
+#pragma unroll
+  for (int s = 0; s < ST.n; ++s) {
+    const int fx = 2 * x + ST.off[s][0], fy = 2 * y + ST.off[s][1], fz = DIM == 3 ? 2 * z + ST.off[s][2] : 0;
+    const bool in = live && fx >= 0 && fy >= 0 && fz >= 0 && fx + fy + fz <= Nf;
+    const int mask = support_mask(DIM, Nf, fx, fy, fz);
+    const bool owned = mask == full || ((F.own_mask >> mask) & 1);
+    const bool dir = mask != full && ((F.dir_mask >> mask) & 1);
+    const bool use = in && owned && !dir;
+    const int64_t i = in ? lidx<DIM>(Nf, fx, fy, fz) : 0;
+    const T r = a.src[F.base + i];
+    const T w = s == ST.centre ? T(1) : T(0.5);
+    acc += use ? w * r : T(0);
+  }
+  if (live) a.dst[C.base + lidx<DIM>(Nc, x, y, z)] = acc;
+}
+template <typename T, int DIM>
+__device__ __forceinline__ void restrict_segment(const TransferArgs<T>& a, const Tile sg) {
+  restrict_point<T, DIM>(a, sg.macro, sg.x0 + (int)(threadIdx.x & (kWave - 1)), sg.y0, DIM == 3 ? sg.z : 0);
+}
+
+// x_f += P e_c: even fine points take the coarse value, the others the mean
+// of the two coarse endpoints of the coarse micro-edge they bisect; the
+// edge direction follows from the coordinate parities.  Dirichlet points are
+// left unchanged.
+template <typename T, int DIM>
+__device__ __forceinline__ void prolong_point(const TransferArgs<T>& a, int macro, int x, int y, int z) {
+  constexpr int full = DIM == 2 ? 7 : 15;
+  const MacroC C = load_macro(a.mdc, macro);
+  const MacroC F = load_macro(a.mdf, macro);
+  const int Nc = C.N, Nf = F.N;
+  const bool live = x + y + z <= Nf;
+  const int mask = support_mask(DIM, Nf, x, y, z);
+  const bool dir = mask != full && ((F.dir_mask >> mask) & 1);
+  // direction s of the coarse micro-edge the point bisects: the parity
+  // pattern, with the middle odd coordinate negated for two or three odd
+  // coordinates ((1,1,0) -> e1 - e2, (1,0,1) -> e1 - e3, (0,1,1) -> e2 - e3,
+  // (1,1,1) -> e1 - e2 + e3); even points have s = 0 and take the coarse
+  // value itself (the two reads coincide)
+  // (lanes past the macro's far face read the coarse point (0, 0, 0))
+  const int xl = live ? x : 0, yl = live ? y : 0, zl = live ? z : 0;
+  const int px = xl & 1, py = yl & 1, pz = zl & 1;
+  const int sx = px;
+  const int sy = (px && py) ? -1 : py;
+  const int sz = (pz && (px ^ py)) ? -1 : pz;
+  const T u = a.src[C.base + lidx<DIM>(Nc, (xl - sx) >> 1, (yl - sy) >> 1, (zl - sz) >> 1)];
+  const T v = a.src[C.base + lidx<DIM>(Nc, (xl + sx) >> 1, (yl + sy) >> 1, (zl + sz) >> 1)];
+  if (live && !dir) a.dst[F.base + lidx<DIM>(Nf, x, y, z)] += T(0.5) * (u + v);
+}
+template <typename T, int DIM>
+__device__ __forceinline__ void prolong_segment(const TransferArgs<T>& a, const Tile sg) {
+  prolong_point<T, DIM>(a, sg.macro, sg.x0 + (int)(threadIdx.x & (kWave - 1)), sg.y0, DIM == 3 ? sg.z : 0);
+}
+
+// First Jacobi sweep of a V-cycle level.  The iterate is zero there, so
+// x' = x + omega D^-1 (b - A x) reduces to omega D^-1 b, with D the diagonal
+// of the row the sweep would finish: the macro's interior centre weight, the
+// partial stencil's centre at a boundary point no other macro shares, the
+// assembled diagonal of a shared DoF (exchange list), and x' = x = 0 at
+// Dirichlet DoFs.  The arithmetic is that of the stencil and exchange
+// kernels with x = 0 (fma(omega d, b - 0, 0)), so the result is bitwise
+// the same, in one pass that reads b once and needs no exchange.
+template <typename T>
+__device__ __forceinline__ T centre_inv(const MacroDev& M, int mask, int full, int centre) {
+  if constexpr (sizeof(T) == 8) return mask == full ? M.inv_diag : 1.0 / M.wm[mask][centre];
+  else return mask == full ? M.inv_diagf : 1.0f / M.wmf[mask][centre];
+}
+
+template <typename T, int DIM>
+__device__ __forceinline__ void jacobi0_point(const Jacobi0Args<T>& a, int macro, int x, int y, int z) {
+  constexpr int full = DIM == 2 ? 7 : 15;
+  constexpr int centre = stencil_table(DIM).centre;
+  const MacroDev& M = a.md[macro];
+  const MacroC C = load_macro(a.md, macro);
+  const int N = C.N;
+  if (x + y + z > N) return;
+  const int mask = support_mask(DIM, N, x, y, z);
+  const bool dir = mask != full && ((C.dir_mask >> mask) & 1);
+  const bool shared = mask != full && !dir && ((M.shared_mask >> mask) & 1);
+  if (shared) return;  // finished by the group part
+  const int64_t i = C.base + lidx<DIM>(N, x, y, z);
+  a.Y[i] = dir ? T(0) : fma(a.omega * centre_inv<T>(M, mask, full, centre), a.B[i], T(0));
+}
+template <typename T, int DIM>
+__device__ __forceinline__ void jacobi0_segment(const Jacobi0Args<T>& a, const Tile sg) {
+  jacobi0_point<T, DIM>(a, sg.macro, sg.x0 + (int)(threadIdx.x & (kWave - 1)), sg.y0, DIM == 3 ? sg.z : 0);
+}
+
+template <int DIM>
+__device__ __forceinline__ int64_t copy_index(const MacroDev& M, const Copy& c) {
+  return M.base + (DIM == 2 ? idx2(M.N, c.x, c.y) : idx3(M.N, c.x, c.y, c.z));
+}
+
+// One DoF shared by several macros and not Dirichlet (exchange list): its
+// copies in Y hold partial rows; sum them in fixed macro order, finish the
+// row and write it to every copy.  Returns the row value; i0 = index of the
+// first copy.
+template <typename T, int DIM, int MODE>
+__device__ __forceinline__ T exchange_row(const GroupArgs<T>& a, int g, int64_t& i0) {
+  const int c0 = a.gptr[g], c1 = a.gptr[g + 1];
+  i0 = copy_index<DIM>(a.md[a.copies[c0].macro], a.copies[c0]);
+  T out;
+  if (MODE == kNormB) {
+    out = a.B[i0];
+  } else {
+    T acc = T(0);
+    for (int c = c0; c < c1; ++c) acc += a.Y[copy_index<DIM>(a.md[a.copies[c].macro], a.copies[c])];
+    if (MODE == kApply || MODE == kApplyDot) out = acc;
+    else if (MODE == kJacobi) out = fma(a.omega * Prec<T>::ginv(a.ginv, a.ginvf, g), a.B[i0] - acc, a.X[i0]);
+    else out = a.B[i0] - acc;
+    for (int c = c0; c < c1; ++c) a.Y[copy_index<DIM>(a.md[a.copies[c].macro], a.copies[c])] = out;
+  }
+  return out;
+}
+
+// One macro-boundary DoF (all-groups list): y = the sum of x over its copies
+// (0 at Dirichlet DoFs), written to every copy (in place allowed).
+template <typename T, int DIM>
+__device__ __forceinline__ void iface_sum_row(const GroupArgs<T>& a, int g) {
+  const int c0 = a.gptr[g], c1 = a.gptr[g + 1];
+  const bool dir = a.gflag[g] & 1;
+  T out = T(0);
+  if (!dir)
+    for (int c = c0; c < c1; ++c) out += a.X[copy_index<DIM>(a.md[a.copies[c].macro], a.copies[c])];
+  for (int c = c0; c < c1; ++c) a.Y[copy_index<DIM>(a.md[a.copies[c].macro], a.copies[c])] = out;
+}
+
+// Coarse direct solve, unknown i, one wavefront (lane = its lane):
+// x(copies of i) = sum_j Ainv[i][j] b(first copy of j).
+template <typename T>
+__device__ __forceinline__ void coarse_row(const CoarseArgs<T>& a, int i, int lane) {
+  T acc = T(0);
+  for (int j = lane; j < a.n; j += kWave) acc = fma(a.Ainv[(int64_t)i * a.n + j], a.B[a.first[j]], acc);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+  for (int c = a.cptr[i] + lane; c < a.cptr[i + 1]; c += kWave) a.X[a.cidx[c]] = acc;
+}
+
+// The zero-iterate Jacobi row of shared non-Dirichlet DoF g (exchange list),
+// written to every copy.
+template <typename T, int DIM>
+__device__ __forceinline__ void jacobi0_group(const Jacobi0Args<T>& a, int g) {
+  const int c0 = a.gptr[g], c1 = a.gptr[g + 1];
+  const Copy& f = a.copies[c0];
+  const MacroDev& M0 = a.md[f.macro];
+  const T b = a.B[M0.base + lidx<DIM>(M0.N, f.x, f.y, f.z)];
+  T d;
+  if constexpr (sizeof(T) == 8) d = a.ginv[g];
+  else d = a.ginvf[g];
+  const T out = fma(a.omega * d, b, T(0));
+  for (int c = c0; c < c1; ++c) {
+    const Copy& k = a.copies[c];
+    const MacroDev& Mk = a.md[k.macro];
+    a.Y[Mk.base + lidx<DIM>(Mk.N, k.x, k.y, k.z)] = out;
+  }
+}
+
+}  // namespace mf

@@ -26,34 +26,18 @@
 #include <hip/hip_runtime.h>
 
 #include "launch.hpp"
+#include "rows.hpp"
 #include "wave.hpp"
 
 namespace mf {
 
 namespace {
 
-template <typename T>
-struct Prec;
-template <>
-struct Prec<double> {
-  static __device__ __forceinline__ double w(const MacroDev& M, int mask, int i) { return M.wm[mask][i]; }
-  static __device__ __forceinline__ double invd(const MacroDev& M) { return M.inv_diag; }
-  static __device__ __forceinline__ double ginv(const double* d, const float*, int g) { return d[g]; }
-};
-template <>
-struct Prec<float> {
-  static __device__ __forceinline__ float w(const MacroDev& M, int mask, int i) { return M.wmf[mask][i]; }
-  static __device__ __forceinline__ float invd(const MacroDev& M) { return M.inv_diagf; }
-  static __device__ __forceinline__ float ginv(const double*, const float* f, int g) { return f[g]; }
-};
 
 using wave::dn1;
 using wave::up1;
 using wave::xcd_wg;
 
-// Ordinary (write-back) stores: partial lines at wave boundaries merge in L2.
-template <typename T>
-__device__ __forceinline__ void st(T* p, T v) { *p = v; }
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -83,11 +67,6 @@ struct Tile2<float> {
   static constexpr int H = kTileH2F, U = kRingU2F;
 };
 
-// The wave's copy of its macro's partial stencils lives in LDS, so that the
-// per-lane lookups of boundary lanes are LDS reads and never wait on the
-// vector-memory counter that paces the row loads in flight.
-template <typename T>
-using WTab = T (*)[16];
 
 // Copies the 16 x 16 partial-stencil table of macro M into W with `nthreads`
 // threads starting at `first` (a wave or the whole workgroup).
@@ -97,63 +76,8 @@ __device__ __forceinline__ void load_wtab(const MacroDev& M, WTab<T> W, int firs
     if (i >= 0) W[i >> 4][i & 15] = Prec<T>::w(M, i >> 4, i & 15);
 }
 
-// Partial stencil sum for a point with support `mask`: neighbours outside
-// the macro (whose values in v are clamped stand-ins) are dropped by
-// selects, so the code is branch-free.
-template <typename T, int DIM>
-__device__ __forceinline__ T partial_sum(const WTab<T> W, int mask, int N, int x, int y, int z, const T* v) {
-  constexpr StencilTable ST = stencil_table(DIM);
-  T acc = T(0);
-#pragma unroll
-  for (int o = 0; o < ST.n; ++o) {
-    const int nx = x + ST.off[o][0], ny = y + ST.off[o][1], nz = z + ST.off[o][2];
-    const bool in = nx >= 0 && ny >= 0 && nz >= 0 && nx + ny + nz <= N;
-    acc = fma(W[mask][o], in ? v[o] : T(0), acc);
-  }
-  return acc;
-}
 
-// Finish the row of one point.  acc is its (partial) stencil value, xc and bv
-// its x and b entries.  Interior points, Dirichlet points (identity rows) and
-// points no other macro shares are finished here; shared non-Dirichlet points
-// get their partial row for the exchange.  Norm partials count each unique
-// DoF once (Dirichlet DoFs on shared primitives only in their owner).
-// Norm / dot partials of one finished row value `out` (xc = the point's x).
-template <typename T, int MODE>
-__device__ __forceinline__ void accum(double& ss, double& mx, T out, T xc) {
-  if (MODE == kResidual || MODE == kNormB) {
-    ss += (double)out * (double)out;
-    mx = fmax(mx, fabs((double)out));
-  } else if (MODE == kApplyDot) {
-    ss += (double)xc * (double)out;
-    mx = fmax(mx, fabs((double)out));
-  }
-}
 
-template <typename T, int DIM, int MODE>
-__device__ __forceinline__ void finish(const MacroDev& M, const WTab<T> W, int mask, T acc, T xc, T bv, T omega,
-                                       T* yp, double& ss, double& mx) {
-  constexpr int FM = full_mask(DIM);
-  constexpr StencilTable ST = stencil_table(DIM);
-  const bool full = mask == FM;
-  const bool dir = !full && ((M.dir_mask >> mask) & 1);
-  const bool shared = !full && ((M.shared_mask >> mask) & 1);
-  if (dir) {
-    const T out = MODE == kResidual ? bv - xc : (MODE == kNormB ? bv : xc);
-    if (MODE != kNormB) st(yp, out);
-    if ((M.own_mask >> mask) & 1) accum<T, MODE>(ss, mx, out, xc);
-  } else if (full || !shared) {
-    T out;
-    if (MODE == kApply || MODE == kApplyDot) out = acc;
-    else if (MODE == kJacobi) out = fma(omega * (full ? Prec<T>::invd(M) : T(1) / W[mask][ST.centre]), bv - acc, xc);
-    else if (MODE == kResidual) out = bv - acc;
-    else out = bv;
-    if (MODE != kNormB) st(yp, out);
-    accum<T, MODE>(ss, mx, out, xc);
-  } else if (MODE != kNormB) {
-    st(yp, acc);
-  }
-}
 
 // Interior finish of one row value (full stencil, interior point).
 template <typename T, int MODE>
@@ -513,41 +437,8 @@ __device__ __forceinline__ void pencil3d(const int x0, const int y0, const int z
   }
 }
 
-// Argument tables are read-only for the whole launch: reading them through
-// the constant address space lets the compiler use scalar loads, so the
-// request's arguments stay in scalar registers as a by-value argument does.
-template <class T>
-__device__ __forceinline__ const __attribute__((address_space(4))) T* as_const(const T* p) {
-  return (const __attribute__((address_space(4))) T*)p;
-}
 
-__device__ __forceinline__ int find_seg_c(const int32_t* wg0, int nseg, int g) {
-  const auto* w = as_const(wg0);
-  int lo = 0, hi = nseg - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (w[mid] <= g) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
 
-// Resolves workgroup g of a launch to its request's arguments and the
-// workgroup index inside that request.
-template <class A>
-__device__ __forceinline__ int resolve(const Launch<A>& L, int g, A& a) {
-  if (L.nseg == 0) {
-    a = L.one;
-    return g;
-  }
-  const int r = find_seg_c(L.wg0, L.nseg, g);
-#if defined(__HIP_DEVICE_COMPILE__)
-  a = as_const(L.many)[r];
-#else
-  a = L.many[r];  // the host pass only type-checks device code
-#endif
-  return g - as_const(L.wg0)[r];
-}
 
 // Whether a wave tile has output points on its macro's boundary (x = 0,
 // y = 0, z = 0 or the far face x + y + z = N).
@@ -625,10 +516,6 @@ __global__ __launch_bounds__(kWG) void stencil_kernel(const Launch<StencilArgs<T
 }
 
 // ------------------------------------------------------------------ exchange
-template <int DIM>
-__device__ __forceinline__ int64_t copy_index(const MacroDev& M, const Copy& c) {
-  return M.base + (DIM == 2 ? idx2(M.N, c.x, c.y) : idx3(M.N, c.x, c.y, c.z));
-}
 
 // One DoF shared by several macros and not Dirichlet: its copies hold
 // partial rows (written by stencil_kernel); sum them in fixed macro order,
@@ -640,19 +527,8 @@ __global__ __launch_bounds__(kIfaceWG) void exchange_kernel(const Launch<GroupAr
   const int g = blk * kIfaceWG + threadIdx.x;
   double ss = 0.0, mx = 0.0;
   if (g < a.ngroups) {
-    const int c0 = a.gptr[g], c1 = a.gptr[g + 1];
-    const int64_t i0 = copy_index<DIM>(a.md[a.copies[c0].macro], a.copies[c0]);
-    T out;
-    if (MODE == kNormB) {
-      out = a.B[i0];
-    } else {
-      T acc = T(0);
-      for (int c = c0; c < c1; ++c) acc += a.Y[copy_index<DIM>(a.md[a.copies[c].macro], a.copies[c])];
-      if (MODE == kApply || MODE == kApplyDot) out = acc;
-      else if (MODE == kJacobi) out = fma(a.omega * Prec<T>::ginv(a.ginv, a.ginvf, g), a.B[i0] - acc, a.X[i0]);
-      else out = a.B[i0] - acc;
-      for (int c = c0; c < c1; ++c) a.Y[copy_index<DIM>(a.md[a.copies[c].macro], a.copies[c])] = out;
-    }
+    int64_t i0;
+    const T out = exchange_row<T, DIM, MODE>(a, g, i0);
     accum<T, MODE>(ss, mx, out, MODE == kApplyDot ? a.X[i0] : T(0));
   }
   if (has_partials(MODE) && a.part != nullptr) {
@@ -686,18 +562,14 @@ __global__ __launch_bounds__(kIfaceWG) void iface_kernel(const Launch<GroupArgs<
   const int blk = resolve(L, (int)blockIdx.x, a);
   const int g = blk * kIfaceWG + threadIdx.x;
   if (g >= a.ngroups) return;
-  const int c0 = a.gptr[g], c1 = a.gptr[g + 1];
-  const bool dir = a.gflag[g] & 1;
   if (MODE == kDirichletSet) {
-    if (!dir) return;
+    const int c0 = a.gptr[g], c1 = a.gptr[g + 1];
+    if (!(a.gflag[g] & 1)) return;
     const T v = a.B ? a.B[copy_index<DIM>(a.md[a.copies[c0].macro], a.copies[c0])] : T(0);
     for (int c = c0; c < c1; ++c) a.Y[copy_index<DIM>(a.md[a.copies[c].macro], a.copies[c])] = v;
     return;
   }
-  T out = T(0);
-  if (!dir)
-    for (int c = c0; c < c1; ++c) out += a.X[copy_index<DIM>(a.md[a.copies[c].macro], a.copies[c])];
-  for (int c = c0; c < c1; ++c) a.Y[copy_index<DIM>(a.md[a.copies[c].macro], a.copies[c])] = out;
+  iface_sum_row<T, DIM>(a, g);
 }
 
 // result = (sum of part[0, np), max of part[np, 2 np)) in a fixed order; one

@@ -1,0 +1,297 @@
+// The bottom of a V-cycle in one workgroup (gfx950).
+//
+// Below a few thousand points per level, every step of the cycle (stencil
+// pass, exchange, transfer, fill, coarse solve) takes about the same time
+// whatever its size: a chain of dependent loads plus the launch, about a
+// dozen launches per level and cycle.  vcycle_tail_kernel runs the coarse
+// solve and the levels just above it (kargs.hpp: kTailLevels,
+// kTailMaxPoints) with one workgroup of 16 waves, a barrier between steps,
+// and the data in that CU's caches.  The steps and their order are those of
+// the multi-launch cycle (pre-smoothing from the zero iterate, residual,
+// restriction and its exchange, recursion, prolongation, post-smoothing),
+// and every point's arithmetic is the same as in the stencil, exchange and
+// transfer kernels: stencil rows are the partial-stencil sum over the 7 / 15
+// offsets in table order, which for interior points is the walk's FMA chain,
+// so results match the multi-launch cycle up to the sign of zero sums.
+//
+// One workgroup per request: a batched launch gives each member its own.
+
+#include <hip/hip_runtime.h>
+
+#include <utility>
+
+#include "launch.hpp"
+#include "rows.hpp"
+
+namespace mf {
+
+namespace {
+
+constexpr int kTailWaves = kTailWG / kWave;
+
+int check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(MF_EDEVICE, hipGetErrorString(e));
+  return MF_OK;
+}
+
+template <typename T>
+__device__ __forceinline__ WTab<T> wtab_of(const MacroDev& M) {
+  if constexpr (sizeof(T) == 8) return const_cast<WTab<T>>(M.wm);
+  else return const_cast<WTab<T>>(M.wmf);
+}
+
+// Every storage point of a level, packed: thread t takes points t,
+// t + kTailWG, ... and decodes each storage index into its macro and lattice
+// point (all macros of a level have the same side N and point count).  The
+// level's row segments would leave most lanes idle in 3D, where rows of
+// small levels are a few points long.
+template <int DIM, class Fn>
+__device__ __forceinline__ void for_points(int N, int nmac, Fn&& fn) {
+  const int P = (int)macro_points(DIM, N);
+  const int n = P * nmac;
+  for (int i = (int)threadIdx.x; i < n; i += kTailWG) {
+    const int m = i / P;
+    int r = i - m * P;
+    int z = 0, S = N;
+    if (DIM == 3) {
+      // slice z holds (S + 1)(S + 2) / 2 points, S = N - z
+      for (int sz = (S + 1) * (S + 2) / 2; r >= sz; sz = (S + 1) * (S + 2) / 2) {
+        r -= sz;
+        --S;
+        ++z;
+      }
+    }
+    int y = 0;
+    for (int len = S + 1; r >= len; --len) {  // row y of the slice holds S + 1 - y points
+      r -= len;
+      ++y;
+    }
+    fn(m, r, y, z);
+  }
+}
+
+// One stencil pass of mode MODE over every point of the level: interior,
+// Dirichlet and unshared rows finished, shared rows left as partial rows.
+template <typename T, int DIM, int MODE>
+__device__ __forceinline__ void tail_stencil(const TailLevel<T>& F, const T* X, T* Y, const T* B, T omega) {
+  constexpr StencilTable ST = stencil_table(DIM);
+  for_points<DIM>(F.N, F.nmac, [&](int m, int x, int y, int z) {
+    const MacroDev& M = F.md[m];
+    const int N = F.N;
+    const int64_t i = M.base + lidx<DIM>(N, x, y, z);
+    T v[ST.n];
+#pragma unroll
+    for (int o = 0; o < ST.n; ++o) {
+      const int nx = x + ST.off[o][0], ny = y + ST.off[o][1], nz = z + ST.off[o][2];
+      const bool in = nx >= 0 && ny >= 0 && nz >= 0 && nx + ny + nz <= N;
+      // neighbours outside the macro read the point itself (a valid index);
+      // partial_sum drops them
+      v[o] = X[in ? M.base + lidx<DIM>(N, nx, ny, nz) : i];
+    }
+    const int mask = support_mask(DIM, N, x, y, z);
+    const WTab<T> W = wtab_of<T>(M);
+    const T acc = partial_sum<T, DIM>(W, mask, N, x, y, z, v);
+    double ss = 0.0, mx = 0.0;
+    finish<T, DIM, MODE>(M, W, mask, acc, v[ST.centre], MODE != kApply ? B[i] : T(0), omega, Y + i, ss, mx);
+  });
+}
+
+// The exchange of that pass: shared non-Dirichlet DoFs, one per thread.
+template <typename T, int DIM, int MODE>
+__device__ __forceinline__ void tail_exchange(const TailLevel<T>& F, const T* X, T* Y, const T* B, T omega) {
+  GroupArgs<T> g{};
+  g.ngroups = F.nx;
+  g.gptr = F.xptr;
+  g.copies = F.xcopies;
+  g.ginv = F.xinv;
+  g.ginvf = F.xinvf;
+  g.md = F.md;
+  g.X = X;
+  g.Y = Y;
+  g.B = B;
+  g.omega = omega;
+  for (int k = (int)threadIdx.x; k < F.nx; k += kTailWG) {
+    int64_t i0;
+    exchange_row<T, DIM, MODE>(g, k, i0);
+  }
+}
+
+template <typename T, int DIM, int MODE>
+__device__ __forceinline__ void tail_pass(const TailLevel<T>& F, const T* X, T* Y, T omega) {
+  tail_stencil<T, DIM, MODE>(F, X, Y, F.b, omega);
+  __syncthreads();
+  tail_exchange<T, DIM, MODE>(F, X, Y, F.b, omega);
+  __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ void tail_fill(T* x, int64_t n) {
+  for (int64_t i = threadIdx.x; i < n; i += kTailWG) x[i] = T(0);
+}
+
+// `sweeps` Jacobi sweeps ping-ponging x <-> t, as jacobi_sweeps does; from
+// zero, as jacobi_sweeps_from_zero (first sweep omega D^-1 b into t).
+template <typename T, int DIM>
+__device__ __forceinline__ void tail_jacobi(const TailLevel<T>& F, int sweeps, T omega, bool from_zero) {
+  if (from_zero && sweeps == 0) {
+    tail_fill(F.x, F.storage);
+    __syncthreads();
+    return;
+  }
+  T* cur = F.x;
+  T* oth = F.t;
+  int i = 0;
+  if (from_zero) {
+    Jacobi0Args<T> ja{};
+    ja.nseg = F.nseg;
+    ja.segs = F.segs;
+    ja.ngroups = F.nx;
+    ja.gptr = F.xptr;
+    ja.copies = F.xcopies;
+    ja.ginv = F.xinv;
+    ja.ginvf = F.xinvf;
+    ja.md = F.md;
+    ja.B = F.b;
+    ja.Y = F.t;
+    ja.omega = omega;
+    for_points<DIM>(F.N, F.nmac, [&](int m, int x, int y, int z) { jacobi0_point<T, DIM>(ja, m, x, y, z); });
+    for (int g = (int)threadIdx.x; g < F.nx; g += kTailWG) jacobi0_group<T, DIM>(ja, g);
+    __syncthreads();
+    cur = F.t;
+    oth = F.x;
+    i = 1;
+  }
+  for (; i < sweeps; ++i) {
+    tail_pass<T, DIM, kJacobi>(F, cur, oth, omega);
+    T* s = cur;
+    cur = oth;
+    oth = s;
+  }
+  if (cur != F.x) {
+    for (int64_t k = threadIdx.x; k < F.storage; k += kTailWG) F.x[k] = cur[k];
+    __syncthreads();
+  }
+}
+
+// The request's record, read in place (constant address space: scalar
+// loads) rather than copied, so that the per-level records indexed by a
+// loop counter need no private memory.
+template <class A>
+__device__ __forceinline__ auto resolve_ref(const Launch<A>& L, int g) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  if (L.nseg == 0) return as_const(&L.one);
+  return as_const(L.many) + find_seg_c(L.wg0, L.nseg, g);
+#else
+  (void)g;
+  return L.nseg == 0 ? &L.one : L.many;  // the host pass only type-checks device code
+#endif
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(kTailWG) void vcycle_tail_kernel(const Launch<TailArgs<T>> L) {
+  const auto* a = resolve_ref(L, (int)blockIdx.x);
+  const int nlev = a->nlev, pre = a->pre, post = a->post;
+  const T omega = a->omega;
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int lane = (int)threadIdx.x & (kWave - 1);
+  // descent: levels lc + nlev - 1 .. lc + 1 (restriction: one coarse point per thread)
+  for (int k = nlev - 1; k >= 1; --k) {
+    const TailLevel<T> F = a->lv[k];
+    const TailLevel<T> C = a->lv[k - 1];
+    tail_jacobi<T, DIM>(F, pre, omega, true);
+    tail_pass<T, DIM, kResidual>(F, F.x, F.t, T(0));
+    const TransferArgs<T> ta{C.segs, C.nseg, 0, C.md, F.md, F.t, C.b};
+    for_points<DIM>(C.N, C.nmac, [&](int m, int x, int y, int z) { restrict_point<T, DIM>(ta, m, x, y, z); });
+    __syncthreads();
+    GroupArgs<T> ga{};
+    ga.ngroups = C.ng;
+    ga.gptr = C.gptr;
+    ga.copies = C.copies;
+    ga.gflag = C.gflag;
+    ga.md = C.md;
+    ga.X = C.b;
+    ga.Y = C.b;
+    for (int g = (int)threadIdx.x; g < C.ng; g += kTailWG) iface_sum_row<T, DIM>(ga, g);
+    __syncthreads();
+  }
+  // coarse level: x = 0, then the dense solve on its unknowns (a wave each)
+  {
+    const CoarseArgs<T> cs = a->coarse;
+    tail_fill(cs.X, a->lv[0].storage);
+    __syncthreads();
+    for (int i = wave; i < cs.n; i += kTailWaves) coarse_row<T>(cs, i, lane);
+    __syncthreads();
+  }
+  // ascent: levels lc + 1 .. lc + nlev - 1
+  for (int k = 1; k < nlev; ++k) {
+    const TailLevel<T> F = a->lv[k];
+    const TailLevel<T> C = a->lv[k - 1];
+    const TransferArgs<T> ta{F.segs, F.nseg, 0, C.md, F.md, C.x, F.x};
+    for_points<DIM>(F.N, F.nmac, [&](int m, int x, int y, int z) { prolong_point<T, DIM>(ta, m, x, y, z); });
+    __syncthreads();
+    tail_jacobi<T, DIM>(F, post, omega, false);
+  }
+}
+
+template <typename T>
+void run_tail(int dim, const Launch<TailArgs<T>>& l, hipStream_t s) {
+  if (dim == 2) hipLaunchKernelGGL((vcycle_tail_kernel<T, 2>), dim3(l.nwg), dim3(kTailWG), 0, s, l);
+  else hipLaunchKernelGGL((vcycle_tail_kernel<T, 3>), dim3(l.nwg), dim3(kTailWG), 0, s, l);
+}
+
+template <class A>
+Launch<A> single(const A& a, int nwg) {
+  Launch<A> l{};
+  l.one = a;
+  l.nseg = 0;
+  l.nwg = nwg;
+  return l;
+}
+
+template <class A>
+Launch<A> batched(const BatchOp& op, const char* table) {
+  Launch<A> l{};
+  l.many = (const A*)(table + op.args_off);
+  l.wg0 = (const int32_t*)(table + op.wg0_off);
+  l.nseg = op.nseg;
+  l.nwg = op.nwg;
+  return l;
+}
+
+}  // namespace
+
+template <typename T>
+TailArgs<T> tail_args(const mf_mesh* m, int lc, int nlev, int pre, int post, double omega,
+                      const std::vector<void*>& b, const std::vector<void*>& x, const std::vector<void*>& t) {
+  TailArgs<T> a{};
+  a.nlev = nlev;
+  a.pre = pre;
+  a.post = post;
+  a.omega = (T)omega;
+  a.coarse = coarse_args<T>(m->levels[lc], b[lc], x[lc]);
+  for (int k = 0; k < nlev; ++k) a.lv[k] = tail_level<T>(m->levels[lc + k], b[lc + k], x[lc + k], t[lc + k]);
+  return a;
+}
+template TailArgs<double> tail_args<double>(const mf_mesh*, int, int, int, int, double, const std::vector<void*>&,
+                                            const std::vector<void*>&, const std::vector<void*>&);
+template TailArgs<float> tail_args<float>(const mf_mesh*, int, int, int, int, double, const std::vector<void*>&,
+                                          const std::vector<void*>&, const std::vector<void*>&);
+
+int launch_vcycle_tail(const mf_mesh* m, int lc, int nlev, int dtype, int pre, int post, double omega,
+                       const std::vector<void*>& b, const std::vector<void*>& x, const std::vector<void*>& t,
+                       hipStream_t s) {
+  if (nlev < 1 || nlev > kTailLevels) return set_error(MF_EINVAL, "tail levels out of range");
+  if (dtype == MF_F64) run_tail<double>(m->dim, single(tail_args<double>(m, lc, nlev, pre, post, omega, b, x, t), 1), s);
+  else run_tail<float>(m->dim, single(tail_args<float>(m, lc, nlev, pre, post, omega, b, x, t), 1), s);
+  return check_launch();
+}
+
+int launch_tail_batch(const BatchOp& op, const char* table, hipStream_t s) {
+  if (op.nwg <= 0) return MF_OK;
+  if (op.dtype == MF_F64) run_tail<double>(op.dim, batched<TailArgs<double>>(op, table), s);
+  else run_tail<float>(op.dim, batched<TailArgs<float>>(op, table), s);
+  return check_launch();
+}
+
+}  // namespace mf

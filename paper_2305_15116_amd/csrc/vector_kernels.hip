@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include "launch.hpp"
+#include "rows.hpp"
 
 namespace mf {
 
@@ -29,10 +30,6 @@ __device__ __forceinline__ uint64_t splitmix(uint64_t z) {
   return z ^ (z >> 31);
 }
 
-template <int DIM>
-__device__ __forceinline__ int64_t lidx(int N, int x, int y, int z) {
-  return DIM == 2 ? idx2(N, x, y) : idx3(N, x, y, z);
-}
 
 // x = 2u - 1 with u from the hash chained over (seed, sorted key pairs).
 template <typename T, int DIM>
@@ -72,98 +69,10 @@ __global__ __launch_bounds__(kWG) void fill_random_kernel(const Tile* __restrict
   X[M.base + lidx<DIM>(N, x, y, z)] = (T)(2.0 * u - 1.0);
 }
 
-// Argument tables are read-only for the whole launch: reading them through
-// the constant address space lets the compiler use scalar loads, so the
-// request's arguments stay in scalar registers as a by-value argument does.
-template <class T>
-__device__ __forceinline__ const __attribute__((address_space(4))) T* as_const(const T* p) {
-  return (const __attribute__((address_space(4))) T*)p;
-}
 
-__device__ __forceinline__ int find_seg_c(const int32_t* wg0, int nseg, int g) {
-  const auto* w = as_const(wg0);
-  int lo = 0, hi = nseg - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (w[mid] <= g) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
 
-// Resolves workgroup g of a launch to its request's arguments and the
-// workgroup index inside that request.
-template <class A>
-__device__ __forceinline__ int resolve(const Launch<A>& L, int g, A& a) {
-  if (L.nseg == 0) {
-    a = L.one;
-    return g;
-  }
-  const int r = find_seg_c(L.wg0, L.nseg, g);
-#if defined(__HIP_DEVICE_COMPILE__)
-  a = as_const(L.many)[r];
-#else
-  a = L.many[r];  // the host pass only type-checks device code
-#endif
-  return g - as_const(L.wg0)[r];
-}
 
-// Restriction r_c = P^T r_f on one macro: a coarse point P gathers the fine
-// point 2P (weight 1) and the fine points 2P + d for the stencil offsets d
-// (weight 1/2) — the fine points whose interpolation uses P — counting only
-// fine points this macro owns, so that the later exchange sums each fine DoF
-// once.  Dirichlet fine points are skipped.
-// Segment and macro records are read-only for the launch: read them through
-// the constant address space (scalar loads, scalar registers).
-__device__ __forceinline__ Tile load_seg(const Tile* segs, int si) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  return as_const(segs)[si];
-#else
-  return segs[si];
-#endif
-}
-struct MacroC {
-  int64_t base;
-  int32_t N;
-  uint16_t own_mask, dir_mask;
-};
-__device__ __forceinline__ MacroC load_macro(const MacroDev* md, int m) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  const auto* p = as_const(md) + m;
-  return MacroC{p->base, p->N, p->own_mask, p->dir_mask};
-#else
-  return MacroC{md[m].base, md[m].N, md[m].own_mask, md[m].dir_mask};
-#endif
-}
 
-template <typename T, int DIM>
-__device__ __forceinline__ void restrict_segment(const TransferArgs<T>& a, const Tile sg) {
-  constexpr StencilTable ST = stencil_table(DIM);
-  constexpr int full = DIM == 2 ? 7 : 15;
-  const MacroC C = load_macro(a.mdc, sg.macro);
-  const MacroC F = load_macro(a.mdf, sg.macro);
-  const int Nc = C.N, Nf = F.N;
-  const int x = sg.x0 + (threadIdx.x & (kWave - 1));
-  const int y = sg.y0, z = DIM == 3 ? sg.z : 0;
-  const bool live = x + y + z <= Nc;
-  // branch-free: every lane takes all offsets; fine points outside the macro
-  // read the centre instead and contribute nothing
-  T acc = T(0);
-#pragma unroll
-  for (int s = 0; s < ST.n; ++s) {
-    const int fx = 2 * x + ST.off[s][0], fy = 2 * y + ST.off[s][1], fz = DIM == 3 ? 2 * z + ST.off[s][2] : 0;
-    const bool in = live && fx >= 0 && fy >= 0 && fz >= 0 && fx + fy + fz <= Nf;
-    const int mask = support_mask(DIM, Nf, fx, fy, fz);
-    const bool owned = mask == full || ((F.own_mask >> mask) & 1);
-    const bool dir = mask != full && ((F.dir_mask >> mask) & 1);
-    const bool use = in && owned && !dir;
-    const int64_t i = in ? lidx<DIM>(Nf, fx, fy, fz) : 0;
-    const T r = a.src[F.base + i];
-    const T w = s == ST.centre ? T(1) : T(0.5);
-    acc += use ? w * r : T(0);
-  }
-  if (live) a.dst[C.base + lidx<DIM>(Nc, x, y, z)] = acc;
-}
 
 template <typename T, int DIM>
 __global__ __launch_bounds__(kWG) void restrict_kernel(const Launch<TransferArgs<T>> L) {
@@ -177,36 +86,6 @@ __global__ __launch_bounds__(kWG) void restrict_kernel(const Launch<TransferArgs
   }
 }
 
-// x_f += P e_c: even fine points take the coarse value, the others the mean
-// of the two coarse endpoints of the coarse micro-edge they bisect; the
-// edge direction follows from the coordinate parities.  Dirichlet points are
-// left unchanged.
-template <typename T, int DIM>
-__device__ __forceinline__ void prolong_segment(const TransferArgs<T>& a, const Tile sg) {
-  constexpr int full = DIM == 2 ? 7 : 15;
-  const MacroC C = load_macro(a.mdc, sg.macro);
-  const MacroC F = load_macro(a.mdf, sg.macro);
-  const int Nc = C.N, Nf = F.N;
-  const int x = sg.x0 + (threadIdx.x & (kWave - 1));
-  const int y = sg.y0, z = DIM == 3 ? sg.z : 0;
-  const bool live = x + y + z <= Nf;
-  const int mask = support_mask(DIM, Nf, x, y, z);
-  const bool dir = mask != full && ((F.dir_mask >> mask) & 1);
-  // direction s of the coarse micro-edge the point bisects: the parity
-  // pattern, with the middle odd coordinate negated for two or three odd
-  // coordinates ((1,1,0) -> e1 - e2, (1,0,1) -> e1 - e3, (0,1,1) -> e2 - e3,
-  // (1,1,1) -> e1 - e2 + e3); even points have s = 0 and take the coarse
-  // value itself (the two reads coincide)
-  // (lanes past the macro's far face read the coarse point (0, 0, 0))
-  const int xl = live ? x : 0, yl = live ? y : 0, zl = live ? z : 0;
-  const int px = xl & 1, py = yl & 1, pz = zl & 1;
-  const int sx = px;
-  const int sy = (px && py) ? -1 : py;
-  const int sz = (pz && (px ^ py)) ? -1 : pz;
-  const T u = a.src[C.base + lidx<DIM>(Nc, (xl - sx) >> 1, (yl - sy) >> 1, (zl - sz) >> 1)];
-  const T v = a.src[C.base + lidx<DIM>(Nc, (xl + sx) >> 1, (yl + sy) >> 1, (zl + sz) >> 1)];
-  if (live && !dir) a.dst[F.base + lidx<DIM>(Nf, x, y, z)] += T(0.5) * (u + v);
-}
 
 // x_f += P e_c (each wave walks several segments of fine points).
 template <typename T, int DIM>
@@ -221,37 +100,7 @@ __global__ __launch_bounds__(kWG) void prolong_add_kernel(const Launch<TransferA
   }
 }
 
-// First Jacobi sweep of a V-cycle level.  The iterate is zero there, so
-// x' = x + omega D^-1 (b - A x) reduces to omega D^-1 b, with D the diagonal
-// of the row the sweep would finish: the macro's interior centre weight, the
-// partial stencil's centre at a boundary point no other macro shares, the
-// assembled diagonal of a shared DoF (exchange list), and x' = x = 0 at
-// Dirichlet DoFs.  The arithmetic is that of the stencil and exchange
-// kernels with x = 0 (fma(omega d, b - 0, 0)), so the result is bitwise
-// the same, in one pass that reads b once and needs no exchange.
-template <typename T>
-__device__ __forceinline__ T centre_inv(const MacroDev& M, int mask, int full, int centre) {
-  if constexpr (sizeof(T) == 8) return mask == full ? M.inv_diag : 1.0 / M.wm[mask][centre];
-  else return mask == full ? M.inv_diagf : 1.0f / M.wmf[mask][centre];
-}
 
-template <typename T, int DIM>
-__device__ __forceinline__ void jacobi0_segment(const Jacobi0Args<T>& a, const Tile sg) {
-  constexpr int full = DIM == 2 ? 7 : 15;
-  constexpr int centre = stencil_table(DIM).centre;
-  const MacroDev& M = a.md[sg.macro];
-  const MacroC C = load_macro(a.md, sg.macro);
-  const int N = C.N;
-  const int x = sg.x0 + (threadIdx.x & (kWave - 1));
-  const int y = sg.y0, z = DIM == 3 ? sg.z : 0;
-  if (x + y + z > N) return;
-  const int mask = support_mask(DIM, N, x, y, z);
-  const bool dir = mask != full && ((C.dir_mask >> mask) & 1);
-  const bool shared = mask != full && !dir && ((M.shared_mask >> mask) & 1);
-  if (shared) return;  // finished by the group part
-  const int64_t i = C.base + lidx<DIM>(N, x, y, z);
-  a.Y[i] = dir ? T(0) : fma(a.omega * centre_inv<T>(M, mask, full, centre), a.B[i], T(0));
-}
 
 template <typename T, int DIM>
 __global__ __launch_bounds__(kWG) void jacobi0_kernel(const Launch<Jacobi0Args<T>> L) {
@@ -267,20 +116,7 @@ __global__ __launch_bounds__(kWG) void jacobi0_kernel(const Launch<Jacobi0Args<T
     return;
   }
   const int g = (blk - a.nblk_pts) * kWG + (int)threadIdx.x;
-  if (g >= a.ngroups) return;
-  const int c0 = a.gptr[g], c1 = a.gptr[g + 1];
-  const Copy& f = a.copies[c0];
-  const MacroDev& M0 = a.md[f.macro];
-  const T b = a.B[M0.base + lidx<DIM>(M0.N, f.x, f.y, f.z)];
-  T d;
-  if constexpr (sizeof(T) == 8) d = a.ginv[g];
-  else d = a.ginvf[g];
-  const T out = fma(a.omega * d, b, T(0));
-  for (int c = c0; c < c1; ++c) {
-    const Copy& k = a.copies[c];
-    const MacroDev& Mk = a.md[k.macro];
-    a.Y[Mk.base + lidx<DIM>(Mk.N, k.x, k.y, k.z)] = out;
-  }
+  if (g < a.ngroups) jacobi0_group<T, DIM>(a, g);
 }
 
 // Coarse direct solve: x(copies of unknown i) = sum_j Ainv[i][j] b(first copy of j).
@@ -292,11 +128,7 @@ __global__ __launch_bounds__(kWG) void coarse_solve_kernel(const Launch<CoarseAr
   const int i = blk * kWavesPerWG + (threadIdx.x >> 6);
   const int lane = threadIdx.x & (kWave - 1);
   if (i >= a.n) return;
-  T acc = T(0);
-  for (int j = lane; j < a.n; j += kWave) acc = fma(a.Ainv[(int64_t)i * a.n + j], a.B[a.first[j]], acc);
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, kWave);
-  for (int c = a.cptr[i] + lane; c < a.cptr[i + 1]; c += kWave) a.X[a.cidx[c]] = acc;
+  coarse_row<T>(a, i, lane);
 }
 
 // Plain vector kernels: grid-stride loops over each request's nblk blocks.
@@ -595,6 +427,7 @@ int launch_vector_batch(const BatchOp& op, const char* table, hipStream_t s) {
     case kOpPcgDir:
       hipLaunchKernelGGL(pcg_dir_kernel, dim3(op.nwg), dim3(256), 0, s, batched<VecArgs>(op, table));
       return check_launch();
+    case kOpTail: return launch_tail_batch(op, table, s);
     case kOpJacobi0:
       if (op.dtype == MF_F64) run_jacobi0<double>(op.dim, batched<Jacobi0Args<double>>(op, table), s);
       else run_jacobi0<float>(op.dim, batched<Jacobi0Args<float>>(op, table), s);
