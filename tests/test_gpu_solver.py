@@ -97,6 +97,46 @@ def test_random_mesh_against_oracle_solve(mode):
     assert np.abs(xu - uo).max() <= kappa_bound * 1e-10 * max(1.0, np.abs(uo).max())
 
 
+# refinement (modes 0, 1) takes any sweep counts; conjugate gradients (modes
+# 2, 3) needs a symmetric preconditioner, so equal pre- and post-sweeps
+CYCLES = [("strip2d", 6, 0, 2, None, 1), ("strip2d", 6, 1, 1, 1, 0), ("strip2d", 6, 3, 3, None, 3),
+          ("strip2d", 6, 2, 0, 3, 0), ("strip3d", 5, 0, 2, None, 1), ("strip3d", 5, 1, 1, 1, 3),
+          ("strip3d", 5, 3, 2, 3, 0), ("strip3d", 4, 2, 2, 0, 2)]
+
+
+@pytest.mark.parametrize("mesh,L,pre,post,lc,mode", CYCLES)
+def test_cycle_shapes_against_oracle(mesh, L, pre, post, lc, mode):
+    """Odd, zero and unequal sweep counts and other coarse levels: the small
+    levels of these meshes run in the one-workgroup bottom of the cycle, the
+    larger ones as separate launches."""
+    co, ce = W.strip_2d(5) if mesh == "strip2d" else W.strip_3d(3)
+    J, t = W.random_affine(co.shape[1], 4)
+    co = W.apply_affine(co, J, t)
+    m = P.create_macro_mesh(co, ce, L)
+    om = OracleMesh(co, ce, L)
+    s2u = harness.storage_to_unique(P.mesh_dof_keys(m, L), om.keys())
+    s, _ = P.mesh_num_dofs(m, L)
+    b = torch.empty(s, dtype=torch.float64, device="cuda")
+    P.mesh_fill_random(m, L, 41, b)
+    x = torch.zeros_like(b)
+    ws = torch.empty(P.mesh_workspace_bytes(m, L, mode), dtype=torch.uint8, device="cuda")
+    rc, it, rel, sec = P.vcycle_solve(m, L, b, x, ws, mode=mode, pre=pre, post=post, coarse_level=lc, rtol=1e-10,
+                                      max_iter=1000)
+    torch.cuda.synchronize()
+    assert rc == P.MF_OK, (it, rel)
+    bo = om.keyed_random(41)
+    xu = np.zeros(om.n)
+    xs = x.cpu().numpy()
+    assert harness.copies_consistent(xs, s2u)
+    xu[s2u] = xs
+    r = bo - om.spmv(xu)
+    assert np.linalg.norm(r) / np.linalg.norm(bo) <= (1.01 if mode < 2 else 1.5) * 1e-10
+    bnd = om.boundary()
+    assert np.array_equal(xu[bnd], bo[bnd])
+    uo = solve(om, bo, tol=1e-14)
+    assert np.abs(xu - uo).max() <= 1e5 * 1e-10 * max(1.0, np.abs(uo).max())
+
+
 def test_split_solve_equals_single_solve():
     """Checkpoint/resume (iterative refinement): k/2 + k/2 iterations from the saved x equal k
     iterations, bitwise."""
