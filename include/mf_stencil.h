@@ -197,7 +197,8 @@ typedef struct {
   int mode;         /* 0: FP64 V-cycles in iterative refinement; 1: FP32 V-cycles in FP64 iterative
                        refinement; 2: conjugate gradients preconditioned by one FP64 V-cycle per
                        iteration; 3: the same with an FP32 V-cycle (FP64 recurrences) */
-  int pre, post;    /* smoothing sweeps (default 2, 2) */
+  int pre, post;    /* smoothing sweeps (default 2, 2); modes 2, 3 need pre == post (a symmetric
+                       preconditioner), else MF_EINVAL */
   int coarse_level; /* solved directly (default min(2, level)) */
   int max_iter;     /* outer iterations (default 50) */
   double omega;     /* Jacobi weight (default 2/3) */

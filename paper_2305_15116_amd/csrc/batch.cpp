@@ -479,6 +479,8 @@ int batch_create(const mf_solve_opts* opts, int capacity, mf_batch** out) {
   mf_solve_opts o = {1, 2, 2, -1, 50, 2.0 / 3.0, 1e-8};
   if (opts) o = *opts;
   if (o.mode < 0 || o.mode > 3) return set_error(MF_EINVAL, "mode must be 0, 1, 2 or 3");
+  if (mode_pcg(o.mode) && o.pre != o.post)
+    return set_error(MF_EINVAL, "conjugate gradients need a symmetric V-cycle (pre == post)");
   if (o.pre < 0 || o.post < 0 || o.max_iter < 0) return set_error(MF_EINVAL, "bad solver options");
   mf_batch* B = nullptr;
   try {

@@ -350,6 +350,8 @@ int vcycle_solve(const mf_mesh* m, int level, const double* b, double* x, void* 
   mf_solve_opts o = {0, 2, 2, default_coarse(level), 50, 2.0 / 3.0, 1e-10};
   if (opts) o = *opts;
   if (o.mode < 0 || o.mode > 3) return set_error(MF_EINVAL, "mode must be 0, 1, 2 or 3");
+  if (mode_pcg(o.mode) && o.pre != o.post)
+    return set_error(MF_EINVAL, "conjugate gradients need a symmetric V-cycle (pre == post)");
   if (o.pre < 0 || o.post < 0 || o.max_iter < 0 || !(o.rtol >= 0.0))
     return set_error(MF_EINVAL, "bad solver options");
   if (o.coarse_level < 0 || o.coarse_level > level) return set_error(MF_EINVAL, "coarse_level outside [0, level]");

@@ -157,6 +157,26 @@ def test_split_solve_equals_single_solve():
     assert torch.equal(x1, x2)
 
 
+def test_cg_rejects_a_non_symmetric_cycle():
+    co, ce = W.two_triangle_square()
+    m = P.create_macro_mesh(co, ce, 3)
+    s, _ = P.mesh_num_dofs(m, 3)
+    b = torch.ones(s, dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(b)
+    ws = torch.empty(P.mesh_workspace_bytes(m, 3, 2), dtype=torch.uint8, device="cuda")
+    for mode in (2, 3):
+        with pytest.raises(P.MFError) as e:
+            P.vcycle_solve(m, 3, b, x, ws, mode=mode, pre=2, post=1)
+        assert e.value.code == P.MF_EINVAL
+        with pytest.raises(P.MFError) as e:
+            P.batch_create(1, mode=mode, pre=1, post=2)
+        assert e.value.code == P.MF_EINVAL
+    # refinement takes any sweep counts
+    rc, it, rel, _ = P.vcycle_solve(m, 3, b, x, ws, mode=0, pre=2, post=1, rtol=1e-8)
+    torch.cuda.synchronize()
+    assert rc == P.MF_OK and rel <= 1e-8
+
+
 def test_nan_rhs_is_reported():
     co, ce = W.two_triangle_square()
     L = 4
