@@ -481,10 +481,9 @@ int64_t or_assemble(or_mesh* m, int dirichlet) {
   return (int64_t)m->cols.size();
 }
 
-// ---- Variable coefficient (the survey's "on-the-fly stencils" row; the
-// paper notes that varying weights can be computed on the fly, trading
-// memory traffic for computation, comparison of matrix-free and sparse
-// storage).  Operator: a(u, v) = integral of k grad u . grad v with k the P1
+// ---- Variable coefficient (the paper notes that varying weights can be
+// computed on the fly, trading memory traffic for computation, comparison of
+// matrix-free and sparse storage).  Operator: a(u, v) = integral of k grad u . grad v with k the P1
 // interpolant of nodal values; grad u . grad v is constant on a P1 element,
 // so the element matrix is exactly (mean of k over the element's vertices)
 // times the constant-coefficient element matrix.  k is given per unique DoF.
@@ -529,8 +528,9 @@ int64_t or_assemble_varcoef(or_mesh* m, int dirichlet, const double* k) {
   return (int64_t)m->cols.size();
 }
 
-// ---- Blended (non-affine) macros in 2D (the survey's on-the-fly-stencil
-// row: geometry that varies inside a macro, so no two rows share a stencil).
+// ---- Blended (non-affine) macros in 2D (the same remark of the paper on
+// stencils computed on the fly: geometry that varies inside a macro, so no
+// two rows share a stencil).
 // Reading: macro c maps reference coordinates xi (lattice point / N) by
 //   F(xi) = P0 + (P1 - P0) xi1 + (P2 - P0) xi2 + xi0 xi1 xi2 d_c,
 // xi0 = 1 - xi1 - xi2, with a per-macro vector d_c.  The cubic bubble
