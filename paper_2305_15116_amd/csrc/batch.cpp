@@ -167,15 +167,17 @@ void vector_op(PlanBuilder& P, const std::vector<Member*>& ms, int dim, int kind
 // First sweep from a zero iterate: t = omega D^-1 b, as jacobi_sweeps_from_zero.
 template <typename T, class LevelOf>
 void jacobi0_op(PlanBuilder& P, const std::vector<Member*>& ms, int dim, const mf_solve_opts& o, LevelOf lof) {
-  std::vector<std::pair<Jacobi0Args<T>, int>> ja;
+  std::vector<std::pair<Jacobi0Args<T>, int>> js, jf;
   for (Member* M : ms) {
     if (M->m->dim != dim) continue;
     const int l = lof(*M);
     if (l < 0) continue;
     const Jacobi0Args<T> a = jacobi0_args<T>(lev(*M, l), M->w.b[l], M->w.t[l], o.omega);
-    ja.push_back({a, jacobi0_blocks(a)});
+    js.push_back({a, jacobi0_stream_blocks(a)});
+    jf.push_back({a, jacobi0_fix_blocks(a)});
   }
-  P.add(kOpJacobi0, dtype_of<T>(), dim, 0, ja);
+  P.add(kOpJacobi0, dtype_of<T>(), dim, 0, js);
+  P.add(kOpJacobi0, dtype_of<T>(), dim, 1, jf);
 }
 
 // Jacobi sweeps at the members' cycle level (ping-pong x <-> t), as

@@ -93,17 +93,21 @@ struct CoarseArgs {
   T* X;
 };
 
-// jacobi0_kernel: the first Jacobi sweep of a V-cycle level, whose iterate is
-// zero.  Blocks [0, nblk_pts) walk the level's point segments; blocks
-// [nblk_pts, nblk_pts + nblk_grp) take the shared non-Dirichlet DoFs (the
+// The first Jacobi sweep of a V-cycle level, whose iterate is zero, in two
+// launches: jacobi0_stream_kernel writes the interior formula to every point
+// of every macro (nmac macros of P points, bpm blocks each), then
+// jacobi0_fix_kernel rewrites the macro-boundary DoFs: blocks [0, nblk_all)
+// take the all-groups list (Dirichlet and unshared DoFs), blocks
+// [nblk_all, nblk_all + nblk_grp) the shared non-Dirichlet ones (the
 // exchange list), one group per thread.
 template <typename T>
 struct Jacobi0Args {
-  const Tile* segs;
-  int nseg;
-  int nblk_pts;
-  int ngroups;
-  int nblk_grp;
+  int nmac, bpm;
+  int64_t P;
+  int nall, nblk_all;  // all macro-boundary DoFs
+  const int32_t* aptr;
+  const Copy* acopies;
+  int ngroups, nblk_grp;  // exchange list
   const int32_t* gptr;
   const Copy* copies;
   const double* ginv;
@@ -113,6 +117,7 @@ struct Jacobi0Args {
   T* Y;
   T omega;
 };
+constexpr int kJ0Points = 2048;  // points per block of the streaming pass
 
 // vcycle_tail_kernel: the bottom of a V-cycle — the coarse solve and up to
 // kTailLevels - 1 levels above it, each of at most kTailMaxPoints storage
@@ -306,9 +311,13 @@ inline int coarse_blocks(const Level& L) { return (int)((L.ncoarse + kWavesPerWG
 template <typename T>
 Jacobi0Args<T> jacobi0_args(const Level& L, const void* b, void* y, double omega) {
   Jacobi0Args<T> a;
-  a.segs = L.dev.segs;
-  a.nseg = (int)L.segs.size();
-  a.nblk_pts = transfer_blocks(a.nseg);
+  a.nmac = (int)L.base.size();
+  a.P = a.nmac > 0 ? L.storage / a.nmac : 0;
+  a.bpm = (int)((a.P + kJ0Points - 1) / kJ0Points);
+  a.nall = (int)L.ngroups();
+  a.nblk_all = (a.nall + kWG - 1) / kWG;
+  a.aptr = L.dev.grp_ptr;
+  a.acopies = L.dev.copies;
   a.ngroups = (int)L.nxgroups();
   a.nblk_grp = (a.ngroups + kWG - 1) / kWG;
   a.gptr = L.dev.xgrp_ptr;
@@ -322,7 +331,9 @@ Jacobi0Args<T> jacobi0_args(const Level& L, const void* b, void* y, double omega
   return a;
 }
 template <typename T>
-int jacobi0_blocks(const Jacobi0Args<T>& a) { return a.nblk_pts + a.nblk_grp; }
+int jacobi0_stream_blocks(const Jacobi0Args<T>& a) { return a.nmac * a.bpm; }
+template <typename T>
+int jacobi0_fix_blocks(const Jacobi0Args<T>& a) { return a.nblk_all + a.nblk_grp; }
 
 template <typename T>
 TailLevel<T> tail_level(const Level& L, void* b, void* x, void* t) {
@@ -383,7 +394,8 @@ enum OpKind : int {
   kOpPcgZDot,      // PcgArgs, dtype = type of e: z = s e, partials of r . z
   kOpPcgDir,       // VecArgs: y = x + beta y, beta = res[2] / res[3] (0 if res[3] == 0)
   kOpPcgUpdate,    // PcgArgs: x += alpha p, r -= alpha q, alpha = res[2] / res[4]; partials of r . r
-  kOpJacobi0,      // Jacobi0Args<T>: y = omega D^-1 b (the first sweep from a zero iterate)
+  kOpJacobi0,      // Jacobi0Args<T>: y = omega D^-1 b (the first sweep from a zero iterate);
+                   // mode 0: streaming pass over all points, mode 1: macro-boundary DoFs
   kOpTail,         // TailArgs<T>: the V-cycle below a level, one workgroup per request
 };
 

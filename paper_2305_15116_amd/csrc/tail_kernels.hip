@@ -144,8 +144,6 @@ __device__ __forceinline__ void tail_jacobi(const TailLevel<T>& F, int sweeps, T
   int i = 0;
   if (from_zero) {
     Jacobi0Args<T> ja{};
-    ja.nseg = F.nseg;
-    ja.segs = F.segs;
     ja.ngroups = F.nx;
     ja.gptr = F.xptr;
     ja.copies = F.xcopies;

@@ -102,20 +102,48 @@ __global__ __launch_bounds__(kWG) void prolong_add_kernel(const Launch<TransferA
 
 
 
-template <typename T, int DIM>
-__global__ __launch_bounds__(kWG) void jacobi0_kernel(const Launch<Jacobi0Args<T>> L) {
+// First sweep from a zero iterate, pass 1: the interior row formula at every
+// point of every macro (a plain stream over each macro's storage range).
+template <typename T>
+__global__ __launch_bounds__(kWG) void jacobi0_stream_kernel(const Launch<Jacobi0Args<T>> L) {
   Jacobi0Args<T> a;
   const int blk = resolve(L, (int)blockIdx.x, a);
-  if (blk < a.nblk_pts) {
-    const int stride = a.nblk_pts * kWavesPerWG;
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (int si = blk * kWavesPerWG + w; si < a.nseg; si += stride) {
-      const Tile sg = load_seg(a.segs, si);
-      if (sg.macro >= 0) jacobi0_segment<T, DIM>(a, sg);
+  const int m = blk / a.bpm;
+  const int64_t begin = (int64_t)(blk - m * a.bpm) * kJ0Points;
+  const int64_t end = min(begin + (int64_t)kJ0Points, a.P);
+  const MacroDev& M = a.md[m];
+  const T c = a.omega * Prec<T>::invd(M);
+  const T* __restrict__ B = a.B + M.base;
+  T* __restrict__ Y = a.Y + M.base;
+  for (int64_t i = begin + threadIdx.x; i < end; i += kWG) Y[i] = fma(c, B[i], T(0));
+}
+
+// Pass 2: the macro-boundary DoFs, as jacobi0_point and jacobi0_group finish
+// them (0 at Dirichlet DoFs, the partial stencil's centre at unshared ones,
+// the assembled diagonal at shared ones).
+template <typename T, int DIM>
+__global__ __launch_bounds__(kWG) void jacobi0_fix_kernel(const Launch<Jacobi0Args<T>> L) {
+  constexpr int full = DIM == 2 ? 7 : 15;
+  constexpr int centre = stencil_table(DIM).centre;
+  Jacobi0Args<T> a;
+  const int blk = resolve(L, (int)blockIdx.x, a);
+  if (blk < a.nblk_all) {
+    const int g = blk * kWG + (int)threadIdx.x;
+    if (g >= a.nall) return;
+    const int c0 = a.aptr[g], c1 = a.aptr[g + 1];
+    for (int c = c0; c < c1; ++c) {
+      const Copy& k = a.acopies[c];
+      const MacroDev& M = a.md[k.macro];
+      const int mask = support_mask(DIM, M.N, k.x, k.y, k.z);
+      const bool dir = mask != full && ((M.dir_mask >> mask) & 1);
+      const bool shared = mask != full && !dir && ((M.shared_mask >> mask) & 1);
+      if (shared) continue;  // the exchange part below
+      const int64_t i = copy_index<DIM>(M, k);
+      a.Y[i] = dir ? T(0) : fma(a.omega * centre_inv<T>(M, mask, full, centre), a.B[i], T(0));
     }
     return;
   }
-  const int g = (blk - a.nblk_pts) * kWG + (int)threadIdx.x;
+  const int g = (blk - a.nblk_all) * kWG + (int)threadIdx.x;
   if (g < a.ngroups) jacobi0_group<T, DIM>(a, g);
 }
 
@@ -305,23 +333,23 @@ int launch_prolong_add(const mf_mesh* m, const Level& F, const Level& C, int dty
 
 namespace {
 template <typename T>
-void run_jacobi0(int dim, const Launch<Jacobi0Args<T>>& l, hipStream_t s) {
-  if (dim == 2) hipLaunchKernelGGL((jacobi0_kernel<T, 2>), dim3(l.nwg), dim3(kWG), 0, s, l);
-  else hipLaunchKernelGGL((jacobi0_kernel<T, 3>), dim3(l.nwg), dim3(kWG), 0, s, l);
+void run_jacobi0(int dim, int part, const Launch<Jacobi0Args<T>>& l, hipStream_t s) {
+  if (part == 0) hipLaunchKernelGGL((jacobi0_stream_kernel<T>), dim3(l.nwg), dim3(kWG), 0, s, l);
+  else if (dim == 2) hipLaunchKernelGGL((jacobi0_fix_kernel<T, 2>), dim3(l.nwg), dim3(kWG), 0, s, l);
+  else hipLaunchKernelGGL((jacobi0_fix_kernel<T, 3>), dim3(l.nwg), dim3(kWG), 0, s, l);
+}
+
+template <typename T>
+void jacobi0_both(int dim, const Jacobi0Args<T>& a, hipStream_t s) {
+  if (const int n = jacobi0_stream_blocks(a)) run_jacobi0<T>(dim, 0, single(a, n), s);
+  if (const int n = jacobi0_fix_blocks(a)) run_jacobi0<T>(dim, 1, single(a, n), s);
 }
 }  // namespace
 
 int launch_jacobi0(const mf_mesh* m, const Level& L, int dtype, double omega, const void* b, void* y,
                    hipStream_t s) {
-  if (dtype == MF_F64) {
-    const Jacobi0Args<double> a = jacobi0_args<double>(L, b, y, omega);
-    const int nwg = jacobi0_blocks(a);
-    if (nwg > 0) run_jacobi0<double>(m->dim, single(a, nwg), s);
-  } else {
-    const Jacobi0Args<float> a = jacobi0_args<float>(L, b, y, omega);
-    const int nwg = jacobi0_blocks(a);
-    if (nwg > 0) run_jacobi0<float>(m->dim, single(a, nwg), s);
-  }
+  if (dtype == MF_F64) jacobi0_both<double>(m->dim, jacobi0_args<double>(L, b, y, omega), s);
+  else jacobi0_both<float>(m->dim, jacobi0_args<float>(L, b, y, omega), s);
   return check_launch();
 }
 
@@ -429,8 +457,8 @@ int launch_vector_batch(const BatchOp& op, const char* table, hipStream_t s) {
       return check_launch();
     case kOpTail: return launch_tail_batch(op, table, s);
     case kOpJacobi0:
-      if (op.dtype == MF_F64) run_jacobi0<double>(op.dim, batched<Jacobi0Args<double>>(op, table), s);
-      else run_jacobi0<float>(op.dim, batched<Jacobi0Args<float>>(op, table), s);
+      if (op.dtype == MF_F64) run_jacobi0<double>(op.dim, op.mode, batched<Jacobi0Args<double>>(op, table), s);
+      else run_jacobi0<float>(op.dim, op.mode, batched<Jacobi0Args<float>>(op, table), s);
       return check_launch();
     default: return set_error(MF_EINVAL, "unknown batch op");
   }
