@@ -229,10 +229,10 @@ void transfer_op(PlanBuilder& P, const std::vector<Member*>& ms, int dim, int dt
     const Level& F = lev(*M, l);
     const Level& C = lev(*M, l - 1);
     if (restrict_op) {
-      ta.push_back({restrict_args<T>(F, C, M->w.t[l], M->w.b[l - 1]), transfer_blocks((int)C.segs.size())});
+      ta.push_back({restrict_args<T>(F, C, M->w.t[l], M->w.b[l - 1]), transfer_blocks((int)C.psegs.size())});
       ia.push_back({iface_args<T>(C, M->w.b[l - 1], M->w.b[l - 1], nullptr), iface_blocks(C)});
     } else {
-      ta.push_back({prolong_args<T>(F, C, M->w.x[l - 1], M->w.x[l]), transfer_blocks((int)F.segs.size())});
+      ta.push_back({prolong_args<T>(F, C, M->w.x[l - 1], M->w.x[l]), transfer_blocks((int)F.psegs.size())});
     }
   }
   P.add(restrict_op ? kOpRestrict : kOpProlong, dtype, dim, 0, ta);

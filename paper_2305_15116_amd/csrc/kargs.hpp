@@ -285,13 +285,13 @@ inline int transfer_blocks(int nseg) {
 }
 template <typename T>
 TransferArgs<T> restrict_args(const Level& F, const Level& C, const void* rf, void* bc) {
-  const int n = (int)C.segs.size();
-  return TransferArgs<T>{C.dev.segs, n, transfer_blocks(n), C.dev.md, F.dev.md, (const T*)rf, (T*)bc};
+  const int n = (int)C.psegs.size();
+  return TransferArgs<T>{C.dev.psegs, n, transfer_blocks(n), C.dev.md, F.dev.md, (const T*)rf, (T*)bc};
 }
 template <typename T>
 TransferArgs<T> prolong_args(const Level& F, const Level& C, const void* ec, void* xf) {
-  const int n = (int)F.segs.size();
-  return TransferArgs<T>{F.dev.segs, n, transfer_blocks(n), C.dev.md, F.dev.md, (const T*)ec, (T*)xf};
+  const int n = (int)F.psegs.size();
+  return TransferArgs<T>{F.dev.psegs, n, transfer_blocks(n), C.dev.md, F.dev.md, (const T*)ec, (T*)xf};
 }
 
 template <typename T>

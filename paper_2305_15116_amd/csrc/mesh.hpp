@@ -22,6 +22,7 @@ struct LevelDev {
   Tile* tiles = nullptr;       // interior wave tiles, padded to a multiple of kWavesPerWG
   Tile* tiles_f32 = nullptr;   // 2D FP32 wave tiles
   Tile* segs = nullptr;        // row segments of 64 points covering every storage point
+  Tile* psegs = nullptr;       // slice segments: 64 consecutive storage points of one slice
   int32_t* grp_ptr = nullptr;  // ngroups + 1
   Copy* copies = nullptr;
   uint8_t* grp_flag = nullptr;  // bit0: Dirichlet
@@ -52,6 +53,10 @@ struct Level {
   std::vector<Tile> tiles;      // interior wave tiles (natural order, padded)
   std::vector<Tile> tiles_f32;  // 2D FP32 wave tiles (kTileH2F rows); empty in 3D (same as tiles)
   std::vector<Tile> segs;       // per-point row segments
+  // per-point slice segments {macro, first slice-local index, 0, z}: a
+  // slice (the whole macro in 2D) is contiguous in storage, so its points
+  // are cut into 64-point pieces across row ends (full lanes where rows are short)
+  std::vector<Tile> psegs;
   std::vector<int32_t> grp_ptr;
   std::vector<Copy> copies;
   std::vector<uint8_t> grp_flag;

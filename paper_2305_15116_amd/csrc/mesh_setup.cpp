@@ -485,6 +485,15 @@ static int build_level(mf_mesh* m, int level, Level& L) {
     }
   }
   while (L.segs.size() % kWavesPerWG) L.segs.push_back({-1, 0, 0, 0});
+  L.psegs.clear();
+  for (int64_t c = 0; c < m->nc; ++c) {
+    const int zmax = dim == 3 ? N : 0;
+    for (int z = 0; z <= zmax; ++z) {
+      const int64_t S = N - z, P = (S + 1) * (S + 2) / 2;
+      for (int64_t r0 = 0; r0 < P; r0 += kWave) L.psegs.push_back({(int32_t)c, (int32_t)r0, 0, z});
+    }
+  }
+  while (L.psegs.size() % kWavesPerWG) L.psegs.push_back({-1, 0, 0, 0});
   return MF_OK;
 }
 
@@ -495,6 +504,7 @@ int upload_level(mf_mesh* m, Level& L) {
   if ((rc = dev_upload(&D.tiles, L.tiles))) return rc;
   if ((rc = dev_upload(&D.tiles_f32, L.tiles_f32))) return rc;
   if ((rc = dev_upload(&D.segs, L.segs))) return rc;
+  if ((rc = dev_upload(&D.psegs, L.psegs))) return rc;
   if ((rc = dev_upload(&D.grp_ptr, L.grp_ptr))) return rc;
   if ((rc = dev_upload(&D.copies, L.copies))) return rc;
   if ((rc = dev_upload(&D.grp_flag, L.grp_flag))) return rc;
@@ -670,7 +680,7 @@ int build_mesh(mf_mesh* m) {
 void free_device(mf_mesh* m) {
   for (auto& L : m->levels) {
     LevelDev& D = L.dev;
-    void* ptrs[] = {D.md, D.tiles, D.tiles_f32, D.segs, D.grp_ptr, D.copies, D.grp_flag, D.xgrp_ptr, D.xcopies, D.xgrp_invdiag,
+    void* ptrs[] = {D.md, D.tiles, D.tiles_f32, D.segs, D.psegs, D.grp_ptr, D.copies, D.grp_flag, D.xgrp_ptr, D.xcopies, D.xgrp_invdiag,
                     D.xgrp_invdiagf,
                     D.part, D.result, D.cinv, D.cinvf, D.cfirst, D.cptr, D.cidx, D.own_bits, D.p2_tiles};
     for (void* p : ptrs)

@@ -193,9 +193,36 @@ __device__ __forceinline__ void restrict_point(const TransferArgs<T>& a, int mac
   }
   if (live) a.dst[C.base + lidx<DIM>(Nc, x, y, z)] = acc;
 }
+// This lane's point of slice segment sg ({macro, first slice-local index, 0,
+// z}) in a macro of side N: the slice of side S = N - z holds (S+1)(S+2)/2
+// points, row y starting at y (2S + 3 - y) / 2, so y is the smaller root of
+// y^2 - (2S + 3) y + 2r = 0, rounded down and corrected by one step either
+// way.  Lanes past the slice's end get x = S + 1 (no point: x + y + z > N).
+template <int DIM>
+__device__ __forceinline__ void slice_point(const Tile& sg, int N, int& x, int& y, int& z) {
+  z = DIM == 3 ? sg.z : 0;
+  const int S = N - z;
+  const int r = sg.x0 + (int)(threadIdx.x & (kWave - 1));
+  if (r >= (S + 1) * (S + 2) / 2) {
+    x = S + 1;
+    y = 0;
+    return;
+  }
+  // (in FP64: the discriminant reaches 2^32 in 2D, exact in a double)
+  const double b = 2.0 * (double)S + 3.0;
+  int yy = (int)((b - sqrt(b * b - 8.0 * (double)r)) * 0.5);
+  yy = min(max(yy, 0), S);
+  if (row_start(S, yy) > r) --yy;
+  else if (yy < S && row_start(S, yy + 1) <= r) ++yy;
+  y = yy;
+  x = r - row_start(S, yy);
+}
+
 template <typename T, int DIM>
 __device__ __forceinline__ void restrict_segment(const TransferArgs<T>& a, const Tile sg) {
-  restrict_point<T, DIM>(a, sg.macro, sg.x0 + (int)(threadIdx.x & (kWave - 1)), sg.y0, DIM == 3 ? sg.z : 0);
+  int x, y, z;
+  slice_point<DIM>(sg, load_macro(a.mdc, sg.macro).N, x, y, z);
+  restrict_point<T, DIM>(a, sg.macro, x, y, z);
 }
 
 // x_f += P e_c: even fine points take the coarse value, the others the mean
@@ -228,7 +255,9 @@ __device__ __forceinline__ void prolong_point(const TransferArgs<T>& a, int macr
 }
 template <typename T, int DIM>
 __device__ __forceinline__ void prolong_segment(const TransferArgs<T>& a, const Tile sg) {
-  prolong_point<T, DIM>(a, sg.macro, sg.x0 + (int)(threadIdx.x & (kWave - 1)), sg.y0, DIM == 3 ? sg.z : 0);
+  int x, y, z;
+  slice_point<DIM>(sg, load_macro(a.mdf, sg.macro).N, x, y, z);
+  prolong_point<T, DIM>(a, sg.macro, x, y, z);
 }
 
 // First Jacobi sweep of a V-cycle level.  The iterate is zero there, so
@@ -259,10 +288,6 @@ __device__ __forceinline__ void jacobi0_point(const Jacobi0Args<T>& a, int macro
   if (shared) return;  // finished by the group part
   const int64_t i = C.base + lidx<DIM>(N, x, y, z);
   a.Y[i] = dir ? T(0) : fma(a.omega * centre_inv<T>(M, mask, full, centre), a.B[i], T(0));
-}
-template <typename T, int DIM>
-__device__ __forceinline__ void jacobi0_segment(const Jacobi0Args<T>& a, const Tile sg) {
-  jacobi0_point<T, DIM>(a, sg.macro, sg.x0 + (int)(threadIdx.x & (kWave - 1)), sg.y0, DIM == 3 ? sg.z : 0);
 }
 
 template <int DIM>

@@ -313,7 +313,7 @@ int launch_fill_random(const mf_mesh* m, const Level& L, int dtype, uint64_t see
 
 int launch_restrict(const mf_mesh* m, const Level& F, const Level& C, int dtype, const void* rf, void* bc,
                     hipStream_t s) {
-  const int nwg = transfer_blocks((int)C.segs.size());
+  const int nwg = transfer_blocks((int)C.psegs.size());
   if (nwg == 0) return MF_OK;
   if (dtype == MF_F64) run_transfer<double>(true, m->dim, single(restrict_args<double>(F, C, rf, bc), nwg), s);
   else run_transfer<float>(true, m->dim, single(restrict_args<float>(F, C, rf, bc), nwg), s);
@@ -324,7 +324,7 @@ int launch_restrict(const mf_mesh* m, const Level& F, const Level& C, int dtype,
 
 int launch_prolong_add(const mf_mesh* m, const Level& F, const Level& C, int dtype, const void* ec, void* xf,
                        hipStream_t s) {
-  const int nwg = transfer_blocks((int)F.segs.size());
+  const int nwg = transfer_blocks((int)F.psegs.size());
   if (nwg == 0) return MF_OK;
   if (dtype == MF_F64) run_transfer<double>(false, m->dim, single(prolong_args<double>(F, C, ec, xf), nwg), s);
   else run_transfer<float>(false, m->dim, single(prolong_args<float>(F, C, ec, xf), nwg), s);
