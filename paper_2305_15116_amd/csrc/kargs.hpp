@@ -139,8 +139,6 @@ constexpr int kTailMaxCoarse = 256;  // coarse unknowns (the dense solve runs on
 
 template <typename T>
 struct TailLevel {
-  const Tile* segs;  // point segments of the level
-  int nseg;
   int nx;  // exchange list: shared non-Dirichlet DoFs
   const int32_t* xptr;
   const Copy* xcopies;
@@ -338,8 +336,6 @@ int jacobi0_fix_blocks(const Jacobi0Args<T>& a) { return a.nblk_all + a.nblk_grp
 template <typename T>
 TailLevel<T> tail_level(const Level& L, void* b, void* x, void* t) {
   TailLevel<T> v;
-  v.segs = L.dev.segs;
-  v.nseg = (int)L.segs.size();
   v.nx = (int)L.nxgroups();
   v.xptr = L.dev.xgrp_ptr;
   v.xcopies = L.dev.xcopies;

@@ -18,8 +18,6 @@
 
 #include <hip/hip_runtime.h>
 
-#include <utility>
-
 #include "launch.hpp"
 #include "rows.hpp"
 
@@ -199,7 +197,7 @@ __global__ __launch_bounds__(kTailWG) void vcycle_tail_kernel(const Launch<TailA
     const TailLevel<T> C = a->lv[k - 1];
     tail_jacobi<T, DIM>(F, pre, omega, true);
     tail_pass<T, DIM, kResidual>(F, F.x, F.t, T(0));
-    const TransferArgs<T> ta{C.segs, C.nseg, 0, C.md, F.md, F.t, C.b};
+    const TransferArgs<T> ta{nullptr, 0, 0, C.md, F.md, F.t, C.b};  // points come from for_points
     for_points<DIM>(C.N, C.nmac, [&](int m, int x, int y, int z) { restrict_point<T, DIM>(ta, m, x, y, z); });
     __syncthreads();
     GroupArgs<T> ga{};
@@ -225,7 +223,7 @@ __global__ __launch_bounds__(kTailWG) void vcycle_tail_kernel(const Launch<TailA
   for (int k = 1; k < nlev; ++k) {
     const TailLevel<T> F = a->lv[k];
     const TailLevel<T> C = a->lv[k - 1];
-    const TransferArgs<T> ta{F.segs, F.nseg, 0, C.md, F.md, C.x, F.x};
+    const TransferArgs<T> ta{nullptr, 0, 0, C.md, F.md, C.x, F.x};
     for_points<DIM>(F.N, F.nmac, [&](int m, int x, int y, int z) { prolong_point<T, DIM>(ta, m, x, y, z); });
     __syncthreads();
     tail_jacobi<T, DIM>(F, post, omega, false);
