@@ -57,6 +57,7 @@ struct GroupArgs {
   int ngroups;
   const int32_t* gptr;
   const Copy* copies;
+  const int64_t* cidx;  // storage index of each copy
   const uint8_t* gflag;  // all-groups list only
   const double* ginv;    // exchange list only
   const float* ginvf;
@@ -110,6 +111,7 @@ struct Jacobi0Args {
   int ngroups, nblk_grp;  // exchange list
   const int32_t* gptr;
   const Copy* copies;
+  const int64_t* gidx;  // storage index of each exchange-list copy
   const double* ginv;
   const float* ginvf;
   const MacroDev* md;
@@ -142,11 +144,13 @@ struct TailLevel {
   int nx;  // exchange list: shared non-Dirichlet DoFs
   const int32_t* xptr;
   const Copy* xcopies;
+  const int64_t* xcidx;
   const double* xinv;
   const float* xinvf;
   int ng;  // all macro-boundary DoFs
   const int32_t* gptr;
   const Copy* copies;
+  const int64_t* gcidx;
   const uint8_t* gflag;
   const MacroDev* md;
   int64_t storage;  // nmac macros of side N, stored one after the other
@@ -241,6 +245,7 @@ GroupArgs<T> exchange_args(const Level& L, const void* x, void* y, const void* b
   g.ngroups = (int)L.nxgroups();
   g.gptr = L.dev.xgrp_ptr;
   g.copies = L.dev.xcopies;
+  g.cidx = L.dev.xcpidx;
   g.gflag = nullptr;
   g.ginv = L.dev.xgrp_invdiag;
   g.ginvf = L.dev.xgrp_invdiagf;
@@ -261,6 +266,7 @@ GroupArgs<T> iface_args(const Level& L, const void* x, void* y, const void* b) {
   g.ngroups = (int)L.ngroups();
   g.gptr = L.dev.grp_ptr;
   g.copies = L.dev.copies;
+  g.cidx = L.dev.cpidx;
   g.gflag = L.dev.grp_flag;
   g.ginv = nullptr;
   g.ginvf = nullptr;
@@ -320,6 +326,7 @@ Jacobi0Args<T> jacobi0_args(const Level& L, const void* b, void* y, double omega
   a.nblk_grp = (a.ngroups + kWG - 1) / kWG;
   a.gptr = L.dev.xgrp_ptr;
   a.copies = L.dev.xcopies;
+  a.gidx = L.dev.xcpidx;
   a.ginv = L.dev.xgrp_invdiag;
   a.ginvf = L.dev.xgrp_invdiagf;
   a.md = L.dev.md;
@@ -339,11 +346,13 @@ TailLevel<T> tail_level(const Level& L, void* b, void* x, void* t) {
   v.nx = (int)L.nxgroups();
   v.xptr = L.dev.xgrp_ptr;
   v.xcopies = L.dev.xcopies;
+  v.xcidx = L.dev.xcpidx;
   v.xinv = L.dev.xgrp_invdiag;
   v.xinvf = L.dev.xgrp_invdiagf;
   v.ng = (int)L.ngroups();
   v.gptr = L.dev.grp_ptr;
   v.copies = L.dev.copies;
+  v.gcidx = L.dev.cpidx;
   v.gflag = L.dev.grp_flag;
   v.md = L.dev.md;
   v.storage = L.storage;

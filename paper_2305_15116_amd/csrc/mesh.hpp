@@ -28,6 +28,8 @@ struct LevelDev {
   uint8_t* grp_flag = nullptr;  // bit0: Dirichlet
   int32_t* xgrp_ptr = nullptr;  // exchange groups: shared, non-Dirichlet DoFs
   Copy* xcopies = nullptr;
+  int64_t* cpidx = nullptr;   // storage index of every copy (all-groups list)
+  int64_t* xcpidx = nullptr;  // storage index of every copy (exchange list)
   double* xgrp_invdiag = nullptr;
   float* xgrp_invdiagf = nullptr;
   double* part = nullptr;       // norm partials: ntiles + iface blocks, then the same again for max
@@ -63,6 +65,7 @@ struct Level {
   // exchange groups: DoFs shared by several macros and not Dirichlet
   std::vector<int32_t> xgrp_ptr;
   std::vector<Copy> xcopies;
+  std::vector<int64_t> cpidx, xcpidx;  // storage indices of copies / xcopies (kernels skip the macro lookup)
   std::vector<double> xgrp_invdiag;
   int64_t ngroups() const { return (int64_t)grp_ptr.size() - 1; }
   int64_t nxgroups() const { return (int64_t)xgrp_ptr.size() - 1; }

@@ -449,6 +449,15 @@ static int build_level(mf_mesh* m, int level, Level& L) {
     }
   }
 
+  // storage indices of the copies, so that exchange kernels index directly
+  auto storage_index = [&](const Copy& c) {
+    return L.md[c.macro].base + (dim == 2 ? idx2(N, c.x, c.y) : idx3(N, c.x, c.y, c.z));
+  };
+  L.cpidx.resize(L.copies.size());
+  for (size_t i = 0; i < L.copies.size(); ++i) L.cpidx[i] = storage_index(L.copies[i]);
+  L.xcpidx.resize(L.xcopies.size());
+  for (size_t i = 0; i < L.xcopies.size(); ++i) L.xcpidx[i] = storage_index(L.xcopies[i]);
+
   // wave tiles over every point of every macro, natural order: macro,
   // (slice chunk,) strip, band
   L.tiles.clear();
@@ -510,6 +519,8 @@ int upload_level(mf_mesh* m, Level& L) {
   if ((rc = dev_upload(&D.grp_flag, L.grp_flag))) return rc;
   if ((rc = dev_upload(&D.xgrp_ptr, L.xgrp_ptr))) return rc;
   if ((rc = dev_upload(&D.xcopies, L.xcopies))) return rc;
+  if ((rc = dev_upload(&D.cpidx, L.cpidx))) return rc;
+  if ((rc = dev_upload(&D.xcpidx, L.xcpidx))) return rc;
   if ((rc = dev_upload(&D.xgrp_invdiag, L.xgrp_invdiag))) return rc;
   if ((rc = dev_upload(&D.own_bits, L.own_bits))) return rc;
   std::vector<float> f(L.xgrp_invdiag.begin(), L.xgrp_invdiag.end());
@@ -680,7 +691,7 @@ int build_mesh(mf_mesh* m) {
 void free_device(mf_mesh* m) {
   for (auto& L : m->levels) {
     LevelDev& D = L.dev;
-    void* ptrs[] = {D.md, D.tiles, D.tiles_f32, D.segs, D.psegs, D.grp_ptr, D.copies, D.grp_flag, D.xgrp_ptr, D.xcopies, D.xgrp_invdiag,
+    void* ptrs[] = {D.md, D.tiles, D.tiles_f32, D.segs, D.psegs, D.grp_ptr, D.copies, D.grp_flag, D.xgrp_ptr, D.xcopies, D.cpidx, D.xcpidx, D.xgrp_invdiag,
                     D.xgrp_invdiagf,
                     D.part, D.result, D.cinv, D.cinvf, D.cfirst, D.cptr, D.cidx, D.own_bits, D.p2_tiles};
     for (void* p : ptrs)

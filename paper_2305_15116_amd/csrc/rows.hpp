@@ -302,17 +302,17 @@ __device__ __forceinline__ int64_t copy_index(const MacroDev& M, const Copy& c) 
 template <typename T, int DIM, int MODE>
 __device__ __forceinline__ T exchange_row(const GroupArgs<T>& a, int g, int64_t& i0) {
   const int c0 = a.gptr[g], c1 = a.gptr[g + 1];
-  i0 = copy_index<DIM>(a.md[a.copies[c0].macro], a.copies[c0]);
+  i0 = a.cidx[c0];
   T out;
   if (MODE == kNormB) {
     out = a.B[i0];
   } else {
     T acc = T(0);
-    for (int c = c0; c < c1; ++c) acc += a.Y[copy_index<DIM>(a.md[a.copies[c].macro], a.copies[c])];
+    for (int c = c0; c < c1; ++c) acc += a.Y[a.cidx[c]];
     if (MODE == kApply || MODE == kApplyDot) out = acc;
     else if (MODE == kJacobi) out = fma(a.omega * Prec<T>::ginv(a.ginv, a.ginvf, g), a.B[i0] - acc, a.X[i0]);
     else out = a.B[i0] - acc;
-    for (int c = c0; c < c1; ++c) a.Y[copy_index<DIM>(a.md[a.copies[c].macro], a.copies[c])] = out;
+    for (int c = c0; c < c1; ++c) a.Y[a.cidx[c]] = out;
   }
   return out;
 }
@@ -325,8 +325,8 @@ __device__ __forceinline__ void iface_sum_row(const GroupArgs<T>& a, int g) {
   const bool dir = a.gflag[g] & 1;
   T out = T(0);
   if (!dir)
-    for (int c = c0; c < c1; ++c) out += a.X[copy_index<DIM>(a.md[a.copies[c].macro], a.copies[c])];
-  for (int c = c0; c < c1; ++c) a.Y[copy_index<DIM>(a.md[a.copies[c].macro], a.copies[c])] = out;
+    for (int c = c0; c < c1; ++c) out += a.X[a.cidx[c]];
+  for (int c = c0; c < c1; ++c) a.Y[a.cidx[c]] = out;
 }
 
 // Coarse direct solve, unknown i, one wavefront (lane = its lane):
@@ -345,18 +345,12 @@ __device__ __forceinline__ void coarse_row(const CoarseArgs<T>& a, int i, int la
 template <typename T, int DIM>
 __device__ __forceinline__ void jacobi0_group(const Jacobi0Args<T>& a, int g) {
   const int c0 = a.gptr[g], c1 = a.gptr[g + 1];
-  const Copy& f = a.copies[c0];
-  const MacroDev& M0 = a.md[f.macro];
-  const T b = a.B[M0.base + lidx<DIM>(M0.N, f.x, f.y, f.z)];
+  const T b = a.B[a.gidx[c0]];
   T d;
   if constexpr (sizeof(T) == 8) d = a.ginv[g];
   else d = a.ginvf[g];
   const T out = fma(a.omega * d, b, T(0));
-  for (int c = c0; c < c1; ++c) {
-    const Copy& k = a.copies[c];
-    const MacroDev& Mk = a.md[k.macro];
-    a.Y[Mk.base + lidx<DIM>(Mk.N, k.x, k.y, k.z)] = out;
-  }
+  for (int c = c0; c < c1; ++c) a.Y[a.gidx[c]] = out;
 }
 
 }  // namespace mf

@@ -565,8 +565,8 @@ __global__ __launch_bounds__(kIfaceWG) void iface_kernel(const Launch<GroupArgs<
   if (MODE == kDirichletSet) {
     const int c0 = a.gptr[g], c1 = a.gptr[g + 1];
     if (!(a.gflag[g] & 1)) return;
-    const T v = a.B ? a.B[copy_index<DIM>(a.md[a.copies[c0].macro], a.copies[c0])] : T(0);
-    for (int c = c0; c < c1; ++c) a.Y[copy_index<DIM>(a.md[a.copies[c].macro], a.copies[c])] = v;
+    const T v = a.B ? a.B[a.cidx[c0]] : T(0);
+    for (int c = c0; c < c1; ++c) a.Y[a.cidx[c]] = v;
     return;
   }
   iface_sum_row<T, DIM>(a, g);

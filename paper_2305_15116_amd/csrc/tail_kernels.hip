@@ -102,6 +102,7 @@ __device__ __forceinline__ void tail_exchange(const TailLevel<T>& F, const T* X,
   g.ngroups = F.nx;
   g.gptr = F.xptr;
   g.copies = F.xcopies;
+  g.cidx = F.xcidx;
   g.ginv = F.xinv;
   g.ginvf = F.xinvf;
   g.md = F.md;
@@ -145,6 +146,7 @@ __device__ __forceinline__ void tail_jacobi(const TailLevel<T>& F, int sweeps, T
     ja.ngroups = F.nx;
     ja.gptr = F.xptr;
     ja.copies = F.xcopies;
+    ja.gidx = F.xcidx;
     ja.ginv = F.xinv;
     ja.ginvf = F.xinvf;
     ja.md = F.md;
@@ -204,6 +206,7 @@ __global__ __launch_bounds__(kTailWG) void vcycle_tail_kernel(const Launch<TailA
     ga.ngroups = C.ng;
     ga.gptr = C.gptr;
     ga.copies = C.copies;
+    ga.cidx = C.gcidx;
     ga.gflag = C.gflag;
     ga.md = C.md;
     ga.X = C.b;
