@@ -369,8 +369,8 @@ void build_plan(mf_batch* B) {
       return ReduceArgs{M.w.part, lev(M, M.level).lin_blocks(), M.w.result + 2, nullptr, 1, 0};
     });
     for (int dim = 2; dim <= 3; ++dim)
-      vector_op(P, corr, dim, kOpPcgDir, MF_F64, [](const Member& M, VecArgs& a) {
-        a = vec_args(M.w.p64, M.w.z64, M.w.result, lev(M, M.level).storage, 0.0);
+      vector_op(P, corr, dim, kOpPcgDir, vdt, [f32](const Member& M, VecArgs& a) {
+        a = vec_args(M.w.p64, f32 ? M.w.x[M.level] : (const void*)M.w.z64, M.w.result, lev(M, M.level).storage, 0.0);
         return true;
       });
     for (int dim = 2; dim <= 3; ++dim)

@@ -406,7 +406,8 @@ int vcycle_solve(const mf_mesh* m, int level, const double* b, double* x, void* 
       // conjugate gradients preconditioned by the V-cycle; scalars stay on the device
       rc = launch_pcg_zdot(m, L, vdt, w.r64, w.x[level], w.z64, w.result, w.part, s);
       if (!rc) rc = launch_reduce_shift(w.part, nlin, w.result + 2, s);                // r.z, previous r.z
-      if (!rc) rc = launch_pcg_dir(w.p64, w.z64, w.result, L.storage, s);              // p = z + beta p
+      if (!rc)
+        rc = launch_pcg_dir(w.p64, f32 ? w.x[level] : (const void*)w.z64, w.result, L.storage, s, vdt);  // p = z + beta p
       if (!rc) rc = launch_stencil(m, L, MF_F64, kApplyDot, w.p64, w.q64, nullptr, 0.0, w.part, s);
       if (!rc) rc = launch_reduce(w.part, stencil_partials(L, MF_F64), w.result + 4, s);       // p.Ap
       if (!rc) rc = launch_pcg_update(m, L, x, w.r64, w.p64, w.q64, w.result, w.part, s);

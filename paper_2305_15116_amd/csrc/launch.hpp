@@ -87,7 +87,9 @@ int launch_pcg_zdot(const mf_mesh* m, const Level& L, int edtype, const double* 
                     const double* res, double* part, hipStream_t s);
 int launch_pcg_update(const mf_mesh* m, const Level& L, double* x, double* r, double* p, const double* q,
                       const double* res, double* part, hipStream_t s);
-int launch_pcg_dir(double* p, const double* z, const double* res, int64_t n, hipStream_t s);
+// p = z + beta p; zdtype MF_F32: z is given as the FP32 V-cycle output e and
+// formed as res[1] e (as launch_pcg_zdot forms it).
+int launch_pcg_dir(double* p, const void* z, const double* res, int64_t n, hipStream_t s, int zdtype = MF_F64);
 // result (2 doubles) = (sum, previous result[0]) of part[0, np)
 int launch_reduce_shift(const double* part, int64_t np, double* result, hipStream_t s);
 

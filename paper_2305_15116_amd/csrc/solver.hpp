@@ -22,7 +22,8 @@ struct Workspace {
   double* r64 = nullptr;
   double* e64 = nullptr;
   double* t64 = nullptr;
-  double* z64 = nullptr;  // PCG: preconditioned residual (== e64 in FP64 mode)
+  double* z64 = nullptr;  // PCG: preconditioned residual (== e64 in FP64 mode; in FP32 mode never
+                          // stored: z = res[1] e is formed where it is read)
   double* p64 = nullptr;  // PCG: search direction
   double* q64 = nullptr;  // PCG: A p
   double* part = nullptr;
@@ -68,7 +69,7 @@ inline Workspace carve(const mf_mesh* m, int level, int mode, int lc, char* base
     }
   }
   if (mode_pcg(mode)) {
-    w.z64 = mode_f32(mode) ? (double*)take(8 * SL) : w.e64;
+    w.z64 = mode_f32(mode) ? nullptr : w.e64;
     w.p64 = (double*)take(8 * SL);
     w.q64 = (double*)take(8 * SL);
   }

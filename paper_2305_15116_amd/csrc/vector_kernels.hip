@@ -210,7 +210,7 @@ __global__ __launch_bounds__(256) void pcg_lin_kernel(const Launch<PcgArgs> L) {
   if (KIND == kOpPcgZDot) {
     const double sc = sizeof(TE) == 4 ? a.res[1] : 1.0;
     const TE* e = (const TE*)a.e;
-    const bool wz = (const void*)a.z != a.e;
+    const bool wz = a.z != nullptr && (const void*)a.z != a.e;
     for (int64_t i = (int64_t)blk * 256 + threadIdx.x; i < a.n; i += stride) {
       const double zv = sc * (double)e[i];
       if (wz) a.z[i] = zv;
@@ -242,19 +242,25 @@ __global__ __launch_bounds__(256) void pcg_lin_kernel(const Launch<PcgArgs> L) {
 }
 
 // p = z + beta p, beta = res[2] / res[3] (0 on the first iteration, res[3] == 0).
+// p = z + beta p.  TZ = double: x is z; TZ = float: x is the FP32 V-cycle
+// output e and z = res[1] e is formed here exactly as the r . z pass forms it
+// (the mixed solver never stores z).
+template <typename TZ>
 __global__ __launch_bounds__(256) void pcg_dir_kernel(const Launch<VecArgs> L) {
   VecArgs a;
   const int blk = resolve(L, (int)blockIdx.x, a);
   const int64_t stride = (int64_t)a.nblk * 256;
   double* p = (double*)a.y;
-  const double* z = (const double*)a.x;
+  const TZ* zs = (const TZ*)a.x;
+  const double sc = sizeof(TZ) == 4 ? a.res[1] : 1.0;
+  auto z = [&](int64_t i) { return sizeof(TZ) == 4 ? sc * (double)zs[i] : (double)zs[i]; };
   if (a.res[3] == 0.0) {
     // first direction: p = z (p holds no earlier direction and is never read)
-    for (int64_t i = (int64_t)blk * 256 + threadIdx.x; i < a.n; i += stride) p[i] = z[i];
+    for (int64_t i = (int64_t)blk * 256 + threadIdx.x; i < a.n; i += stride) p[i] = z(i);
     return;
   }
   const double beta = a.res[2] / a.res[3];
-  for (int64_t i = (int64_t)blk * 256 + threadIdx.x; i < a.n; i += stride) p[i] = fma(beta, p[i], z[i]);
+  for (int64_t i = (int64_t)blk * 256 + threadIdx.x; i < a.n; i += stride) p[i] = fma(beta, p[i], z(i));
 }
 
 template <class A>
@@ -422,10 +428,11 @@ int launch_pcg_update(const mf_mesh* m, const Level& L, double* x, double* r, do
   return check_launch();
 }
 
-int launch_pcg_dir(double* p, const double* z, const double* res, int64_t n, hipStream_t s) {
+int launch_pcg_dir(double* p, const void* z, const double* res, int64_t n, hipStream_t s, int zdtype) {
   if (n <= 0) return MF_OK;
   const VecArgs a = vec_args(p, z, res, n, 0.0);
-  hipLaunchKernelGGL(pcg_dir_kernel, dim3(a.nblk), dim3(256), 0, s, single(a, a.nblk));
+  if (zdtype == MF_F32) hipLaunchKernelGGL(pcg_dir_kernel<float>, dim3(a.nblk), dim3(256), 0, s, single(a, a.nblk));
+  else hipLaunchKernelGGL(pcg_dir_kernel<double>, dim3(a.nblk), dim3(256), 0, s, single(a, a.nblk));
   return check_launch();
 }
 
@@ -453,7 +460,10 @@ int launch_vector_batch(const BatchOp& op, const char* table, hipStream_t s) {
     case kOpPcgZDot: run_pcg_point<kOpPcgZDot>(op.dim, op.dtype, batched<PcgArgs>(op, table), s); return check_launch();
     case kOpPcgUpdate: run_pcg_point<kOpPcgUpdate>(op.dim, MF_F64, batched<PcgArgs>(op, table), s); return check_launch();
     case kOpPcgDir:
-      hipLaunchKernelGGL(pcg_dir_kernel, dim3(op.nwg), dim3(256), 0, s, batched<VecArgs>(op, table));
+      if (op.dtype == MF_F32)
+        hipLaunchKernelGGL(pcg_dir_kernel<float>, dim3(op.nwg), dim3(256), 0, s, batched<VecArgs>(op, table));
+      else
+        hipLaunchKernelGGL(pcg_dir_kernel<double>, dim3(op.nwg), dim3(256), 0, s, batched<VecArgs>(op, table));
       return check_launch();
     case kOpTail: return launch_tail_batch(op, table, s);
     case kOpJacobi0:
