@@ -189,3 +189,64 @@ def test_3d_level11_largest_supported_level():
     wsum = np.abs(P.mesh_stencil(m, L, 0)).sum()
     y[y == 1.0] = 0.0  # Dirichlet rows
     assert float(y.abs().max()) <= 1e-12 * wsum
+
+
+def _local_coords(dim, N, nmac):
+    """Macro-local lattice coordinates (x, y, z) of every storage point of a
+    level (macros stored one after the other), as int64 tensors."""
+    def tri(S):
+        rows = torch.arange(S + 1, device="cuda", dtype=torch.int64)
+        lengths = S + 1 - rows
+        y = torch.repeat_interleave(rows, lengths)
+        x = torch.arange(int(lengths.sum()), device="cuda", dtype=torch.int64) - (torch.cumsum(lengths, 0) - lengths)[y]
+        return x, y
+    if dim == 2:
+        x, y = tri(N)
+        z = torch.zeros_like(x)
+    else:
+        parts = [tri(N - k) + (torch.full(((N - k + 1) * (N - k + 2) // 2,), k, device="cuda", dtype=torch.int64),)
+                 for k in range(N + 1)]
+        x, y, z = (torch.cat([p[i] for p in parts]) for i in range(3))
+    return x.repeat(nmac), y.repeat(nmac), z.repeat(nmac)
+
+
+@pytest.mark.parametrize("dim,L,dtype", [(2, 15, torch.float64), (3, 8, torch.float32), (3, 8, torch.float64)])
+def test_transfers_full_size(dim, L, dtype):
+    """Prolongation and restriction over every point of the largest 2D level
+    and the benchmark cube, by properties exact in floating point: the P1
+    interpolant of an integer linear function of the macro-local coordinates
+    (every non-Dirichlet fine point gets the function's value, Dirichlet
+    points keep theirs), and the restriction of the constant 1 (interior
+    coarse points gather 1 + 6/2 in 2D, 1 + 14/2 in 3D)."""
+    co, ce = W.affine_triangle(2) if dim == 2 else W.kuhn_cube()
+    m = P.create_macro_mesh(co, ce, L)
+    nmac = len(ce)
+    Nf, Nc = 1 << L, 1 << (L - 1)
+    sf, _ = P.mesh_num_dofs(m, L)
+    sc, _ = P.mesh_num_dofs(m, L - 1)
+    xc, yc, zc = _local_coords(dim, Nc, nmac)
+    ec = (6 * xc + 10 * yc + 14 * zc).to(dtype)
+    del xc, yc, zc
+    xf = torch.zeros(sf, dtype=dtype, device="cuda")
+    P.prolong_add(m, L, ec, xf)
+    torch.cuda.synchronize()
+    fx, fy, fz = _local_coords(dim, Nf, nmac)
+    want = (3 * fx + 5 * fy + 7 * fz).to(dtype)
+    # Dirichlet fine points: the domain boundary, where prolongation leaves x alone
+    ones = torch.ones(sf, dtype=dtype, device="cuda")
+    dirichlet = torch.empty_like(ones)
+    P.mesh_set_dirichlet(m, L, None, dirichlet.copy_(ones))
+    dirichlet = dirichlet == 0
+    assert bool((xf[~dirichlet] == want[~dirichlet]).all())
+    assert bool((xf[dirichlet] == 0).all())
+    del want, dirichlet
+    bc = torch.full((sc,), float("nan"), dtype=dtype, device="cuda")
+    P.restrict_residual(m, L, ones, bc)
+    torch.cuda.synchronize()
+    del fx, fy, fz
+    xc, yc, zc = _local_coords(dim, Nc, nmac)
+    inner = (xc >= 1) & (yc >= 1) & (xc + yc + zc <= Nc - 1)
+    if dim == 3:
+        inner &= zc >= 1
+    assert bool(torch.isfinite(bc).all())
+    assert bool((bc[inner] == (4.0 if dim == 2 else 8.0)).all())
