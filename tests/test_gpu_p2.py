@@ -148,3 +148,37 @@ def test_p2_full_size_quadratic_rows(level):
     err = (y - expect).abs().max().item()
     assert err <= 1e-12, err
     assert (y[~inner] == x[~inner]).all()
+
+
+def test_p2_fp32_full_size_quadratic_rows():
+    """Benchmark size in FP32 (P2 level 13): the quadratic's interpolant gives
+    interior vertex rows 0 and interior edge rows -Laplace(q) times the basis
+    integral, to FP32 rounding of rows whose terms are O(1); Dirichlet rows
+    copy x exactly."""
+    level = 13
+    co, ce = W.affine_triangle(2)
+    m = P.create_macro_mesh(co, ce, level + 1)
+    M = 1 << (level + 1)
+    X, Y = _lattice(M)
+    P0, P1, P2 = (torch.tensor(co[i], device="cuda") for i in ce[0])
+    u, v = X.double() / M, Y.double() / M
+    px = P0[0] + u * (P1[0] - P0[0]) + v * (P2[0] - P0[0])
+    py = P0[1] + u * (P1[1] - P0[1]) + v * (P2[1] - P0[1])
+    del u, v
+    x = (px * px + 3.0 * px * py - 2.0 * py * py + px).float()
+    del px, py
+    y = torch.full_like(x, float("nan"))
+    P.apply_p2(m, level, x, y)
+    torch.cuda.synchronize()
+    N = M // 2
+    area = 0.5 * abs(np.linalg.det(np.array([co[ce[0][1]] - co[ce[0][0]], co[ce[0][2]] - co[ce[0][0]]])))
+    edge_row = 2.0 * 2.0 * (area / N ** 2) / 3.0
+    inner = (X >= 1) & (Y >= 1) & (X + Y <= M - 1)
+    vert = (X % 2 == 0) & (Y % 2 == 0)
+    expect = torch.where(vert, torch.zeros_like(y, dtype=torch.float64), torch.full_like(y, edge_row, dtype=torch.float64))
+    assert bool(torch.isfinite(y).all())
+    assert bool((y[~inner] == x[~inner]).all())
+    # rows add up to 19 terms of size about |w| |x| with |x| <= 6 and |w| <= 8/3:
+    # FP32 rounding of the inputs and the sums bounds the error by about 1e-4
+    err = (y[inner].double() - expect[inner]).abs().max().item()
+    assert err <= 2e-4, err

@@ -143,3 +143,33 @@ def test_varcoef_full_size_properties(L):
     torch.cuda.synchronize()
     assert (y[~inner] == 1.0).all()
     assert y[inner].abs().max().item() <= 1e-12
+
+
+def test_varcoef_fp32_full_size():
+    """Level 14 in FP32 (the benchmark's FP32 line): constant k = 2 gives twice
+    the FP32 constant-coefficient apply to FP32 rounding (the two sum their
+    terms in different orders), and Dirichlet rows copy x exactly."""
+    co, ce = W.affine_triangle(2)
+    L = 14
+    m = P.create_macro_mesh(co, ce, L)
+    s, _ = P.mesh_num_dofs(m, L)
+    x = torch.empty(s, dtype=torch.float32, device="cuda")
+    P.mesh_fill_random(m, L, 3, x)
+    k = torch.full_like(x, 2.0)
+    y, y1 = torch.empty_like(x), torch.empty_like(x)
+    P.apply_varcoef(m, L, k, x, y)
+    P.apply_stencil(m, L, x, y1)
+    torch.cuda.synchronize()
+    N = 1 << L
+    rows = torch.arange(N + 1, device="cuda", dtype=torch.int64)
+    lengths = N + 1 - rows
+    Y = torch.repeat_interleave(rows, lengths)
+    X = torch.arange(s, device="cuda", dtype=torch.int64) - (torch.cumsum(lengths, 0) - lengths)[Y]
+    inner = (X >= 1) & (Y >= 1) & (X + Y <= N - 1)
+    del rows, lengths, X, Y
+    assert bool((y[~inner] == x[~inner]).all())
+    # each row sums 18 products of |x| <= 1 with element-matrix entries of the order of
+    # the centre weight, in FP32, in both applies
+    wc = float(np.abs(P.mesh_stencil(m, L, 0)).sum())
+    err = (y[inner].double() - 2.0 * y1[inner].double()).abs().max().item()
+    assert err <= 256 * 2.0 ** -24 * 2.0 * wc, err
