@@ -250,3 +250,27 @@ def test_transfers_full_size(dim, L, dtype):
         inner &= zc >= 1
     assert bool(torch.isfinite(bc).all())
     assert bool((bc[inner] == (4.0 if dim == 2 else 8.0)).all())
+
+
+@pytest.mark.parametrize("order", ["canonical", "random"])
+def test_3d_level8_cube_fp32(order):
+    """The FP32 3D apply (the mixed solver's sweeps) on the benchmark cube:
+    sampled rows against the oracle's FP64 rows of the same (FP32-rounded)
+    keyed input, within 16 u32 of the row's absolute weight sum."""
+    co, ce = W.kuhn_cube(order, 5)
+    L = 8
+    N = 1 << L
+    m = P.create_macro_mesh(co, ce, L)
+    s, _ = P.mesh_num_dofs(m, L)
+    x = torch.empty(s, dtype=torch.float32, device="cuda")
+    P.mesh_fill_random(m, L, 4, x)
+    y = torch.empty_like(x)
+    P.apply_stencil(m, L, x, y)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(46)
+    ml = _samples_3d(N, 6, rng)
+    err, scale, _ = _check_sampled(co, ce, m, L, y, 4, ml, None)
+    w = max(np.abs(P.mesh_stencil(m, L, c)).sum() for c in range(6))
+    # the oracle evaluates the FP64 input; FP32 rounding of x (u32 |x|) and of
+    # the 15-term sums stays within a few u32 of sum |w|
+    assert err.max() <= 16 * U32 * w, (err.max(), w)
