@@ -66,7 +66,7 @@ def _rand(m, L, seed, dtype=torch.float64):
 CASES = [("tri_ref", 8), ("tri_affine", 6), ("tri_affine", 9), ("square", 7), ("strip2d", 6),
          ("strip2d_shuf", 5), ("tri_affine", 0), ("tri_affine", 1), ("tri_affine", 2), ("strip2d", 3),
          ("tet", 5), ("cube", 4), ("cube_random", 5), ("strip3d", 4), ("cube", 1), ("cube_random", 2),
-         ("tet", 3), ("cube_random", 6)]
+         ("tet", 3), ("cube_random", 6), ("tet", 0), ("cube", 0), ("tri_ref", 0)]
 
 
 @pytest.mark.parametrize("name,L", CASES)
