@@ -1,0 +1,222 @@
+"""Parity of the 3D kernels that the cube benchmarks run, against the oracle.
+
+From N = 128 (level 7) on, 3D stencil launches use pencils of 8 slices
+instead of 4, a separate kernel instance with its own slice ring and
+right-hand-side double buffer.  These tests run that instance at level 7 on
+the 6-tet unit cube in both vertex orders (the canonical Kuhn order and a
+seeded random order per tet) and compare every storage DoF with the oracle's
+CSR (2,146,689 unique DoFs): the apply, three Jacobi sweeps and the residual
+with its norm, in FP64 (1e-12 relative, max norm) and FP32 (the rounding
+bound of the parity tests).  The CG solver's fused apply + dot mode is
+checked through solves whose residual the oracle recomputes, the batched
+launches through a level-7 member that must equal its solve alone, and the
+mixed-precision solve of the benchmark (cube level 8) against the closed-form
+discrete solution.
+"""
+import numpy as np
+import pytest
+
+import harness
+import paper_2305_15116_amd as P
+from oracle.oracle import OracleMesh
+from paper_2305_15116_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+L7 = 7
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+_CACHE = {}
+
+
+def _cube(order):
+    """Mesh, oracle mesh, storage -> unique map and the Dirichlet CSR at level 7."""
+    if order not in _CACHE:
+        co, ce = W.kuhn_cube() if order == "canonical" else W.kuhn_cube("random", 5)
+        m = P.create_macro_mesh(co, ce, L7)
+        om = OracleMesh(co, ce, L7)
+        s2u = harness.storage_to_unique(P.mesh_dof_keys(m, L7), om.keys())
+        _CACHE[order] = (co, ce, m, om, s2u, om.csr(dirichlet=True))
+    return _CACHE[order]
+
+
+def _rand(m, seed, dtype):
+    s, _ = P.mesh_num_dofs(m, L7)
+    x = torch.empty(s, dtype=dtype, device="cuda")
+    P.mesh_fill_random(m, L7, seed, x)
+    return x
+
+
+@pytest.mark.parametrize("order", ["canonical", "random"])
+def test_apply_level7_every_dof(order):
+    co, ce, m, om, s2u, A = _cube(order)
+    assert om.N == 128 and om.n == 129 ** 3
+    for dtype in (torch.float64, torch.float32):
+        x = _rand(m, 71, dtype)
+        y = torch.full_like(x, float("nan"))
+        P.apply_stencil(m, L7, x, y)
+        torch.cuda.synchronize()
+        xo = om.keyed_random(71)
+        ys = y.cpu().numpy()
+        assert np.isfinite(ys).all()
+        assert harness.copies_consistent(ys, s2u)
+        if dtype == torch.float64:
+            assert np.array_equal(x.cpu().numpy(), xo[s2u]), "keyed generators disagree"
+            assert harness.rel_err_max(ys, om.spmv(xo)[s2u]) <= 1e-12
+        else:
+            x32 = xo.astype(np.float32).astype(np.float64)
+            bound = 16 * U32 * (abs(A) @ np.abs(x32))
+            assert (np.abs(ys.astype(np.float64) - (A @ x32)[s2u]) <= bound[s2u] + 1e-30).all()
+
+
+@pytest.mark.parametrize("order", ["canonical", "random"])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_smooth_and_residual_level7_every_dof(order, dtype):
+    co, ce, m, om, s2u, A = _cube(order)
+    x = _rand(m, 72, dtype)
+    b = _rand(m, 73, dtype)
+    tmp = torch.empty_like(x)
+    r = torch.empty_like(x)
+    omega = 2.0 / 3.0
+    nrm = P.residual(m, L7, b, x, r, norm=True)
+    P.smooth(m, L7, omega, 3, b, x, tmp)
+    torch.cuda.synchronize()
+    xo, bo = om.keyed_random(72), om.keyed_random(73)
+    if dtype == torch.float32:
+        xo, bo = xo.astype(np.float32).astype(np.float64), bo.astype(np.float32).astype(np.float64)
+    ro = bo - A @ xo
+    rs = r.cpu().numpy()
+    assert harness.copies_consistent(rs, s2u)
+    if dtype == torch.float64:
+        assert harness.rel_err_max(rs, ro[s2u]) <= 1e-12
+        assert abs(nrm - np.linalg.norm(ro)) <= 1e-12 * np.linalg.norm(ro)
+    else:
+        # forward error of b - sum of 15 fused products, all operands rounded to FP32
+        bound = 16 * U32 * (np.abs(bo) + abs(A) @ np.abs(xo))
+        assert (np.abs(rs.astype(np.float64) - ro[s2u]) <= bound[s2u] + 1e-30).all()
+        assert abs(nrm - np.linalg.norm(ro)) <= 1e-5 * np.linalg.norm(ro)
+    bnd = om.boundary()
+    d = A.diagonal()
+    xs = xo.copy()
+    for _ in range(3):
+        xs = np.where(bnd, xs, xs + omega / d * (bo - A @ xs))
+    out = x.cpu().numpy()
+    assert harness.copies_consistent(out, s2u)
+    assert harness.rel_err_max(out.astype(np.float64), xs[s2u]) <= (1e-12 if dtype == torch.float64 else 2e-5)
+
+
+def _rhs(m, om, s2u, seed):
+    """Keyed b with Dirichlet entries zeroed, on the device and for the oracle."""
+    b = _rand(m, seed, torch.float64)
+    P.mesh_set_dirichlet(m, L7, None, b)
+    bo = om.keyed_random(seed)
+    bo[om.boundary()] = 0.0
+    return b, bo
+
+
+@pytest.mark.parametrize("order,mode", [("canonical", 2), ("random", 3)])
+def test_cg_level7_residual_by_oracle(order, mode):
+    """CG's search-direction product runs the fused apply + dot instance; a
+    wrong row or dot would leave the oracle's residual above the tolerance."""
+    co, ce, m, om, s2u, A = _cube(order)
+    b, bo = _rhs(m, om, s2u, 74)
+    x = torch.zeros_like(b)
+    ws = torch.empty(P.mesh_workspace_bytes(m, L7, mode), dtype=torch.uint8, device="cuda")
+    rc, it, rel, _ = P.vcycle_solve(m, L7, b, x, ws, mode=mode, rtol=1e-10, max_iter=100)
+    torch.cuda.synchronize()
+    assert rc == P.MF_OK and rel <= 1e-10, (rc, it, rel)
+    xs = x.cpu().numpy()
+    assert harness.copies_consistent(xs, s2u)
+    xu = np.zeros(om.n)
+    xu[s2u] = xs
+    res = np.linalg.norm(bo - om.spmv(xu)) / np.linalg.norm(bo)
+    assert res <= 1.01e-10
+    assert abs(rel - res) <= 1e-2 * res, (rel, res)
+
+
+@pytest.mark.parametrize("mode", [1, 3])
+def test_batch_level7_member_equals_alone(mode):
+    """A level-7 cube member in a batch with small 2D and 3D members: the
+    batched launches of the pencil-depth-8 instance give bitwise its solve
+    alone."""
+    co, ce, m7, om, s2u, A = _cube("random")
+    b7, _ = _rhs(m7, om, s2u, 75)
+    reqs = [(m7, L7, b7)]
+    for dim, k, L, seed in ((2, 3, 6, 1), (3, 2, 4, 2)):
+        c2, e2 = W.strip_2d(k) if dim == 2 else W.strip_3d(k)
+        J, t = W.random_affine(dim, seed)
+        mm = P.create_macro_mesh(W.apply_affine(c2, J, t), W.shuffle_cell_orders(e2, seed), L)
+        s, _ = P.mesh_num_dofs(mm, L)
+        bb = torch.empty(s, dtype=torch.float64, device="cuda")
+        P.mesh_fill_random(mm, L, 80 + seed, bb)
+        P.mesh_set_dirichlet(mm, L, None, bb)
+        reqs.append((mm, L, bb))
+    alone = []
+    for mm, L, bb in reqs:
+        x = torch.zeros_like(bb)
+        ws = torch.empty(P.mesh_workspace_bytes(mm, L, mode), dtype=torch.uint8, device="cuda")
+        rc, it, rel, _ = P.vcycle_solve(mm, L, bb, x, ws, mode=mode, rtol=1e-9, max_iter=100)
+        torch.cuda.synchronize()
+        alone.append((rc, it, rel, x))
+    batch = P.batch_create(len(reqs), mode=mode, max_iter=100)
+    xs, keep, done = [], [], {}
+    for tag, (mm, L, bb) in enumerate(reqs):
+        x = torch.zeros_like(bb)
+        ws = torch.empty(P.mesh_workspace_bytes(mm, L, mode), dtype=torch.uint8, device="cuda")
+        P.batch_add(batch, mm, L, bb, x, ws, 1e-9, tag)
+        xs.append(x)
+        keep.append(ws)
+    for _ in range(300):
+        for tag, st, it, rel, _ in P.batch_step(batch):
+            done[tag] = (st, it, rel)
+        if len(done) == len(reqs):
+            break
+    for tag, (rc, it, rel, x) in enumerate(alone):
+        assert rc == P.MF_OK
+        assert done[tag] == (rc, it, rel), (tag, done[tag], (rc, it, rel))
+        assert torch.equal(xs[tag], x), tag
+
+
+@pytest.mark.parametrize("mode", [1, 3])
+def test_benchmark_solve_cube_level8_against_discrete_solution(mode):
+    """The mixed-precision solve of the benchmark (cube level 8, lumped load of
+    f = 3 pi^2 sin(pi x) sin(pi y) sin(pi z), V(2,2), omega 2/3, 1e-10).  On
+    this mesh b = A u_h with u_h = u* (pi^2 h^2 / 4) / sin^2(pi h / 2), the
+    lowest eigenvector of A, so ||x - u_h||_2 <= rtol ||u_h||_2 over unique
+    DoFs; storage copies (at most 6 per DoF) give the factor sqrt(6)."""
+    co, ce = W.kuhn_cube()
+    L = 8
+    m = P.create_macro_mesh(co, ce, L)
+    s, u = P.mesh_num_dofs(m, L)
+    assert (s, u) == (17173254, 16974593)
+    v, w = P.mesh_dof_keys(m, L)
+    N = 1 << L
+    xyz = np.zeros((s, 3))
+    for k in range(4):
+        ok = v[:, k] >= 0
+        xyz[ok] += (w[ok, k:k + 1] / N) * co[v[ok, k]]
+    h = 1.0 / N
+    us = np.prod(np.sin(np.pi * xyz), axis=1)
+    b = torch.as_tensor(h ** 3 * 3 * np.pi ** 2 * us, device="cuda")
+    x = torch.zeros_like(b)
+    ws = torch.empty(P.mesh_workspace_bytes(m, L, mode), dtype=torch.uint8, device="cuda")
+    rc, it, rel, _ = P.vcycle_solve(m, L, b, x, ws, mode=mode, rtol=1e-10)
+    torch.cuda.synchronize()
+    assert rc == P.MF_OK and rel <= 1e-10, (rc, it, rel)
+    uh = us * (np.pi ** 2 * h ** 2 / 4) / np.sin(np.pi * h / 2) ** 2
+    xs = x.cpu().numpy()
+    assert np.linalg.norm(xs - uh) <= np.sqrt(6) * 1.01e-10 * np.linalg.norm(uh)
+    # the discretisation error of the P1 solution at the nodes, about pi^2 h^2 / 12
+    assert np.abs(xs - us).max() <= 1.05 * (np.pi ** 2 * h ** 2 / 12)
+    del ws, x, b
+    P.destroy_macro_mesh(m)
