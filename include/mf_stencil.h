@@ -217,10 +217,14 @@ typedef struct {
  * every CG scalar stays on the device).  x_dev holds the initial guess (its
  * Dirichlet entries are set to b's); workspace_dev must hold
  * mesh_workspace_bytes(level, opts->mode) bytes.  The stopping test uses the
- * FP64 residual over unique DoFs (recomputed each iteration in modes 0, 1;
- * the CG recurrence in modes 2, 3).  Returns MF_OK, MF_NOT_CONVERGED (x =
- * last iterate) or an error.  Synchronous; one device-to-host copy of two
- * doubles per iteration. */
+ * true FP64 residual b - A x over unique DoFs: recomputed each iteration in
+ * modes 0, 1; in modes 2, 3 the CG recurrence's residual decides when to
+ * recompute it, and MF_OK is returned only if the recomputed one meets rtol
+ * (otherwise CG goes on).  info->rel_res is that true relative residual
+ * (modes 2, 3 after a miss that ends at max_iter: the last recomputed one).
+ * Returns MF_OK, MF_NOT_CONVERGED (x = last iterate) or an error.
+ * Synchronous; one device-to-host copy of two doubles per iteration, plus
+ * one per recomputed residual in modes 2, 3. */
 int vcycle_solve(const mf_mesh* mesh, int level, const double* b_dev, double* x_dev, void* workspace_dev,
                  const mf_solve_opts* opts, mf_solve_info* info, void* stream);
 
@@ -259,7 +263,10 @@ int batch_add(mf_batch* batch, const mf_mesh* mesh, int level, const double* b_d
  * (MF_NOT_CONVERGED) or met a non-finite norm (MF_ENUMERIC) — leave the
  * batch and are reported in done_tags / done_status / done_info (each with
  * room for batch_size() entries; done_info may be NULL); *n_done = their
- * number.  done_info.seconds = time since batch_add. */
+ * number.  done_info.seconds = time since batch_add.  In modes 2, 3 a member
+ * whose CG recurrence meets rtol spends its next step on recomputing the
+ * true FP64 residual (no iteration), and finishes only if that meets rtol,
+ * as vcycle_solve does. */
 int batch_step(mf_batch* batch, void* stream, int64_t* done_tags, int* done_status, mf_solve_info* done_info,
                int* n_done);
 

@@ -34,7 +34,9 @@ using namespace mf;
 
 namespace {
 
-enum MemberState { kNew = 0, kRunning = 1 };
+// kVerify (CG modes): the recurrence met rtol in the last step; this step
+// recomputes the true FP64 residual b - A x and performs no iteration.
+enum MemberState { kNew = 0, kRunning = 1, kVerify = 2 };
 
 struct Member {
   int64_t tag = 0;
@@ -272,12 +274,13 @@ void build_plan(mf_batch* B) {
   const bool f32 = mode_f32(o.mode), pcg = mode_pcg(o.mode);
   const int vdt = f32 ? MF_F32 : MF_F64;
   auto slot = [B](const Member& M) { return B->dres + 4 * (&M - B->mem.data()); };
-  std::vector<Member*> all, corr, fresh;
+  std::vector<Member*> all, corr, fresh, verify;
   for (size_t i = 0; i < B->mem.size(); ++i) {
     Member* M = &B->mem[i];
     all.push_back(M);
     if (M->correct) corr.push_back(M);
     if (M->state == kNew) fresh.push_back(M);
+    if (M->state == kVerify) verify.push_back(M);
   }
   for (int dim = 2; dim <= 3; ++dim) {
     // ---- V-cycle correction (members with a residual that did not converge)
@@ -439,6 +442,23 @@ void build_plan(mf_batch* B) {
       ra.push_back({ReduceArgs{M->w.part, stencil_partials(lev(*M, M->level), MF_F64), M->w.result, slot(*M), 0, 0}, 1});
     reduce_op(P, ra);
   }
+  // ---- CG members whose recurrence met rtol: the true residual, as vcycle_solve
+  // recomputes it (into q and result[6..7], which no recurrence reads)
+  if (verify.empty()) return;
+  for (int dim = 2; dim <= 3; ++dim)
+    stencil_op(P, verify, dim, MF_F64, kResidual, 0.0, [](const Member& M, Pass& p) {
+      p.level = M.level;
+      p.x = M.x;
+      p.y = M.w.q64;
+      p.b = M.b;
+      p.part = M.w.part;
+      return true;
+    });
+  std::vector<std::pair<ReduceArgs, int>> ra;
+  for (Member* M : verify)
+    ra.push_back(
+        {ReduceArgs{M->w.part, stencil_partials(lev(*M, M->level), MF_F64), M->w.result + 6, slot(*M), 0, 0}, 1});
+  reduce_op(P, ra);
 }
 
 int upload_plan(mf_batch* B, hipStream_t s) {
@@ -602,24 +622,41 @@ int batch_step(mf_batch* B, void* stream, int64_t* done_tags, int* done_status, 
       M.state = kRunning;
       changed = true;
     }
+    bool verify_next = false;
     if (running) {
       if (!std::isfinite(r[0]) || !std::isfinite(r[1])) {
         status = MF_ENUMERIC;
         running = false;
       } else {
+        const bool verified = M.state == kVerify;  // r holds the true residual
         M.rel = M.bnorm > 0.0 ? std::sqrt(r[0]) / M.bnorm : std::sqrt(r[0]);
         if (M.rel <= M.rtol || r[1] == 0.0) {
-          status = MF_OK;
-          running = false;
-        } else if (M.iters >= B->o.max_iter) {
+          if (mode_pcg(B->o.mode) && M.iters > 0 && !verified) {
+            verify_next = true;  // the recurrence says converged: confirm on b - A x first
+          } else {
+            status = MF_OK;
+            running = false;
+          }
+        }
+        if (running && !verify_next && M.iters >= B->o.max_iter) {
           status = MF_NOT_CONVERGED;
           running = false;
+        }
+        if (verified) {
+          M.state = kRunning;
+          changed = true;
         }
       }
     }
     if (running) {
-      if (!M.correct) changed = true;
-      M.correct = true;
+      if (verify_next) {
+        M.state = kVerify;
+        M.correct = false;
+        changed = true;
+      } else {
+        if (!M.correct) changed = true;
+        M.correct = true;
+      }
       keep.push_back(std::move(M));
       continue;
     }

@@ -386,8 +386,20 @@ int vcycle_solve(const mf_mesh* m, int level, const double* b, double* x, void* 
   for (;;) {
     rel = bnorm > 0.0 ? std::sqrt(ss) / bnorm : std::sqrt(ss);
     if (rel <= o.rtol || mx == 0.0) {
-      converged = true;
-      break;
+      if (pcg && it > 0) {
+        // The CG recurrence says converged: confirm it on the true FP64
+        // residual b - A x (into q, which the next iteration overwrites, and
+        // result[6..7], which no recurrence reads), and report that value.
+        // If it misses the tolerance the recurrence goes on unchanged.
+        double ts = 0.0, tm = 0.0;
+        rc = residual_norm(m, L, MF_F64, b, x, w.q64, w.part, w.result + 6, &ts, &tm, s);
+        if (rc) return rc;
+        rel = bnorm > 0.0 ? std::sqrt(ts) / bnorm : std::sqrt(ts);
+        converged = rel <= o.rtol || tm == 0.0;
+      } else {
+        converged = true;
+      }
+      if (converged) break;
     }
     if (it >= o.max_iter) break;
     // preconditioner / correction: one V-cycle on r from zero

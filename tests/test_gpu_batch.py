@@ -102,8 +102,7 @@ def test_batch_solution_against_oracle(mode):
     xu = np.zeros(om.n)
     xu[s2u] = x.cpu().numpy()
     bo = om.keyed_random(77)
-    # CG (mode 3) stops on its recurred residual, which may trail the true one slightly
-    assert np.linalg.norm(bo - om.spmv(xu)) / np.linalg.norm(bo) <= (1.01 if mode < 2 else 1.5) * 1e-10
+    assert np.linalg.norm(bo - om.spmv(xu)) / np.linalg.norm(bo) <= 1.01e-10
 
 
 @pytest.mark.parametrize("mode", [1, 3])
