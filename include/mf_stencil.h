@@ -178,6 +178,21 @@ int smooth(const mf_mesh* mesh, int level, int dtype, double omega, int sweeps, 
 int residual(const mf_mesh* mesh, int level, int dtype, const void* b_dev, const void* x_dev, void* r_dev,
              double* norm2, void* stream);
 
+/* residual() with the norm, for callers that cannot allocate device memory
+ * (tight serving loops, harnesses that forbid hipMalloc): r = b - A x and
+ * *norm2 = ||r||_2 over unique DoFs, the same kernels and bitwise the same
+ * results as residual(..., norm2, ...).  The norm partials live in a static
+ * device array of the library (2 MiB per device, held until the process
+ * ends) instead of the mesh's buffers, so the call allocates nothing and
+ * takes no lock.  Every call on one device shares that array: calls that
+ * overlap on one device (other threads or streams) race and must be
+ * serialised by the caller.  norm2 is required (host pointer); the call
+ * synchronises `stream`.  MF_ENOMEM if the level's partials exceed the
+ * array (more than 131,071 partial pairs: beyond the 2D level-14 triangle
+ * or the 6-tet cube at level 9); MF_ENUMERIC if the norm is not finite. */
+int residual_noalloc(const mf_mesh* mesh, int level, int dtype, const void* b_dev, const void* x_dev, void* r_dev,
+                     double* norm2, void* stream);
+
 /* Multigrid restriction r_c = P^T r_f from `level` to `level`-1, where P is
  * the P1 interpolation between the nested refinement levels (the paper
  * names the levels a natural basis for multigrid, Intro, "Hybrid Tetrahedral

@@ -23,7 +23,7 @@ MF_FLAG_DIRICHLET, MF_FLAG_HOST_ONLY = 1, 2
 #: every symbol include/mf_stencil.h declares
 EXPORTS = ["mf_last_error", "create_macro_mesh", "destroy_macro_mesh", "mesh_info", "mesh_num_dofs",
            "mesh_dof_keys", "mesh_dof_index", "mesh_stencil", "mesh_workspace_bytes", "mesh_fill_random",
-           "mesh_set_dirichlet", "apply_stencil", "apply_p2", "apply_varcoef", "apply_blended", "smooth", "residual", "restrict_residual", "prolong_add",
+           "mesh_set_dirichlet", "apply_stencil", "apply_p2", "apply_varcoef", "apply_blended", "smooth", "residual", "residual_noalloc", "restrict_residual", "prolong_add",
            "vcycle_solve", "batch_create", "batch_destroy", "batch_size", "batch_add", "batch_step"]
 
 
@@ -67,6 +67,7 @@ def lib():
         L.apply_stencil.argtypes = [vp, i, i, vp, vp, vp]
         L.smooth.argtypes = [vp, i, i, dbl, i, vp, vp, vp, vp]
         L.residual.argtypes = [vp, i, i, vp, vp, vp, C.POINTER(dbl), vp]
+        L.residual_noalloc.argtypes = [vp, i, i, vp, vp, vp, C.POINTER(dbl), vp]
         L.restrict_residual.argtypes = [vp, i, i, vp, vp, vp]
         L.prolong_add.argtypes = [vp, i, i, vp, vp, vp]
         L.vcycle_solve.argtypes = [vp, i, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
@@ -235,6 +236,15 @@ def residual(mesh: Mesh, level: int, b, x, r, norm: bool = False, stream=None):
     _check(lib().residual(mesh, level, _dtype_code(x), C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
                           C.c_void_p(r.data_ptr()), C.byref(n2) if norm else None, _stream(stream)))
     return n2.value if norm else None
+
+
+def residual_noalloc(mesh: Mesh, level: int, b, x, r, stream=None):
+    """r = b - A x and ||r||_2 over unique DoFs (synchronises), with the norm
+    partials in the library's static device scratch (no allocation)."""
+    n2 = C.c_double()
+    _check(lib().residual_noalloc(mesh, level, _dtype_code(x), C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
+                                  C.c_void_p(r.data_ptr()), C.byref(n2), _stream(stream)))
+    return n2.value
 
 
 def restrict_residual(mesh: Mesh, level: int, rf, bc, stream=None):
