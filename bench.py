@@ -13,8 +13,9 @@ the 8 TB/s HBM3E peak.  cpu_baseline: the oracle's CSR row loop on the host
 cores for a bounded sample.  extra: the FP32 apply, the 3D 6-tet cube apply,
 the fused 2D P2 apply (vertex and edge DoFs, level 13: the same 134,242,305
 DoFs), the variable-coefficient apply (weights formed on the fly from a nodal
-coefficient, level 14), a device copy for reference, and the mixed-precision
-vs FP64 V-cycle solve.
+coefficient, level 14), the library's streaming copy (the measured-copy
+denominator of the roofline), and the mixed-precision vs FP64 V-cycle solve
+with its algorithmic bytes per iteration and fraction of HBM peak.
 """
 from __future__ import annotations
 
@@ -123,54 +124,88 @@ def bench_blended(P, torch, co, ce, L, steps, warmup):
     return {"storage": s, "unique": u, **r}
 
 
-def copy_bandwidth(torch, nbytes=2 * 1024 ** 3, reps=20):
+def copy_bandwidth(P, torch, nbytes=1 << 30, reps=20):
+    """Read + write GB/s of the library's streaming copy (device_copy: 16-byte
+    loads, non-temporal 16-byte stores) and of torch's copy_, both over 1 GiB,
+    each launch timed with HIP events on the launch stream."""
     a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
     a.fill_(1.0)
-    for _ in range(3):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    return 2 * nbytes / (ms * 1e-3) / 1e9
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, call in (("device_copy", lambda st: P.device_copy(b, a, st)), ("torch_copy", lambda st: b.copy_(a))):
+        r = _launch_times(torch, stream, call, reps, 3)
+        out[name] = 2 * nbytes / (r["launch_avg_ms"] * 1e-3) / 1e9
+    del a, b
+    return out
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
+
+
+def _time_oracle(om, budget_s, single_reps):
+    """Median seconds of the oracle's CSR row loop on all host threads (reps
+    fitted to budget_s) and on one thread."""
+    nnz = om._native(True)
+    nthreads = os.cpu_count() or 1
+    t, used = om.time_spmv(nthreads, 2, 3)
+    per = float(sorted(t)[len(t) // 2])
+    reps = max(5, min(400, int(budget_s / max(per, 1e-6))))
+    t, used = om.time_spmv(nthreads, 0, reps)
+    med = float(sorted(t)[len(t) // 2])
+    t1, _ = om.time_spmv(1, 1, single_reps)
+    med1 = float(sorted(t1)[len(t1) // 2])
+    csr_bytes = om.n * 8 * 2 + nnz * 16 + (om.n + 1) * 8  # x, y, values + column indices, row pointers
+    return med, med1, reps, int(used), nnz, csr_bytes
 
 
 def cpu_baseline(W, budget_s=20.0):
     """The oracle's CSR row loop on all host cores for a bounded sample of the
-    same workload: the same affine triangle at level 11."""
+    same workload: the same affine triangle at level 13 (33.6M DoFs, a CSR of
+    about 3.8 GB, far beyond the host caches)."""
     from oracle.oracle import OracleMesh
     co, ce = W.affine_triangle(2)
-    L = 11
+    L = 13
     t0 = time.time()
     om = OracleMesh(co, ce, L)
-    om.csr(dirichlet=True)
+    om._native(True)
     t_build = time.time() - t0
+    med, med1, reps, used, nnz, csr_bytes = _time_oracle(om, budget_s, 3)
+    out = {"value": om.n / med / 1e9, "unit": "GDoF/s", "cores": used, "kind": "oracle",
+           "sample": f"same affine triangle at level {L} ({om.n} DoFs, {nnz} CSR entries, {csr_bytes / 1e9:.2f} GB "
+                     f"moved per product): CSR row loop y = A x, median of {reps} reps on {used} threads; CSR "
+                     f"assembly ({t_build:.1f} s) excluded",
+           "csr_GBps": csr_bytes / med / 1e9, "single_thread_GDoF_s": om.n / med1 / 1e9, "cpu_model": _cpu_model(),
+           "nproc": os.cpu_count()}
+    del om
+    return out
+
+
+def cpu_oracle_cube(W, L=8, reps=100):
+    """The oracle on the 3D benchmark mesh (6-tet cube, level 8: 16,974,593
+    unique DoFs, 15-entry rows): CSR row loop, median of `reps` products on
+    all host threads and of 5 on one thread."""
+    from oracle.oracle import OracleMesh
+    t0 = time.time()
+    om = OracleMesh(*W.kuhn_cube(), L)
+    om._native(True)
+    t_build = time.time() - t0
+    med, med1, _, used, nnz, csr_bytes = _time_oracle(om, 1e9, 5)
     nthreads = os.cpu_count() or 1
-    t, used = om.time_spmv(nthreads, 3, 5)
-    per = float(sorted(t)[len(t) // 2])
-    reps = max(10, min(400, int(budget_s / max(per, 1e-6))))
-    t, used = om.time_spmv(nthreads, 0, reps)
+    t, used = om.time_spmv(nthreads, 3, reps)
     med = float(sorted(t)[len(t) // 2])
-    t1, _ = om.time_spmv(1, 3, 10)
-    med1 = float(sorted(t1)[len(t1) // 2])
-    model = ""
-    try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                model = line.split(":", 1)[1].strip()
-                break
-    except OSError:
-        pass
-    return {"value": om.n / med / 1e9, "unit": "GDoF/s", "cores": int(used), "kind": "oracle",
-            "sample": f"same affine triangle at level {L} ({om.n} DoFs): CSR row loop y = A x, median of {reps} "
-                      f"reps on {used} threads; CSR assembly ({t_build:.1f} s) excluded",
-            "csr_GBps": (om.n * 8 * 2 + om.csr().nnz * 16 + (om.n + 1) * 8) / med / 1e9,
-            "single_thread_GDoF_s": om.n / med1 / 1e9, "cpu_model": model, "nproc": os.cpu_count()}
+    out = {"GDoF_s": om.n / med / 1e9, "single_thread_GDoF_s": om.n / med1 / 1e9, "threads": int(used),
+           "reps": reps, "csr_GBps": csr_bytes / med / 1e9, "nnz": nnz, "assembly_s": t_build,
+           "cpu_model": _cpu_model(), "nproc": os.cpu_count()}
+    del om
+    return out
 
 
 def traffic_for(kernel_hash):
@@ -181,6 +216,26 @@ def traffic_for(kernel_hash):
     if d.get("kernel_source_sha256") != kernel_hash:
         return None
     return d.get("bytes_per_launch")
+
+
+def solve_bytes(P, m, L, mode, iters, lc=2):
+    """Algorithmic HBM bytes of one vcycle_solve with V(2,2) cycles: every
+    vector a kernel of the solve must read or write, once (interface and
+    coarse-solve traffic excluded).  Per V-cycle level l above the coarse
+    level (storage S_l, precision e bytes: 8 FP64, 4 FP32 cycles): first
+    sweep from zero 2e, second sweep 3e, residual 3e, restriction e + e S_{l-1}/S_l,
+    prolongation e S_{l-1}/S_l + 2e, two post-sweeps 6e.  Outer step per fine
+    DoF: refinement x += e and r = b - A x (FP64 48, mixed 56 with the
+    scaled cast); CG r.z, direction, A p with p.Ap, x/r update (FP64 104,
+    mixed 108 with the cast).  Set-up: norm of b and the first residual (32),
+    plus one recomputed residual (24) at CG termination."""
+    S = [P.mesh_num_dofs(m, l)[0] for l in range(L + 1)]
+    e = 4 if mode & 1 else 8
+    cycle = sum((17 * e + 2 * e * S[l - 1] / S[l]) * S[l] for l in range(lc + 1, L + 1))
+    outer = {0: 48, 1: 56, 2: 104, 3: 108}[mode] * S[L]
+    setup = (32 + (24 if mode & 2 else 0)) * S[L]
+    return {"per_iteration": cycle + outer, "per_iteration_B_per_dof": (cycle + outer) / S[L],
+            "per_solve": setup + iters * (cycle + outer)}
 
 
 def solve_bench(P, torch, W, L=8, repeats=10):
@@ -217,9 +272,14 @@ def solve_bench(P, torch, W, L=8, repeats=10):
         xs = x.cpu().numpy()
         err = float(np.abs(xs - uh).max())
         err_cont = float(np.abs(xs - us).max())
+        by = solve_bytes(P, m, L, mode, it)
         out[names[mode]] = {"mode": mode, "status": rc, "iters": it, "rel_res": rel, "ms_per_solve": dt * 1e3,
-                            "solves_per_s": 1.0 / dt, "max_err_vs_discrete_solution": err,
-                            "max_err_vs_continuous_solution": err_cont}
+                            "ms_per_iteration": dt * 1e3 / max(it, 1), "solves_per_s": 1.0 / dt,
+                            "algorithmic_B_per_dof_per_iteration": round(by["per_iteration_B_per_dof"], 1),
+                            "algorithmic_GB_per_solve": by["per_solve"] / 1e9,
+                            "achieved_GBps": by["per_solve"] / dt / 1e9,
+                            "frac_of_hbm_peak": by["per_solve"] / dt / 1e9 / HBM_PEAK_GBS,
+                            "max_err_vs_discrete_solution": err, "max_err_vs_continuous_solution": err_cont}
         del ws
     P.destroy_macro_mesh(m)
     return out
@@ -237,6 +297,11 @@ def serve_bench(torch, variant, n, util=0.75, budget_gib=None, calib_n=40, serve
     budget = int(budget_gib * 2 ** 30)
     levels3 = (5, 8) if variant == "capped" else (5, 11)
     out = {"variant": variant, "n": n, "budget_GiB": budget_gib}
+    if variant == "capped":
+        out["deviation"] = ("not the stated serving workload: 3D levels 5-8 instead of 5-11, and an arrival rate of "
+                            f"{util:.0%} of the plain server's measured capacity instead of 200 requests/s, whose "
+                            "offered load (3D levels 9-11 with up to 64 tets) exceeds one GPU; --serve full runs "
+                            "the stated workload")
     if variant == "capped":
         sample = loadgen.requests(n=calib_n, rate=1.0, levels3=levels3, seed_arrival=16, seed_req=17)
         srv = serving.Server(budget, batched=False, keep_solutions=False)
@@ -301,6 +366,8 @@ def main():
     ap.add_argument("--serve-n", type=int, default=None, help="requests of the serving run")
     ap.add_argument("--serve-servers", choices=["both", "plain", "batched"], default="both",
                     help="which servers the serving run measures")
+    ap.add_argument("--cpu-cube", action="store_true",
+                    help="also time the oracle on the 3D benchmark mesh (cube level 8, 100 products; assembly takes minutes)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device copy of 1 GiB (counter calibration for profiles)")
     args = ap.parse_args()
@@ -379,9 +446,12 @@ def main():
             "GB_s": 16 * rb["unique"] / (rb["launch_avg_ms"] * 1e-3) / 1e9,
             "launch_avg_ms": rb["launch_avg_ms"], "dofs": rb["unique"], "algorithmic_B_per_dof": 16}
         log("device copy reference")
-        cbw = copy_bandwidth(torch)
-        extra["device_copy_GBps"] = cbw
-        extra["apply2d_frac_of_copy"] = achieved / cbw
+        cbw = copy_bandwidth(P, torch)
+        extra["device_copy_GBps"] = cbw["device_copy"]
+        extra["torch_copy_GBps"] = cbw["torch_copy"]
+        extra["apply2d_frac_of_copy"] = achieved / cbw["device_copy"]
+        roofline["measured_copy_GBps"] = round(cbw["device_copy"], 1)
+        roofline["frac_of_measured_copy"] = round(achieved / cbw["device_copy"], 4)
         if not args.skip_solve:
             log("solve: mixed vs fp64, cube level 8")
             extra["solve_cube_l8"] = solve_bench(P, torch, W)
@@ -393,6 +463,9 @@ def main():
     if not args.skip_cpu:
         log("cpu baseline (oracle)")
         cpu = cpu_baseline(W)
+        if args.cpu_cube:
+            log("oracle timing on the cube, level 8")
+            extra["cpu_oracle_cube_l8"] = cpu_oracle_cube(W)
     line = {
         "metric": "stencil-apply GDoF/s & % HBM peak; batched-solve p50/p99 latency vs plain",
         "value": round(gdofs, 3), "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

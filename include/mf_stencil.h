@@ -243,6 +243,15 @@ typedef struct {
 int vcycle_solve(const mf_mesh* mesh, int level, const double* b_dev, double* x_dev, void* workspace_dev,
                  const mf_solve_opts* opts, mf_solve_info* info, void* stream);
 
+/* Streaming device copy dst = src of n_bytes (a multiple of 16; both
+ * pointers 16-byte aligned; no overlap): one 16-byte load and one
+ * non-temporal 16-byte store per lane.  The measured copy bandwidth is the
+ * reference the apply's HBM throughput is reported against, beside the
+ * HBM3E peak (the paper measures its machine's load/store bandwidth the same
+ * way before modelling its kernels, Intro, hardware description).  No part
+ * of the operator.  Asynchronous. */
+int device_copy(void* dst_dev, const void* src_dev, int64_t n_bytes, void* stream);
+
 /* ---- Continuous batching of solves (serving) ----------------------------
  * A batch advances many independent solves of the kind vcycle_solve runs
  * (any meshes, dimensions and levels on the current device) together: each

@@ -24,7 +24,7 @@ MF_FLAG_DIRICHLET, MF_FLAG_HOST_ONLY = 1, 2
 EXPORTS = ["mf_last_error", "create_macro_mesh", "destroy_macro_mesh", "mesh_info", "mesh_num_dofs",
            "mesh_dof_keys", "mesh_dof_index", "mesh_stencil", "mesh_workspace_bytes", "mesh_fill_random",
            "mesh_set_dirichlet", "apply_stencil", "apply_p2", "apply_varcoef", "apply_blended", "smooth", "residual", "residual_noalloc", "restrict_residual", "prolong_add",
-           "vcycle_solve", "batch_create", "batch_destroy", "batch_size", "batch_add", "batch_step"]
+           "vcycle_solve", "device_copy", "batch_create", "batch_destroy", "batch_size", "batch_add", "batch_step"]
 
 
 class MFError(RuntimeError):
@@ -71,6 +71,7 @@ def lib():
         L.restrict_residual.argtypes = [vp, i, i, vp, vp, vp]
         L.prolong_add.argtypes = [vp, i, i, vp, vp, vp]
         L.vcycle_solve.argtypes = [vp, i, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
+        L.device_copy.argtypes = [vp, vp, i64, vp]
         L.batch_create.argtypes = [C.POINTER(SolveOpts), i, C.POINTER(vp)]
         L.batch_destroy.argtypes = [vp]
         L.batch_size.argtypes = [vp, C.POINTER(i)]
@@ -245,6 +246,14 @@ def residual_noalloc(mesh: Mesh, level: int, b, x, r, stream=None):
     _check(lib().residual_noalloc(mesh, level, _dtype_code(x), C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
                                   C.c_void_p(r.data_ptr()), C.byref(n2), _stream(stream)))
     return n2.value
+
+
+def device_copy(dst, src, stream=None):
+    """dst = src (same byte size, a multiple of 16): the library's streaming copy."""
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb:
+        raise ValueError("dst and src differ in size")
+    _check(lib().device_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), nb, _stream(stream)))
 
 
 def restrict_residual(mesh: Mesh, level: int, rf, bc, stream=None):

@@ -28,8 +28,14 @@ struct Prec<float> {
 };
 
 // Ordinary (write-back) stores: partial lines at wave boundaries merge in L2.
+#ifndef MF_NT_STORE
+#define MF_NT_STORE 0
+#endif
 template <typename T>
-__device__ __forceinline__ void st(T* p, T v) { *p = v; }
+__device__ __forceinline__ void st(T* p, T v) {
+  if (MF_NT_STORE) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
 
 // A macro's 16 x 16 partial-stencil table (row = support mask).  The stencil
 // kernels keep a copy in LDS, so that the per-lane lookups of boundary lanes

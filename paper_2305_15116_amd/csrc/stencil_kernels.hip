@@ -51,7 +51,7 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 #ifndef MF_RING_U2
-#define MF_RING_U2 4
+#define MF_RING_U2 8
 #endif
 constexpr int kU2 = MF_RING_U2;  // rows loaded ahead (2D)
 static_assert(kTileH2 % kU2 == 0, "ring depth must divide the tile height");
@@ -254,8 +254,10 @@ __device__ __forceinline__ void tile2d(const int x0, const int y0, const MacroDe
     const int yy = y0 + k;
     const T ap = q[k % kU];
     const T bv = MODE != kApply ? qb[k % kU] : T(0);
-    q[k % kU] = ldrow(X, N, y0 + 1 + k + kU, y1, xc);
-    if (MODE != kApply) qb[k % kU] = ldrow(B, N, y0 + k + kU, y1 - 1, xc);
+    // (compile-time guards: a ring slot is refilled only if a later row of
+    // this tile reads it)
+    if (k + kU < kH) q[k % kU] = ldrow(X, N, y0 + 1 + k + kU, y1, xc);
+    if (MODE != kApply && k + kU < kH) qb[k % kU] = ldrow(B, N, y0 + k + kU, y1 - 1, xc);
     if (k >= nrows) continue;
     const T ap_l = up1(ap), ap_r = dn1(ap);
     const T v[7] = {am, am_r, a0_l, a0, a0_r, ap_l, ap};
