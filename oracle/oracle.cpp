@@ -189,6 +189,23 @@ void edge_matrix(int dim, const double* coords, const int64_t* cellv, int64_t N,
   }
 }
 
+// Edge vectors of a micro-triangle of a blended 2D macro (map F = affine
+// part + xi0 xi1 xi2 d, xi = lattice point / N): the affine part as in
+// edge_matrix, plus d times the difference of the bubble between the two
+// lattice points.  The bubble at (i, j) is n(i, j) / N^3 with the integer
+// n(i, j) = (N - i - j) i j, so the difference is formed exactly in integers
+// and divided once: no O(1) mapped coordinates are subtracted from each other.
+void blended_edge_matrix(const double* coords, const int64_t* cellv, int64_t N, const double* d, int64_t (*v)[3],
+                         double E[3][3]) {
+  edge_matrix(2, coords, cellv, N, v, E);
+  auto n = [N](const int64_t* p) { return (N - p[0] - p[1]) * p[0] * p[1]; };
+  const double N3 = (double)N * (double)N * (double)N;
+  for (int k = 0; k < 2; ++k) {
+    const double db = (double)(n(v[k + 1]) - n(v[0])) / N3;
+    for (int r = 0; r < 2; ++r) E[r][k] += db * d[r];
+  }
+}
+
 // E = [X1-X0 | .. | Xd-X0]; lambda_{1..d} = E^{-1}(x - X0), so grad lambda_k
 // is row k of E^{-1}; grad lambda_0 = -sum of the others; |T| = |det E| / d!.
 // Returns false for a degenerate element.
@@ -546,20 +563,9 @@ int64_t or_assemble_blended(or_mesh* m, int dirichlet, const double* d) {
   for (int64_t c = 0; c < m->nc; ++c) {
     const int64_t* cv = &m->cells[c * 3];
     const int64_t* L = &m->lat[c * m->lat_stride];
-    const double* P0 = &m->coords[cv[0] * 2];
-    const double* P1 = &m->coords[cv[1] * 2];
-    const double* P2 = &m->coords[cv[2] * 2];
-    auto map = [&](const int64_t* p, double out[2]) {
-      const double a = (double)p[0] / (double)N, b = (double)p[1] / (double)N;
-      const double bub = (1.0 - a - b) * a * b;
-      for (int r = 0; r < 2; ++r) out[r] = P0[r] + (P1[r] - P0[r]) * a + (P2[r] - P0[r]) * b + bub * d[c * 2 + r];
-    };
     for_each_cell_element(m, c, [&](int64_t (*v)[3]) {
-      double X[3][2];
-      for (int i = 0; i < 3; ++i) map(v[i], X[i]);
-      double E[3][3] = {{0}};
-      for (int k = 0; k < 2; ++k)
-        for (int r = 0; r < 2; ++r) E[r][k] = X[k + 1][r] - X[0][r];
+      double E[3][3];
+      blended_edge_matrix(m->coords.data(), cv, N, &d[c * 2], v, E);
       double K[MAXV][MAXV], vol;
       if (!element_stiffness(2, E, K, &vol)) { bad = true; return; }
       int64_t ids[3];
@@ -753,9 +759,10 @@ int or_lumped_mass(const or_mesh* m, double* mass) {
 // lattice points, for x given by the keyed SplitMix64 generator with `seed`;
 // needs no global build, so it runs at any level.  Sample s is the point
 // sample_lat[s*dim ..] of cell sample_cell[s].  Returns 0, or -1 on bad input.
-int or_sample_rows(int dim, int64_t nv, const double* coords, int64_t nc, const int64_t* cells, int level,
-                   int dirichlet, uint64_t seed, int64_t ns, const int64_t* sample_cell,
-                   const int64_t* sample_lat, double* y, int8_t* is_boundary) {
+namespace {
+int sample_rows_impl(int dim, int64_t nv, const double* coords, int64_t nc, const int64_t* cells, int level,
+                     int dirichlet, uint64_t seed, int64_t ns, const int64_t* sample_cell, const int64_t* sample_lat,
+                     const double* bubble, double* y, int8_t* is_boundary) {
   if (dim != 2 && dim != 3) { g_err = "dim must be 2 or 3"; return -1; }
   Topology topo = build_topology(dim, nc, cells);
   if (!topo.ok) return -1;
@@ -806,7 +813,8 @@ int or_sample_rows(int dim, int64_t nv, const double* coords, int64_t nc, const 
           weights_of(dim, N, v[i], wi);
           xv[i] = keyed_value(seed, make_key(dim, cv2, wi));
         }
-        edge_matrix(dim, coords, cv2, N, v, E);
+        if (bubble) blended_edge_matrix(coords, cv2, N, &bubble[c2 * 2], v, E);
+        else edge_matrix(dim, coords, cv2, N, v, E);
         element_stiffness(dim, E, K, &vol);
         for (int j = 0; j < d1; ++j) acc += K[me][j] * xv[j];
       });
@@ -814,6 +822,23 @@ int or_sample_rows(int dim, int64_t nv, const double* coords, int64_t nc, const 
     y[s] = acc;
   }
   return 0;
+}
+}  // namespace
+
+int or_sample_rows(int dim, int64_t nv, const double* coords, int64_t nc, const int64_t* cells, int level,
+                   int dirichlet, uint64_t seed, int64_t ns, const int64_t* sample_cell,
+                   const int64_t* sample_lat, double* y, int8_t* is_boundary) {
+  return sample_rows_impl(dim, nv, coords, nc, cells, level, dirichlet, seed, ns, sample_cell, sample_lat, nullptr, y,
+                          is_boundary);
+}
+
+// The same rows for the blended 2D operator of or_assemble_blended (bubble:
+// nc x 2 values, one vector d per macro).
+int or_sample_rows_blended(int64_t nv, const double* coords, int64_t nc, const int64_t* cells, int level,
+                           int dirichlet, uint64_t seed, const double* bubble, int64_t ns,
+                           const int64_t* sample_cell, const int64_t* sample_lat, double* y, int8_t* is_boundary) {
+  return sample_rows_impl(2, nv, coords, nc, cells, level, dirichlet, seed, ns, sample_cell, sample_lat, bubble, y,
+                          is_boundary);
 }
 
 // Keyed input values x(key) at (cell, lattice point) pairs, without a global build.

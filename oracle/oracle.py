@@ -61,6 +61,9 @@ def lib():
         L.or_sample_rows.restype = C.c_int
         L.or_sample_rows.argtypes = [C.c_int, C.c_int64, f64p, C.c_int64, i64p, C.c_int, C.c_int,
                                      C.c_uint64, C.c_int64, i64p, i64p, f64p, i8p]
+        L.or_sample_rows_blended.restype = C.c_int
+        L.or_sample_rows_blended.argtypes = [C.c_int64, f64p, C.c_int64, i64p, C.c_int, C.c_int, C.c_uint64, f64p,
+                                             C.c_int64, i64p, i64p, f64p, i8p]
         L.or_keyed_points.restype = C.c_int
         L.or_keyed_points.argtypes = [C.c_int, C.c_int64, i64p, C.c_int, C.c_uint64, C.c_int64, i64p, i64p, f64p]
         L.or_prolongation.restype = C.c_int64
@@ -265,6 +268,24 @@ def sample_rows(coords, cells, level: int, seed: int, sample_cell, sample_lat, d
     b = np.empty(ns, np.int8)
     r = lib().or_sample_rows(coords.shape[1], coords.shape[0], coords.ravel(), cells.shape[0], cells.ravel(),
                              level, int(dirichlet), seed, ns, sc, sl, y, b)
+    if r != 0:
+        raise ValueError(_err())
+    return y, b.astype(bool)
+
+
+def sample_rows_blended(coords, cells, level: int, seed: int, bubble, sample_cell, sample_lat, dirichlet: bool = True):
+    """Rows of the blended 2D operator (csr_blended) at sampled (cell, lattice
+    point) pairs for x = keyed random(seed), with no global build."""
+    coords = np.ascontiguousarray(coords, dtype=np.float64)
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    bub = np.ascontiguousarray(bubble, dtype=np.float64).reshape(-1)
+    sc = np.ascontiguousarray(sample_cell, dtype=np.int64)
+    sl = np.ascontiguousarray(sample_lat, dtype=np.int64).ravel()
+    ns = sc.shape[0]
+    y = np.empty(ns)
+    b = np.empty(ns, np.int8)
+    r = lib().or_sample_rows_blended(coords.shape[0], coords.ravel(), cells.shape[0], cells.ravel(), level,
+                                     int(dirichlet), seed, bub, ns, sc, sl, y, b)
     if r != 0:
         raise ValueError(_err())
     return y, b.astype(bool)

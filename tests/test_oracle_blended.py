@@ -90,3 +90,88 @@ def test_zero_bubble_is_affine_and_dirichlet_rows(name):
     np.testing.assert_array_equal(Ad[~bnd], An[~bnd])
     # a real bubble changes the interior rows
     assert np.abs(An - A1).max() > 1e-3 * np.abs(A1).max()
+
+
+def _exact_row(co, ce, c, d, N, p, xval):
+    """Row p of the blended operator in exact rational arithmetic: the six
+    micro-triangles of macro c around the interior lattice point p, each with
+    the textbook P1 matrix K_ij = (E_i . E_j) / (4 |T|), E_i the edge opposite
+    vertex i, on exactly mapped points F(i, j) = P0 + (P1 - P0) i/N +
+    (P2 - P0) j/N + (N - i - j) i j / N^3 d."""
+    from fractions import Fraction as Fr
+    P = [[Fr(float(v)) for v in co[k]] for k in ce[c]]
+    dd = [Fr(float(v)) for v in d[c]]
+
+    def F(q):
+        i, j = q
+        bub = Fr((N - i - j) * i * j, N ** 3)
+        return [P[0][r] + (P[1][r] - P[0][r]) * Fr(i, N) + (P[2][r] - P[0][r]) * Fr(j, N) + bub * dd[r]
+                for r in range(2)]
+
+    i, j = p
+    tris = [((i, j), (i + 1, j), (i, j + 1)), ((i - 1, j), (i, j), (i - 1, j + 1)), ((i, j - 1), (i + 1, j - 1), (i, j)),
+            ((i, j), (i, j + 1), (i - 1, j + 1)), ((i, j - 1), (i, j), (i - 1, j)), ((i + 1, j - 1), (i + 1, j), (i, j))]
+    acc = Fr(0)
+    for t in tris:
+        X = [F(q) for q in t]
+        E = [[X[2][r] - X[1][r] for r in range(2)], [X[0][r] - X[2][r] for r in range(2)],
+             [X[1][r] - X[0][r] for r in range(2)]]
+        area2 = abs(E[2][0] * (-E[1][1]) - E[2][1] * (-E[1][0]))  # |det [X1-X0, X2-X0]|
+        me = t.index(p)
+        for k in range(3):
+            acc += (E[me][0] * E[k][0] + E[me][1] * E[k][1]) / (2 * area2) * xval[t[k]]
+    return acc
+
+
+def test_sampled_rows_match_exact_rational_rows_at_level_14():
+    """At level 14 the mapped points are O(1) apart from the origin but 1/N
+    apart from each other; the oracle's rows must still agree with rows
+    computed in exact rational arithmetic to about the rounding of the
+    element matrices (1e-13 of the row's absolute sum)."""
+    from fractions import Fraction as Fr
+
+    from oracle.oracle import keyed_points, sample_rows_blended
+    co, ce = W.affine_triangle(2)
+    L = 14
+    N = 1 << L
+    d = np.array([[0.45, -0.3]])
+    rng = np.random.default_rng(5)
+    pts = []
+    while len(pts) < 12:
+        i, j = int(rng.integers(1, N)), int(rng.integers(1, N))
+        if i + j <= N - 1:
+            pts.append((i, j))
+    pts += [(1, 1), (N - 2, 1), (1, N - 2), (N // 3, N // 3)]
+    y, bnd = sample_rows_blended(co, ce, L, 11, d, np.zeros(len(pts), np.int64), np.array(pts))
+    assert not bnd.any()
+    for p, yo in zip(pts, y):
+        nb = [(p[0] + a, p[1] + b) for a, b in ((0, 0), (1, 0), (-1, 0), (0, 1), (0, -1), (1, -1), (-1, 1))]
+        xv = keyed_points(ce, 2, L, 11, np.zeros(len(nb), np.int64), np.array(nb))
+        xval = {q: Fr(float(v)) for q, v in zip(nb, xv)}
+        ex = _exact_row(co, ce, 0, d, N, p, xval)
+        scale = float(sum(abs(v) for v in xval.values()))
+        assert abs(yo - float(ex)) <= 1e-13 * scale, (p, yo, float(ex))
+
+
+@pytest.mark.parametrize("name", sorted(MESHES))
+def test_row_evaluator_matches_assembled_rows(name):
+    """The sampled-row evaluator (no global build) against the assembled CSR
+    of the same blended operator, every point of a small level."""
+    import harness
+    from oracle.oracle import sample_rows_blended
+    co, ce = MESHES[name]()
+    L = 3
+    d = _bubbles(len(ce), 4)
+    om = OracleMesh(co, ce, L)
+    yo = om.csr_blended(d) @ om.keyed_random(9)
+    N = om.N
+    pts = np.array([(c, i, j) for c in range(len(ce)) for j in range(N + 1) for i in range(N + 1 - j)], np.int64)
+    ys, _ = sample_rows_blended(co, ce, L, 9, d, pts[:, 0], pts[:, 1:])
+    # map (cell, lattice point) to unique DoFs through the exact keys
+    vid, wt = om.keys()
+    key_of = {tuple(sorted((int(v), int(w)) for v, w in zip(vv, ww) if v >= 0 and w > 0)): u
+              for u, (vv, ww) in enumerate(zip(vid, wt))}
+    for (c, i, j), val in zip(pts, ys):
+        cv = ce[c]
+        k = tuple(sorted((int(v), int(w)) for v, w in zip(cv, (N - i - j, i, j)) if w > 0))
+        assert abs(val - yo[key_of[k]]) <= 1e-13 * max(1.0, np.abs(yo).max())
