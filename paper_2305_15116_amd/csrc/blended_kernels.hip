@@ -4,7 +4,7 @@
 // xi = lattice point / N, xi0 = 1 - xi1 - xi2 (a cubic bubble that vanishes
 // on the macro's edges, so neighbouring macros agree on shared points).  No
 // two rows share a stencil, so every element matrix is formed on the fly from
-// the mapped coordinates: the paper's remark that varying weights can be
+// the edge vectors between mapped lattice points: the paper's remark that varying weights can be
 // computed on the fly at an arithmetic cost, here taken to the point where
 // the arithmetic (about 85 vector instructions per DoF, most of them FP64)
 // outweighs the 16 B/DoF of memory traffic.
@@ -61,18 +61,18 @@ __device__ __forceinline__ double half_inv_abs(double d) {
 
 // What one band leaves for the rows above it.
 struct Band {
-  V2 c, r, h;     // mapped points (x, b+1), (x+1, b+1) and their difference
+  V2 h;           // edge vector (x, b+1) -> (x+1, b+1)
   double u_cr;    // U's -K on the horizontal edge (x,b)-(x+1,b)
   double wv, wd;  // weights of the edges (x,b)-(x,b+1) and (x+1,b)-(x,b+1)
   double d_top;   // D's -K on the horizontal edge (x,b+1)-(x+1,b+1)
 };
 
-// Band b from the points of row b (c, r = right neighbour, h = r - c) and
-// c1 = F(x, b+1).  in_u / in_d: whether U(x,b) / D(x,b) lie in the macro.
-__device__ __forceinline__ Band make_band(V2 c, V2 r, V2 h, V2 c1, bool in_u, bool in_d) {
+// Band b from three edge vectors at the lane's point C = (x, b): h = C -> R,
+// v = C -> C1 and h1 = C1 -> R1; R -> R1 is the right lane's v and R -> C1 is
+// v - h.  in_u / in_d: whether U(x,b) / D(x,b) lie in the macro.
+__device__ __forceinline__ Band make_band(V2 h, V2 v, V2 h1, bool in_u, bool in_d) {
   Band B;
-  const V2 r1 = dn1v(c1);
-  const V2 h1 = r1 - c1, v = c1 - c, g = c1 - r, f = r1 - r;
+  const V2 g = v - h, f = dn1v(v);
   // one reciprocal for both triangles: 1 / (2 |det U| |det D|); a triangle
   // outside the macro enters as 1, so a degenerate one cannot spoil the other
   const double tu = in_u ? fabs(cross(h, v)) : 1.0, td = in_d ? fabs(cross(f, g)) : 1.0;
@@ -86,8 +86,6 @@ __device__ __forceinline__ Band make_band(V2 c, V2 r, V2 h, V2 c1, bool in_u, bo
   B.wv = (in_u ? u_cc1 : 0.0) + up1(d_rr1m);
   B.wd = (in_u ? u_rc1 : 0.0) + (in_d ? d_rc1 : 0.0);
   B.d_top = in_d ? d_r1c1 : 0.0;
-  B.c = c1;
-  B.r = r1;
   B.h = h1;
   return B;
 }
@@ -107,22 +105,28 @@ __device__ __forceinline__ void bl_tile(int x0, int y0, const MacroDev& M, const
   const int y1 = min(y0 + kBlH, N - x0 + 1);  // output rows y0 .. y1-1
   X += M.base;
   Y += M.base;
+  // Edge vectors between neighbouring mapped lattice points, formed from
+  // lattice differences rather than as differences of O(1) mapped
+  // coordinates (which would cost about log10(N) digits): with bubble
+  // n(i, j) / N^3, n(i, j) = (N - i - j) i j, the differences
+  // n(x+1, r) - n(x, r) = r (N - r - 2x - 1) and n(x, r+1) - n(x, r) =
+  // x (N - x - 2r - 1) are exact integers, and the scalings by powers of two
+  // are exact, so each component takes one rounding.
   const double invN = 1.0 / (double)N;  // exact: N is a power of two
-  const double a = (double)x * invN;
-  const double ax = fma(G.e1[0], a, G.p0[0]), ay = fma(G.e1[1], a, G.p0[1]);
-  auto map = [&](int r) -> V2 {
-    const double b = (double)r * invN;
-    const double bub = (1.0 - a - b) * a * b;
-    return {fma(bub, bx, fma(G.e2[0], b, ax)), fma(bub, by, fma(G.e2[1], b, ay))};
+  const double invN3 = invN * invN * invN;
+  const double e1x = G.e1[0] * invN, e1y = G.e1[1] * invN, e2x = G.e2[0] * invN, e2y = G.e2[1] * invN;
+  auto hv = [&](int r) -> V2 {  // F(x+1, r) - F(x, r)
+    const double nb = (double)r * (double)(N - r - 2 * x - 1) * invN3;
+    return {fma(nb, bx, e1x), fma(nb, by, e1y)};
+  };
+  auto vv = [&](int r) -> V2 {  // F(x, r+1) - F(x, r)
+    const double nb = (double)x * (double)(N - x - 2 * r - 1) * invN3;
+    return {fma(nb, bx, e2x), fma(nb, by, e2y)};
   };
   // triangles U(x,b) and D(x,b) inside the macro (always, on interior tiles)
   auto in_u = [&](int b) { return INNER || (x >= 0 && b >= 0 && x + b <= N - 1); };
   auto in_d = [&](int b) { return INNER || (x >= 0 && b >= 0 && x + b <= N - 2); };
-  Band bm;  // band y0-1
-  {
-    const V2 c = map(y0 - 1), r = dn1v(c);
-    bm = make_band(c, r, r - c, map(y0), in_u(y0 - 1), in_d(y0 - 1));
-  }
+  Band bm = make_band(hv(y0 - 1), vv(y0 - 1), hv(y0), in_u(y0 - 1), in_d(y0 - 1));  // band y0-1
   double xm = ld_row(X, N, y0 - 1, y1, xc), x0v = ld_row(X, N, y0, y1, xc);
   double q[kBlU];
 #pragma unroll
@@ -134,7 +138,7 @@ __device__ __forceinline__ void bl_tile(int x0, int y0, const MacroDev& M, const
     const double xp = q[j % kBlU];
     q[j % kBlU] = ld_row(X, N, y0 + 1 + j + kBlU, y1, xc);
     if (!INNER && j >= nrows) break;  // interior tiles always have kBlH rows
-    const Band bp = make_band(bm.c, bm.r, bm.h, map(yy + 1), in_u(yy), in_d(yy));  // band y
+    const Band bp = make_band(bm.h, vv(yy), hv(yy + 1), in_u(yy), in_d(yy));  // band y
     const double wh = bp.u_cr + bm.d_top;                                          // edge (x,y)-(x+1,y)
     const double acc = ((wh * (x0v - dn1(x0v)) + up1(wh) * (x0v - up1(x0v))) +
                         (bp.wv * (x0v - xp) + bm.wv * (x0v - xm))) +
