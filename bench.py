@@ -238,7 +238,7 @@ def solve_bytes(P, m, L, mode, iters, lc=2):
             "per_solve": setup + iters * (cycle + outer)}
 
 
-def solve_bench(P, torch, W, L=8, repeats=10):
+def solve_bench(P, torch, W, L=8, repeats=10, modes=(0, 1, 2, 3)):
     co, ce = W.kuhn_cube()
     m = P.create_macro_mesh(co, ce, L)
     s, _ = P.mesh_num_dofs(m, L)
@@ -256,7 +256,7 @@ def solve_bench(P, torch, W, L=8, repeats=10):
     b = torch.as_tensor(h ** 3 * f, device="cuda")
     out = {}
     names = {0: "fp64", 1: "mixed", 2: "fp64_pcg", 3: "mixed_pcg"}
-    for mode in (0, 1, 2, 3):
+    for mode in modes:
         ws = torch.empty(P.mesh_workspace_bytes(m, L, mode), dtype=torch.uint8, device="cuda")
         x = torch.zeros(s, dtype=torch.float64, device="cuda")
         rc, it, rel, sec = P.vcycle_solve(m, L, b, x, ws, mode=mode, rtol=1e-10)
@@ -366,6 +366,8 @@ def main():
     ap.add_argument("--serve-n", type=int, default=None, help="requests of the serving run")
     ap.add_argument("--serve-servers", choices=["both", "plain", "batched"], default="both",
                     help="which servers the serving run measures")
+    ap.add_argument("--solve-only", type=int, choices=[0, 1, 2, 3], default=None,
+                    help="only run the cube level-8 solve of this mode three times (for kernel traces)")
     ap.add_argument("--cpu-cube", action="store_true",
                     help="also time the oracle on the 3D benchmark mesh (cube level 8, 100 products; assembly takes minutes)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -383,6 +385,9 @@ def main():
     torch.cuda.set_device(0)
     P.lib()
 
+    if args.solve_only is not None:
+        print(json.dumps({"solve_cube_l8": solve_bench(P, torch, W, repeats=3, modes=(args.solve_only,))}), flush=True)
+        return
     co, ce = W.affine_triangle(2)
     L = 14
     log(f"apply 2D level {L} fp64: {args.warmup} warmup + {args.steps} timed")
