@@ -760,9 +760,16 @@ int or_lumped_mass(const or_mesh* m, double* mass) {
 // needs no global build, so it runs at any level.  Sample s is the point
 // sample_lat[s*dim ..] of cell sample_cell[s].  Returns 0, or -1 on bad input.
 namespace {
+// kcoef: evaluate the variable-coefficient operator of or_assemble_varcoef
+// with nodal coefficient k = keyed value(kseed) + kshift.
+struct KCoef {
+  bool on;
+  uint64_t seed;
+  double shift;
+};
 int sample_rows_impl(int dim, int64_t nv, const double* coords, int64_t nc, const int64_t* cells, int level,
                      int dirichlet, uint64_t seed, int64_t ns, const int64_t* sample_cell, const int64_t* sample_lat,
-                     const double* bubble, double* y, int8_t* is_boundary) {
+                     const double* bubble, KCoef kcoef, double* y, int8_t* is_boundary) {
   if (dim != 2 && dim != 3) { g_err = "dim must be 2 or 3"; return -1; }
   Topology topo = build_topology(dim, nc, cells);
   if (!topo.ok) return -1;
@@ -808,15 +815,20 @@ int sample_rows_impl(int dim, int64_t nv, const double* coords, int64_t nc, cons
         if (me < 0) return;
         double E[3][3], K[MAXV][MAXV], vol;
         double xv[MAXV];
+        double kt = 0.0;
         for (int i = 0; i < d1; ++i) {
           int64_t wi[MAXV];
           weights_of(dim, N, v[i], wi);
-          xv[i] = keyed_value(seed, make_key(dim, cv2, wi));
+          const Key ki = make_key(dim, cv2, wi);
+          xv[i] = keyed_value(seed, ki);
+          if (kcoef.on) kt += keyed_value(kcoef.seed, ki) + kcoef.shift;
         }
         if (bubble) blended_edge_matrix(coords, cv2, N, &bubble[c2 * 2], v, E);
         else edge_matrix(dim, coords, cv2, N, v, E);
         element_stiffness(dim, E, K, &vol);
-        for (int j = 0; j < d1; ++j) acc += K[me][j] * xv[j];
+        double r = 0.0;
+        for (int j = 0; j < d1; ++j) r += K[me][j] * xv[j];
+        acc += kcoef.on ? (kt / (double)d1) * r : r;
       });
     }
     y[s] = acc;
@@ -828,8 +840,17 @@ int sample_rows_impl(int dim, int64_t nv, const double* coords, int64_t nc, cons
 int or_sample_rows(int dim, int64_t nv, const double* coords, int64_t nc, const int64_t* cells, int level,
                    int dirichlet, uint64_t seed, int64_t ns, const int64_t* sample_cell,
                    const int64_t* sample_lat, double* y, int8_t* is_boundary) {
-  return sample_rows_impl(dim, nv, coords, nc, cells, level, dirichlet, seed, ns, sample_cell, sample_lat, nullptr, y,
-                          is_boundary);
+  return sample_rows_impl(dim, nv, coords, nc, cells, level, dirichlet, seed, ns, sample_cell, sample_lat, nullptr,
+                          KCoef{false, 0, 0.0}, y, is_boundary);
+}
+
+// The same rows for the variable-coefficient operator of or_assemble_varcoef
+// with k = keyed value(kseed) + kshift at every DoF.
+int or_sample_rows_varcoef(int dim, int64_t nv, const double* coords, int64_t nc, const int64_t* cells, int level,
+                           int dirichlet, uint64_t seed, uint64_t kseed, double kshift, int64_t ns,
+                           const int64_t* sample_cell, const int64_t* sample_lat, double* y, int8_t* is_boundary) {
+  return sample_rows_impl(dim, nv, coords, nc, cells, level, dirichlet, seed, ns, sample_cell, sample_lat, nullptr,
+                          KCoef{true, kseed, kshift}, y, is_boundary);
 }
 
 // The same rows for the blended 2D operator of or_assemble_blended (bubble:
@@ -837,8 +858,8 @@ int or_sample_rows(int dim, int64_t nv, const double* coords, int64_t nc, const 
 int or_sample_rows_blended(int64_t nv, const double* coords, int64_t nc, const int64_t* cells, int level,
                            int dirichlet, uint64_t seed, const double* bubble, int64_t ns,
                            const int64_t* sample_cell, const int64_t* sample_lat, double* y, int8_t* is_boundary) {
-  return sample_rows_impl(2, nv, coords, nc, cells, level, dirichlet, seed, ns, sample_cell, sample_lat, bubble, y,
-                          is_boundary);
+  return sample_rows_impl(2, nv, coords, nc, cells, level, dirichlet, seed, ns, sample_cell, sample_lat, bubble,
+                          KCoef{false, 0, 0.0}, y, is_boundary);
 }
 
 // Keyed input values x(key) at (cell, lattice point) pairs, without a global build.

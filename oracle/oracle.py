@@ -64,6 +64,9 @@ def lib():
         L.or_sample_rows_blended.restype = C.c_int
         L.or_sample_rows_blended.argtypes = [C.c_int64, f64p, C.c_int64, i64p, C.c_int, C.c_int, C.c_uint64, f64p,
                                              C.c_int64, i64p, i64p, f64p, i8p]
+        L.or_sample_rows_varcoef.restype = C.c_int
+        L.or_sample_rows_varcoef.argtypes = [C.c_int, C.c_int64, f64p, C.c_int64, i64p, C.c_int, C.c_int, C.c_uint64,
+                                             C.c_uint64, C.c_double, C.c_int64, i64p, i64p, f64p, i8p]
         L.or_keyed_points.restype = C.c_int
         L.or_keyed_points.argtypes = [C.c_int, C.c_int64, i64p, C.c_int, C.c_uint64, C.c_int64, i64p, i64p, f64p]
         L.or_prolongation.restype = C.c_int64
@@ -286,6 +289,25 @@ def sample_rows_blended(coords, cells, level: int, seed: int, bubble, sample_cel
     b = np.empty(ns, np.int8)
     r = lib().or_sample_rows_blended(coords.shape[0], coords.ravel(), cells.shape[0], cells.ravel(), level,
                                      int(dirichlet), seed, bub, ns, sc, sl, y, b)
+    if r != 0:
+        raise ValueError(_err())
+    return y, b.astype(bool)
+
+
+def sample_rows_varcoef(coords, cells, level: int, seed: int, kseed: int, kshift: float, sample_cell, sample_lat,
+                        dirichlet: bool = True):
+    """Rows of the variable-coefficient operator (csr_varcoef with k = keyed
+    random(kseed) + kshift) at sampled (cell, lattice point) pairs for
+    x = keyed random(seed), with no global build."""
+    coords = np.ascontiguousarray(coords, dtype=np.float64)
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    sc = np.ascontiguousarray(sample_cell, dtype=np.int64)
+    sl = np.ascontiguousarray(sample_lat, dtype=np.int64).ravel()
+    ns = sc.shape[0]
+    y = np.empty(ns)
+    b = np.empty(ns, np.int8)
+    r = lib().or_sample_rows_varcoef(coords.shape[1], coords.shape[0], coords.ravel(), cells.shape[0], cells.ravel(),
+                                     level, int(dirichlet), seed, kseed, float(kshift), ns, sc, sl, y, b)
     if r != 0:
         raise ValueError(_err())
     return y, b.astype(bool)

@@ -81,3 +81,35 @@ def test_constant_and_linear_in_k(name):
     bnd = om.boundary()
     np.testing.assert_array_equal(Ad[bnd], np.eye(om.n)[bnd])
     np.testing.assert_array_equal(Ad[~bnd], Ak.toarray()[~bnd])
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_row_evaluator_matches_assembled_varcoef_rows(dim):
+    """The sampled-row evaluator (no global build) against the assembled
+    variable-coefficient CSR, every point of a small level."""
+    from oracle.oracle import sample_rows_varcoef
+    if dim == 2:
+        co, ce = W.strip_2d(3)
+    else:
+        co, ce = W.kuhn_cube("random", 5)
+    J, t = W.random_affine(dim, 6)
+    co = W.apply_affine(co, J, t)
+    L = 2
+    om = OracleMesh(co, ce, L)
+    k = om.keyed_random(8) + 1.5
+    yo = om.csr_varcoef(k) @ om.keyed_random(9)
+    N = om.N
+    if dim == 2:
+        lat = [(i, j) for j in range(N + 1) for i in range(N + 1 - j)]
+    else:
+        lat = [(i, j, z) for z in range(N + 1) for j in range(N + 1 - z) for i in range(N + 1 - j - z)]
+    pts = np.array([(c, *p) for c in range(len(ce)) for p in lat], np.int64)
+    ys, _ = sample_rows_varcoef(co, ce, L, 9, 8, 1.5, pts[:, 0], pts[:, 1:])
+    vid, wt = om.keys()
+    key_of = {tuple(sorted((int(v), int(w)) for v, w in zip(vv, ww) if v >= 0 and w > 0)): u
+              for u, (vv, ww) in enumerate(zip(vid, wt))}
+    for row, val in zip(pts, ys):
+        c, p = row[0], row[1:]
+        bary = (N - int(sum(p)), *[int(q) for q in p])
+        key = tuple(sorted((int(v), w) for v, w in zip(ce[c], bary) if w > 0))
+        assert abs(val - yo[key_of[key]]) <= 1e-13 * max(1.0, np.abs(yo).max())
