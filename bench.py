@@ -444,6 +444,15 @@ def main():
                 "GDoF_s": rv["unique"] / (rv["launch_avg_ms"] * 1e-3) / 1e9,
                 "GB_s": bpd * rv["unique"] / (rv["launch_avg_ms"] * 1e-3) / 1e9,
                 "launch_avg_ms": rv["launch_avg_ms"], "dofs": rv["unique"], "algorithmic_B_per_dof": bpd}
+        for dt, bpd in ((torch.float64, 24), (torch.float32, 12)):
+            tag = "fp64" if dt == torch.float64 else "fp32"
+            log(f"variable-coefficient apply 3D cube level 8 {tag} (weights formed on the fly)")
+            rv = bench_varcoef(P, torch, *W.kuhn_cube(), 8, dt, args.steps, args.warmup)
+            extra[f"apply3d_varcoef_cube_l8_{tag}"] = {
+                "GDoF_s": rv["unique"] / (rv["launch_avg_ms"] * 1e-3) / 1e9,
+                "GB_s_storage": bpd * rv["storage"] / (rv["launch_avg_ms"] * 1e-3) / 1e9,
+                "launch_avg_ms": rv["launch_avg_ms"], "storage": rv["storage"], "unique": rv["unique"],
+                "algorithmic_B_per_dof": bpd}
         log("blended (non-affine) apply 2D level 14 fp64 (element matrices formed on the fly)")
         rb = bench_blended(P, torch, co, ce, 14, args.steps, args.warmup)
         extra["apply2d_blended_l14_fp64"] = {

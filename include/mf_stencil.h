@@ -128,14 +128,14 @@ int mesh_set_dirichlet(const mf_mesh* mesh, int level, int dtype, const void* b_
  * overwritten and must not alias x.  Asynchronous. */
 int apply_stencil(const mf_mesh* mesh, int level, int dtype, const void* x_dev, void* y_dev, void* stream);
 
-/* y = A(k) x for -div(k grad u) on a 2D mesh (P1), with k the P1
- * interpolant of the nodal coefficient k_dev (storage layout of `level`,
- * same dtype as x; copies equal).  Each micro-triangle's element matrix is
- * the mean of k over its vertices times the constant-coefficient one, formed
- * on the fly (no stored matrix: the paper's remark that varying stencil
- * weights can be computed on the fly, comparison of matrix-free and sparse
- * storage).  Dirichlet rows give y = x.  y is overwritten and must not alias
- * x or k.  MF_ENOTSUP for a 3D mesh.  Asynchronous. */
+/* y = A(k) x for -div(k grad u) (P1), with k the P1 interpolant of the
+ * nodal coefficient k_dev (storage layout of `level`, same dtype as x;
+ * copies equal).  Each micro-triangle's (2D) or micro-tet's (3D) element
+ * matrix is the mean of k over its vertices times the constant-coefficient
+ * one, formed on the fly (no stored matrix: the paper's remark that varying
+ * stencil weights can be computed on the fly, comparison of matrix-free and
+ * sparse storage).  Dirichlet rows give y = x.  y is overwritten and must not
+ * alias x or k.  Asynchronous. */
 int apply_varcoef(const mf_mesh* mesh, int level, int dtype, const void* k_dev, const void* x_dev, void* y_dev,
                   void* stream);
 

@@ -202,7 +202,7 @@ def apply_stencil(mesh: Mesh, level: int, x, y, stream=None):
 
 
 def apply_varcoef(mesh: Mesh, level: int, k, x, y, stream=None):
-    """y = A(k) x for -div(k grad u) (2D P1, k nodal, same layout and dtype as x)."""
+    """y = A(k) x for -div(k grad u) (P1, 2D or 3D; k nodal, same layout and dtype as x)."""
     if k.dtype != x.dtype:
         raise MFError(MF_EINVAL, "k and x must have the same dtype")
     _check(lib().apply_varcoef(mesh, level, _dtype_code(x), C.c_void_p(k.data_ptr()), C.c_void_p(x.data_ptr()),

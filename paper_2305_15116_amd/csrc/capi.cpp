@@ -275,7 +275,6 @@ int apply_varcoef(const mf_mesh* m, int level, int dtype, const void* k, const v
   int rc = check_mesh(m, level, true);
   if (!rc) rc = check_dtype(dtype);
   if (rc) return rc;
-  if (m->dim != 2) return set_error(MF_ENOTSUP, "the variable-coefficient apply is built for 2D meshes");
   if (!k || !x || !y) return set_error(MF_EINVAL, "NULL vector");
   if (x == y || k == y) return set_error(MF_EINVAL, "y must not alias x or k");
   return launch_varcoef_apply(m, m->levels[level], dtype, k, x, y, (hipStream_t)stream);

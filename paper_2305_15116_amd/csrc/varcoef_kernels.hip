@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include "launch.hpp"
+#include "rows.hpp"
 #include "wave.hpp"
 
 namespace mf {
@@ -171,11 +172,128 @@ int run_varcoef(const Level& L, const void* k, const void* x, void* y, hipStream
   return launch_exchange_apply(L, dtype_of<T>(), y, s);
 }
 
+
+// ---------------------------------------------------------------- 3D
+// Tetrahedral macros: a point's row sums over the micro-tets of its macro
+// that contain it (24 for an interior point: each of the 6 element types
+// with the point at each of its 4 vertices), each tet contributing
+// mean_T(k) times its row of the constant-coefficient element matrix.  Every
+// vertex of such a tet is the point itself or one of its 15 stencil
+// neighbours, so one lane loads k and x at those 15 points (gathers within a
+// few rows of 3 slices, served by L1/L2) and forms all contributions in
+// registers.  One wave takes a 64-point slice segment (consecutive storage
+// points of one slice, across row ends), so short rows leave no lane idle.
+
+// Index into the 15 stencil offsets of lattice offset d (-1 if none).
+__host__ __device__ constexpr int stencil_slot(int dx, int dy, int dz) {
+  constexpr StencilTable ST = stencil_table(3);
+  for (int o = 0; o < ST.n; ++o)
+    if (ST.off[o][0] == dx && ST.off[o][1] == dy && ST.off[o][2] == dz) return o;
+  return -1;
+}
+
+// Stencil slot of vertex u of a type-t tet whose vertex v is the point.
+__host__ __device__ constexpr int tet_slot(int t, int v, int u) {
+  constexpr ElemTable E = elem_table(3);
+  return stencil_slot(E.off[t][u][0] - E.off[t][v][0], E.off[t][u][1] - E.off[t][v][1],
+                      E.off[t][u][2] - E.off[t][v][2]);
+}
+
+__host__ __device__ constexpr bool tet_slots_valid() {
+  for (int t = 0; t < 6; ++t)
+    for (int v = 0; v < 4; ++v)
+      for (int u = 0; u < 4; ++u)
+        if (tet_slot(t, v, u) < 0) return false;
+  return true;
+}
+static_assert(tet_slots_valid(), "every edge of a micro-tet is a stencil offset");
+
+template <typename T>
+__device__ __forceinline__ void vc3_point(const MacroDev& M, const T* __restrict__ K, const T* __restrict__ X,
+                                          T* __restrict__ Y, int x, int y, int z) {
+  constexpr StencilTable ST = stencil_table(3);
+  constexpr ElemTable E = elem_table(3);
+  const int N = M.N;
+  const int S = N - z;
+  // slice bases of z - 1, z, z + 1 (clamped into the macro; only read for
+  // neighbours inside it)
+  const int64_t bz = slice_base(N, z);
+  const int64_t bm = z > 0 ? slice_base(N, z - 1) : bz;
+  const int64_t bp = z < N ? slice_base(N, z + 1) : bz;
+  const int64_t ic = M.base + bz + row_start(S, y) + x;
+  T kv[ST.n], xv[ST.n];
+#pragma unroll
+  for (int o = 0; o < ST.n; ++o) {
+    const int nx = x + ST.off[o][0], ny = y + ST.off[o][1], nz = z + ST.off[o][2];
+    const bool in = nx >= 0 && ny >= 0 && nz >= 0 && nx + ny + nz <= N;
+    const int dz = ST.off[o][2];
+    const int64_t sb = dz < 0 ? bm : (dz > 0 ? bp : bz);
+    const int Sn = S - dz;
+    // neighbours outside the macro read the point itself; no tet uses them
+    const int64_t i = in ? M.base + sb + row_start(Sn, ny) + nx : ic;
+    kv[o] = K[i];
+    xv[o] = X[i];
+  }
+  const int mask = support_mask(3, N, x, y, z);
+  if (mask != full_mask(3) && ((M.dir_mask >> mask) & 1)) {
+    Y[ic] = xv[ST.centre];  // identity row
+    return;
+  }
+  T acc = T(0);
+#pragma unroll
+  for (int t = 0; t < E.ntypes; ++t) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int ax = x - E.off[t][v][0], ay = y - E.off[t][v][1], az = z - E.off[t][v][2];
+      const bool exists = ax >= 0 && ay >= 0 && az >= 0 && ax + ay + az <= N - E.slack[t];
+      const int s0 = tet_slot(t, v, 0), s1 = tet_slot(t, v, 1), s2 = tet_slot(t, v, 2), s3 = tet_slot(t, v, 3);
+      const T km = (kv[s0] + kv[s1] + kv[s2] + kv[s3]) * T(0.25);
+      const double* Kt = M.K[t] + 4 * v;
+      T r = T(Kt[0]) * xv[s0];
+      r = fma(T(Kt[1]), xv[s1], r);
+      r = fma(T(Kt[2]), xv[s2], r);
+      r = fma(T(Kt[3]), xv[s3], r);
+      acc = exists ? fma(km, r, acc) : acc;
+    }
+  }
+  // interior, unshared and shared points alike store their (partial) row;
+  // the exchange kernel completes shared DoFs
+  Y[ic] = acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWG) void varcoef3d_kernel(const Tile* __restrict__ segs, int nwg, const MacroDev* md,
+                                                        const T* __restrict__ K, const T* __restrict__ X,
+                                                        T* __restrict__ Y) {
+  const int g = wave::xcd_wg(nwg);
+  if (g < 0) return;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const Tile sg = load_seg(segs, g * kWavesPerWG + wv);
+  if (sg.macro < 0) return;
+  const MacroDev& M = md[sg.macro];
+  int x, y, z;
+  slice_point<3>(sg, M.N, x, y, z);
+  if (x + y + z > M.N) return;  // lanes past the slice's last point
+  vc3_point<T>(M, K, X, Y, x, y, z);
+}
+
+template <typename T>
+int run_varcoef3d(const Level& L, const void* k, const void* x, void* y, hipStream_t s) {
+  const int nwg = (int)(L.psegs.size() / kWavesPerWG);
+  if (nwg > 0)
+    hipLaunchKernelGGL(varcoef3d_kernel<T>, dim3(wave::xcd_grid(nwg)), dim3(kWG), 0, s, L.dev.psegs, nwg, L.dev.md,
+                       (const T*)k, (const T*)x, (T*)y);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(MF_EDEVICE, hipGetErrorString(e));
+  return launch_exchange_apply(L, dtype_of<T>(), y, s);
+}
+
 }  // namespace
 
 int launch_varcoef_apply(const mf_mesh* m, const Level& L, int dtype, const void* k, const void* x, void* y,
                          hipStream_t s) {
-  (void)m;
+  if (m->dim == 3)
+    return dtype == MF_F64 ? run_varcoef3d<double>(L, k, x, y, s) : run_varcoef3d<float>(L, k, x, y, s);
   return dtype == MF_F64 ? run_varcoef<double>(L, k, x, y, s) : run_varcoef<float>(L, k, x, y, s);
 }
 
