@@ -1,17 +1,19 @@
 """Parity of the 3D kernels that the cube benchmarks run, against the oracle.
 
-From N = 128 (level 7) on, 3D stencil launches use pencils of 8 slices
+From N = 256 (level 8) on, 3D stencil launches use pencils of 8 slices
 instead of 4, a separate kernel instance with its own slice ring and
-right-hand-side double buffer.  These tests run that instance at level 7 on
-the 6-tet unit cube in both vertex orders (the canonical Kuhn order and a
-seeded random order per tet) and compare every storage DoF with the oracle's
-CSR (2,146,689 unique DoFs): the apply, three Jacobi sweeps and the residual
-with its norm, in FP64 (1e-12 relative, max norm) and FP32 (the rounding
-bound of the parity tests).  The CG solver's fused apply + dot mode is
+right-hand-side double buffer.  These tests compare every storage DoF with
+the oracle's CSR: the apply, three Jacobi sweeps and the residual with its
+norm, in FP64 (1e-12 relative, max norm) and FP32 (the rounding bound of the
+parity tests), on the 6-tet unit cube at level 7 in both vertex orders (the
+canonical Kuhn order and a seeded random order per tet; 2,146,689 unique
+DoFs, pencils of 4 slices) and on two face-sharing tets with shuffled vertex
+orders at level 8 (5,691,265 unique DoFs, pencils of 8 slices, the shared
+face completed by the exchange).  The CG solver's fused apply + dot mode is
 checked through solves whose residual the oracle recomputes, the batched
-launches through a level-7 member that must equal its solve alone, and the
-mixed-precision solve of the benchmark (cube level 8) against the closed-form
-discrete solution.
+launches through members that must equal their solve alone, and the
+mixed-precision solve of the benchmark (cube level 8) against the
+closed-form discrete solution.
 """
 import numpy as np
 import pytest
@@ -37,34 +39,44 @@ def _device():
 
 
 _CACHE = {}
+L8 = 8
+MESHES = ["canonical", "random", "strip2"]
 
 
 def _cube(order):
-    """Mesh, oracle mesh, storage -> unique map and the Dirichlet CSR at level 7."""
+    """Mesh, oracle mesh, storage -> unique map, the Dirichlet CSR and the
+    level: the cube at level 7 (canonical or random vertex order), or two
+    face-sharing tets with shuffled vertex orders at level 8 ("strip2")."""
     if order not in _CACHE:
-        co, ce = W.kuhn_cube() if order == "canonical" else W.kuhn_cube("random", 5)
-        m = P.create_macro_mesh(co, ce, L7)
-        om = OracleMesh(co, ce, L7)
-        s2u = harness.storage_to_unique(P.mesh_dof_keys(m, L7), om.keys())
-        _CACHE[order] = (co, ce, m, om, s2u, om.csr(dirichlet=True))
+        if order == "strip2":
+            co, ce = W.strip_3d(2)
+            ce = W.shuffle_cell_orders(ce, 7)
+            L = L8
+        else:
+            co, ce = W.kuhn_cube() if order == "canonical" else W.kuhn_cube("random", 5)
+            L = L7
+        m = P.create_macro_mesh(co, ce, L)
+        om = OracleMesh(co, ce, L)
+        s2u = harness.storage_to_unique(P.mesh_dof_keys(m, L), om.keys())
+        _CACHE[order] = (co, ce, m, om, s2u, om.csr(dirichlet=True), L)
     return _CACHE[order]
 
 
-def _rand(m, seed, dtype):
-    s, _ = P.mesh_num_dofs(m, L7)
+def _rand(m, seed, dtype, L=L7):
+    s, _ = P.mesh_num_dofs(m, L)
     x = torch.empty(s, dtype=dtype, device="cuda")
-    P.mesh_fill_random(m, L7, seed, x)
+    P.mesh_fill_random(m, L, seed, x)
     return x
 
 
-@pytest.mark.parametrize("order", ["canonical", "random"])
+@pytest.mark.parametrize("order", MESHES)
 def test_apply_level7_every_dof(order):
-    co, ce, m, om, s2u, A = _cube(order)
-    assert om.N == 128 and om.n == 129 ** 3
+    co, ce, m, om, s2u, A, L = _cube(order)
+    assert (om.N, om.n) == ((128, 129 ** 3) if L == L7 else (256, 5691265))
     for dtype in (torch.float64, torch.float32):
-        x = _rand(m, 71, dtype)
+        x = _rand(m, 71, dtype, L)
         y = torch.full_like(x, float("nan"))
-        P.apply_stencil(m, L7, x, y)
+        P.apply_stencil(m, L, x, y)
         torch.cuda.synchronize()
         xo = om.keyed_random(71)
         ys = y.cpu().numpy()
@@ -79,17 +91,17 @@ def test_apply_level7_every_dof(order):
             assert (np.abs(ys.astype(np.float64) - (A @ x32)[s2u]) <= bound[s2u] + 1e-30).all()
 
 
-@pytest.mark.parametrize("order", ["canonical", "random"])
+@pytest.mark.parametrize("order", MESHES)
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_smooth_and_residual_level7_every_dof(order, dtype):
-    co, ce, m, om, s2u, A = _cube(order)
-    x = _rand(m, 72, dtype)
-    b = _rand(m, 73, dtype)
+    co, ce, m, om, s2u, A, L = _cube(order)
+    x = _rand(m, 72, dtype, L)
+    b = _rand(m, 73, dtype, L)
     tmp = torch.empty_like(x)
     r = torch.empty_like(x)
     omega = 2.0 / 3.0
-    nrm = P.residual(m, L7, b, x, r, norm=True)
-    P.smooth(m, L7, omega, 3, b, x, tmp)
+    nrm = P.residual(m, L, b, x, r, norm=True)
+    P.smooth(m, L, omega, 3, b, x, tmp)
     torch.cuda.synchronize()
     xo, bo = om.keyed_random(72), om.keyed_random(73)
     if dtype == torch.float32:
@@ -115,24 +127,24 @@ def test_smooth_and_residual_level7_every_dof(order, dtype):
     assert harness.rel_err_max(out.astype(np.float64), xs[s2u]) <= (1e-12 if dtype == torch.float64 else 2e-5)
 
 
-def _rhs(m, om, s2u, seed):
+def _rhs(m, om, s2u, seed, L=L7):
     """Keyed b with Dirichlet entries zeroed, on the device and for the oracle."""
-    b = _rand(m, seed, torch.float64)
-    P.mesh_set_dirichlet(m, L7, None, b)
+    b = _rand(m, seed, torch.float64, L)
+    P.mesh_set_dirichlet(m, L, None, b)
     bo = om.keyed_random(seed)
     bo[om.boundary()] = 0.0
     return b, bo
 
 
-@pytest.mark.parametrize("order,mode", [("canonical", 2), ("random", 3)])
+@pytest.mark.parametrize("order,mode", [("canonical", 2), ("random", 3), ("strip2", 2), ("strip2", 3)])
 def test_cg_level7_residual_by_oracle(order, mode):
     """CG's search-direction product runs the fused apply + dot instance; a
     wrong row or dot would leave the oracle's residual above the tolerance."""
-    co, ce, m, om, s2u, A = _cube(order)
-    b, bo = _rhs(m, om, s2u, 74)
+    co, ce, m, om, s2u, A, L = _cube(order)
+    b, bo = _rhs(m, om, s2u, 74, L)
     x = torch.zeros_like(b)
-    ws = torch.empty(P.mesh_workspace_bytes(m, L7, mode), dtype=torch.uint8, device="cuda")
-    rc, it, rel, _ = P.vcycle_solve(m, L7, b, x, ws, mode=mode, rtol=1e-10, max_iter=100)
+    ws = torch.empty(P.mesh_workspace_bytes(m, L, mode), dtype=torch.uint8, device="cuda")
+    rc, it, rel, _ = P.vcycle_solve(m, L, b, x, ws, mode=mode, rtol=1e-10, max_iter=100)
     torch.cuda.synchronize()
     assert rc == P.MF_OK and rel <= 1e-10, (rc, it, rel)
     xs = x.cpu().numpy()
@@ -146,12 +158,14 @@ def test_cg_level7_residual_by_oracle(order, mode):
 
 @pytest.mark.parametrize("mode", [1, 3])
 def test_batch_level7_member_equals_alone(mode):
-    """A level-7 cube member in a batch with small 2D and 3D members: the
-    batched launches of the pencil-depth-8 instance give bitwise its solve
-    alone."""
-    co, ce, m7, om, s2u, A = _cube("random")
+    """A level-7 cube member and a level-8 two-tet member in a batch with
+    small 2D and 3D members: the batched launches of both pencil depths give
+    bitwise their solves alone."""
+    co, ce, m7, om, s2u, A, _ = _cube("random")
     b7, _ = _rhs(m7, om, s2u, 75)
-    reqs = [(m7, L7, b7)]
+    co8, ce8, m8, om8, s2u8, A8, _ = _cube("strip2")
+    b8, _ = _rhs(m8, om8, s2u8, 76, L8)
+    reqs = [(m7, L7, b7), (m8, L8, b8)]
     for dim, k, L, seed in ((2, 3, 6, 1), (3, 2, 4, 2)):
         c2, e2 = W.strip_2d(k) if dim == 2 else W.strip_3d(k)
         J, t = W.random_affine(dim, seed)

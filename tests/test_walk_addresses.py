@@ -172,10 +172,10 @@ def test_2d_walk_apex_and_hypotenuse_tiles_large_levels(L, H, U):
     check_2d(N, H, U, tl)
 
 
-@pytest.mark.parametrize("L", range(0, 8))
+@pytest.mark.parametrize("L", range(0, 9))
 def test_3d_walk_every_pencil_small_levels(L):
     N = 1 << L
-    PZ = 4 if N < 128 else 8
+    PZ = 4 if N < 256 else 8
     check_3d(N, 4, PZ, pencils(N, 4, PZ))
 
 
