@@ -402,10 +402,12 @@ def main():
                 "launch_avg_ms": r64["launch_avg_ms"], "launch_median_ms": r64["launch_median_ms"]}
     extra = {}
     if args.copy_calibration:
+        # one library streaming copy (stream_copy_kernel) of exactly 1 GiB read and 1 GiB written:
+        # its FETCH_SIZE / WRITE_SIZE readings calibrate the counters of the other kernels
         a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
         torch.cuda.synchronize()
-        b.copy_(a)
+        P.device_copy(b, a)
         torch.cuda.synchronize()
         extra["copy_calibration_bytes"] = {"read": a.numel() * 8, "write": b.numel() * 8}
         del a, b
