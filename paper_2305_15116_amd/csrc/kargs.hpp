@@ -80,6 +80,8 @@ struct TransferArgs {
   const MacroDev* mdf;
   const T* src;
   T* dst;
+  const int32_t* sbc;  // slice bases of the coarse and the fine level (3D segment kernels)
+  const int32_t* sbf;
 };
 
 // coarse_solve_kernel
@@ -290,12 +292,12 @@ inline int transfer_blocks(int nseg) {
 template <typename T>
 TransferArgs<T> restrict_args(const Level& F, const Level& C, const void* rf, void* bc) {
   const int n = (int)C.psegs.size();
-  return TransferArgs<T>{C.dev.psegs, n, transfer_blocks(n), C.dev.md, F.dev.md, (const T*)rf, (T*)bc};
+  return TransferArgs<T>{C.dev.psegs, n, transfer_blocks(n), C.dev.md, F.dev.md, (const T*)rf, (T*)bc, C.dev.sbase, F.dev.sbase};
 }
 template <typename T>
 TransferArgs<T> prolong_args(const Level& F, const Level& C, const void* ec, void* xf) {
   const int n = (int)F.psegs.size();
-  return TransferArgs<T>{F.dev.psegs, n, transfer_blocks(n), C.dev.md, F.dev.md, (const T*)ec, (T*)xf};
+  return TransferArgs<T>{F.dev.psegs, n, transfer_blocks(n), C.dev.md, F.dev.md, (const T*)ec, (T*)xf, C.dev.sbase, F.dev.sbase};
 }
 
 template <typename T>

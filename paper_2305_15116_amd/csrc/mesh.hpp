@@ -23,6 +23,7 @@ struct LevelDev {
   Tile* tiles_f32 = nullptr;   // 2D FP32 wave tiles
   Tile* segs = nullptr;        // row segments of 64 points covering every storage point
   Tile* psegs = nullptr;       // slice segments: 64 consecutive storage points of one slice
+  int32_t* sbase = nullptr;    // first macro-local index of each slice z = 0 .. N + 1 (3D)
   int32_t* grp_ptr = nullptr;  // ngroups + 1
   Copy* copies = nullptr;
   uint8_t* grp_flag = nullptr;  // bit0: Dirichlet
@@ -59,6 +60,7 @@ struct Level {
   // slice (the whole macro in 2D) is contiguous in storage, so its points
   // are cut into 64-point pieces across row ends (full lanes where rows are short)
   std::vector<Tile> psegs;
+  std::vector<int32_t> sbase;  // slice bases, z = 0 .. N + 1 (3D; fits 32 bits up to N = 2048)
   std::vector<int32_t> grp_ptr;
   std::vector<Copy> copies;
   std::vector<uint8_t> grp_flag;

@@ -503,6 +503,9 @@ static int build_level(mf_mesh* m, int level, Level& L) {
     }
   }
   while (L.psegs.size() % kWavesPerWG) L.psegs.push_back({-1, 0, 0, 0});
+  L.sbase.assign(dim == 3 ? N + 2 : 1, 0);
+  if (dim == 3)
+    for (int z = 0; z <= N + 1; ++z) L.sbase[z] = (int32_t)slice_base(N, z);
   return MF_OK;
 }
 
@@ -514,6 +517,7 @@ int upload_level(mf_mesh* m, Level& L) {
   if ((rc = dev_upload(&D.tiles_f32, L.tiles_f32))) return rc;
   if ((rc = dev_upload(&D.segs, L.segs))) return rc;
   if ((rc = dev_upload(&D.psegs, L.psegs))) return rc;
+  if ((rc = dev_upload(&D.sbase, L.sbase))) return rc;
   if ((rc = dev_upload(&D.grp_ptr, L.grp_ptr))) return rc;
   if ((rc = dev_upload(&D.copies, L.copies))) return rc;
   if ((rc = dev_upload(&D.grp_flag, L.grp_flag))) return rc;
@@ -691,7 +695,7 @@ int build_mesh(mf_mesh* m) {
 void free_device(mf_mesh* m) {
   for (auto& L : m->levels) {
     LevelDev& D = L.dev;
-    void* ptrs[] = {D.md, D.tiles, D.tiles_f32, D.segs, D.psegs, D.grp_ptr, D.copies, D.grp_flag, D.xgrp_ptr, D.xcopies, D.cpidx, D.xcpidx, D.xgrp_invdiag,
+    void* ptrs[] = {D.md, D.tiles, D.tiles_f32, D.segs, D.psegs, D.sbase, D.grp_ptr, D.copies, D.grp_flag, D.xgrp_ptr, D.xcopies, D.cpidx, D.xcpidx, D.xgrp_invdiag,
                     D.xgrp_invdiagf,
                     D.part, D.result, D.cinv, D.cinvf, D.cfirst, D.cptr, D.cidx, D.own_bits, D.p2_tiles};
     for (void* p : ptrs)

@@ -214,9 +214,18 @@ __device__ __forceinline__ void slice_point(const Tile& sg, int N, int& x, int& 
     y = 0;
     return;
   }
-  // (in FP64: the discriminant reaches 2^32 in 2D, exact in a double)
-  const double b = 2.0 * (double)S + 3.0;
-  int yy = (int)((b - sqrt(b * b - 8.0 * (double)r)) * 0.5);
+  int yy;
+  if (DIM == 3) {
+    // 3D slices have S <= 2048: the FP32 discriminant is exact or within an
+    // ulp, and the hardware root within an ulp, far inside the one-step
+    // correction below
+    const float b = 2.0f * (float)S + 3.0f;
+    yy = (int)((b - __builtin_amdgcn_sqrtf(b * b - 8.0f * (float)r)) * 0.5f);
+  } else {
+    // 2D: the discriminant reaches 2^32, exact in a double
+    const double b = 2.0 * (double)S + 3.0;
+    yy = (int)((b - sqrt(b * b - 8.0 * (double)r)) * 0.5);
+  }
   yy = min(max(yy, 0), S);
   if (row_start(S, yy) > r) --yy;
   else if (yy < S && row_start(S, yy + 1) <= r) ++yy;
@@ -224,11 +233,70 @@ __device__ __forceinline__ void slice_point(const Tile& sg, int N, int& x, int& 
   x = r - row_start(S, yy);
 }
 
+// Restriction over one 3D slice segment of coarse points: the same sum as
+// restrict_point, in the same order, with cheaper index work.  Slice bases
+// come from the per-level tables; the storage index of fine point 2P + d is
+// formed from that of 2P (slice 2z of side S = Nf - 2z, row 2y of
+// l = S + 1 - 2y points): +-1 along the row, l after / l + 1 before it for
+// rows 2y +- 1, T(S) - 2y after and T(S + 1) - 2y before it for slices
+// 2z +- 1 (T(s) = (s + 1)(s + 2) / 2 points in a slice of side s), all as
+// 32-bit offsets from the first point of slice 2z - 1.  Whether 2P + d lies
+// in the macro, and its support mask, follow from P's position:
+// 2x + dx = 0 only for x = 0 and dx = 0, and Nf - |2P + d| =
+// 2 (Nc - |P|) - |d| vanishes only on P's far face with |d| = 0.
+template <typename T>
+__device__ __forceinline__ T restrict_seg3(const TransferArgs<T>& a, const Tile sg, int64_t& di, bool& wr) {
+  constexpr StencilTable ST = stencil_table(3);
+  constexpr int full = 15;
+  const MacroC C = load_macro(a.mdc, sg.macro);
+  const MacroC F = load_macro(a.mdf, sg.macro);
+  const int Nc = C.N, Nf = F.N;
+  int x, y, z;
+  slice_point<3>(sg, Nc, x, y, z);
+  const bool live = x + y + z <= Nc;
+  const bool x0 = x == 0, y0 = y == 0, z0 = z == 0, far = x + y + z == Nc;
+  const int zf = 2 * z, S = Nf - zf, yf = live ? 2 * y : 0, xf = live ? 2 * x : 0;
+  const int za = zf > 0 ? zf - 1 : 0;
+  const T* __restrict__ Fa = a.src + F.base + as_const(a.sbf)[za];  // anchor: slice 2z - 1 (slice 0 at z = 0)
+  const int tb = as_const(a.sbf)[zf] - as_const(a.sbf)[za];         // points of slice 2z - 1 (0 at z = 0)
+  const int c = tb + row_start(S, yf) + xf;
+  const int l = S + 1 - yf;
+  const int up = c + (S + 1) * (S + 2) / 2 - yf;
+  const int dn = c - tb + yf;
+  const int rel[15] = {dn,     dn + 1,     dn + l + 1, dn + l, c - l - 1, c - l, c - 1, c,
+                       c + 1,  c + l - 1,  c + l,      up - l, up - l + 1, up - 1, up};
+  T acc = T(0);
+#pragma unroll
+  for (int s = 0; s < ST.n; ++s) {
+    const int dx = ST.off[s][0], dy = ST.off[s][1], dz = ST.off[s][2], sd = dx + dy + dz;
+    const bool in = live && (dx >= 0 || !x0) && (dy >= 0 || !y0) && (dz >= 0 || !z0) && (sd <= 0 || !far);
+    const int mask = ((sd == 0 && far) ? 0 : 1) | ((dx == 0 && x0) ? 0 : 2) | ((dy == 0 && y0) ? 0 : 4) |
+                     ((dz == 0 && z0) ? 0 : 8);
+    const bool owned = mask == full || ((F.own_mask >> mask) & 1);
+    const bool dir = mask != full && ((F.dir_mask >> mask) & 1);
+    const bool use = in && owned && !dir;
+    // points outside the macro read the anchor (value unused)
+    const T r = Fa[in ? (unsigned)rel[s] : 0u];
+    const T w = s == ST.centre ? T(1) : T(0.5);
+    acc += use ? w * r : T(0);
+  }
+  di = C.base + as_const(a.sbc)[z] + sg.x0 + (int)(threadIdx.x & (kWave - 1));
+  wr = live;
+  return acc;
+}
+
 template <typename T, int DIM>
 __device__ __forceinline__ void restrict_segment(const TransferArgs<T>& a, const Tile sg) {
-  int x, y, z;
-  slice_point<DIM>(sg, load_macro(a.mdc, sg.macro).N, x, y, z);
-  restrict_point<T, DIM>(a, sg.macro, x, y, z);
+  if constexpr (DIM == 3) {
+    int64_t di;
+    bool wr;
+    const T acc = restrict_seg3<T>(a, sg, di, wr);
+    if (wr) a.dst[di] = acc;
+  } else {
+    int x, y, z;
+    slice_point<DIM>(sg, load_macro(a.mdc, sg.macro).N, x, y, z);
+    restrict_point<T, DIM>(a, sg.macro, x, y, z);
+  }
 }
 
 // x_f += P e_c: even fine points take the coarse value, the others the mean
@@ -259,11 +327,54 @@ __device__ __forceinline__ void prolong_point(const TransferArgs<T>& a, int macr
   const T v = a.src[C.base + lidx<DIM>(Nc, (xl + sx) >> 1, (yl + sy) >> 1, (zl + sz) >> 1)];
   if (live && !dir) a.dst[F.base + lidx<DIM>(Nf, x, y, z)] += T(0.5) * (u + v);
 }
+// Prolongation over one 3D slice segment of fine points: prolong_point's
+// update, with the slice bases from the per-level tables and the coarse
+// points addressed by 32-bit offsets from the first point of coarse slice
+// z / 2 (the other coarse slice, (z + 1) / 2, follows it), the fine point by
+// its slice-local index.
+template <typename T>
+__device__ __forceinline__ void prolong_seg3(const TransferArgs<T>& a, const Tile sg, int64_t& di, T& u, T& v,
+                                             bool& wr) {
+  constexpr int full = 15;
+  const MacroC C = load_macro(a.mdc, sg.macro);
+  const MacroC F = load_macro(a.mdf, sg.macro);
+  const int Nc = C.N, Nf = F.N;
+  int x, y, z;
+  slice_point<3>(sg, Nf, x, y, z);
+  const bool live = x + y + z <= Nf;
+  const int mask = support_mask(3, Nf, x, y, z);
+  const bool dir = mask != full && ((F.dir_mask >> mask) & 1);
+  // dead lanes read the coarse points of (0, 0, z)
+  const int xl = live ? x : 0, yl = live ? y : 0;
+  const int px = xl & 1, py = yl & 1, pz = z & 1;
+  const int sx = px;
+  const int sy = (px && py) ? -1 : py;
+  const int sz = (pz && (px ^ py)) ? -1 : pz;
+  // coarse slices (z - sz) / 2 and (z + sz) / 2 are z / 2 or (z + 1) / 2
+  const int zl = z >> 1, zh = (z + 1) >> 1;
+  const T* __restrict__ Cl = a.src + C.base + as_const(a.sbc)[zl];
+  const int dh = as_const(a.sbc)[zh] - as_const(a.sbc)[zl];
+  const int zu = sz < 0 ? zh : zl, zv = sz > 0 ? zh : zl;
+  u = Cl[(unsigned)((sz < 0 ? dh : 0) + row_start(Nc - zu, (yl - sy) >> 1) + ((xl - sx) >> 1))];
+  v = Cl[(unsigned)((sz > 0 ? dh : 0) + row_start(Nc - zv, (yl + sy) >> 1) + ((xl + sx) >> 1))];
+  // dead lanes name the macro's first point (a valid address, never written)
+  di = F.base + (live ? as_const(a.sbf)[z] + sg.x0 + (int)(threadIdx.x & (kWave - 1)) : 0);
+  wr = live && !dir;
+}
+
 template <typename T, int DIM>
 __device__ __forceinline__ void prolong_segment(const TransferArgs<T>& a, const Tile sg) {
-  int x, y, z;
-  slice_point<DIM>(sg, load_macro(a.mdf, sg.macro).N, x, y, z);
-  prolong_point<T, DIM>(a, sg.macro, x, y, z);
+  if constexpr (DIM == 3) {
+    int64_t di;
+    T u, v;
+    bool wr;
+    prolong_seg3<T>(a, sg, di, u, v, wr);
+    if (wr) a.dst[di] += T(0.5) * (u + v);
+  } else {
+    int x, y, z;
+    slice_point<DIM>(sg, load_macro(a.mdf, sg.macro).N, x, y, z);
+    prolong_point<T, DIM>(a, sg.macro, x, y, z);
+  }
 }
 
 // First Jacobi sweep of a V-cycle level.  The iterate is zero there, so

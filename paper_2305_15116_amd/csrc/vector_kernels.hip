@@ -74,29 +74,74 @@ __global__ __launch_bounds__(kWG) void fill_random_kernel(const Tile* __restrict
 
 
 
+// Each wave walks several segments.  In 3D a wave takes kTransferU of them at
+// a time and issues all their loads before any store: a segment's work is a
+// short chain of dependent loads (segment record, macro records, values),
+// so independent segments in flight hide that latency.
+constexpr int kTransferU = 4;
+
 template <typename T, int DIM>
 __global__ __launch_bounds__(kWG) void restrict_kernel(const Launch<TransferArgs<T>> L) {
   TransferArgs<T> a;
   const int blk = resolve(L, (int)blockIdx.x, a);
   const int stride = a.nblk * kWavesPerWG;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  for (int si = blk * kWavesPerWG + w; si < a.nseg; si += stride) {
-    const Tile sg = load_seg(a.segs, si);
-    if (sg.macro >= 0) restrict_segment<T, DIM>(a, sg);
+  if constexpr (DIM == 3) {
+    for (int si = blk * kWavesPerWG + w; si < a.nseg; si += kTransferU * stride) {
+      T acc[kTransferU];
+      int64_t di[kTransferU];
+      bool wr[kTransferU];
+#pragma unroll
+      for (int k = 0; k < kTransferU; ++k) {
+        const int sk = si + k * stride;
+        const Tile sg = sk < a.nseg ? load_seg(a.segs, sk) : Tile{-1, 0, 0, 0};
+        wr[k] = false;
+        if (sg.macro >= 0) acc[k] = restrict_seg3<T>(a, sg, di[k], wr[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < kTransferU; ++k)
+        if (wr[k]) a.dst[di[k]] = acc[k];
+    }
+  } else {
+    for (int si = blk * kWavesPerWG + w; si < a.nseg; si += stride) {
+      const Tile sg = load_seg(a.segs, si);
+      if (sg.macro >= 0) restrict_segment<T, DIM>(a, sg);
+    }
   }
 }
 
 
-// x_f += P e_c (each wave walks several segments of fine points).
+// x_f += P e_c.
 template <typename T, int DIM>
 __global__ __launch_bounds__(kWG) void prolong_add_kernel(const Launch<TransferArgs<T>> L) {
   TransferArgs<T> a;
   const int blk = resolve(L, (int)blockIdx.x, a);
   const int stride = a.nblk * kWavesPerWG;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  for (int si = blk * kWavesPerWG + w; si < a.nseg; si += stride) {
-    const Tile sg = load_seg(a.segs, si);
-    if (sg.macro >= 0) prolong_segment<T, DIM>(a, sg);
+  if constexpr (DIM == 3) {
+    for (int si = blk * kWavesPerWG + w; si < a.nseg; si += kTransferU * stride) {
+      T u[kTransferU], v[kTransferU], xo[kTransferU];
+      int64_t di[kTransferU];
+      bool wr[kTransferU];
+#pragma unroll
+      for (int k = 0; k < kTransferU; ++k) {
+        const int sk = si + k * stride;
+        const Tile sg = sk < a.nseg ? load_seg(a.segs, sk) : Tile{-1, 0, 0, 0};
+        wr[k] = false;
+        if (sg.macro >= 0) prolong_seg3<T>(a, sg, di[k], u[k], v[k], wr[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < kTransferU; ++k)
+        if (wr[k]) xo[k] = a.dst[di[k]];
+#pragma unroll
+      for (int k = 0; k < kTransferU; ++k)
+        if (wr[k]) a.dst[di[k]] = xo[k] + T(0.5) * (u[k] + v[k]);
+    }
+  } else {
+    for (int si = blk * kWavesPerWG + w; si < a.nseg; si += stride) {
+      const Tile sg = load_seg(a.segs, si);
+      if (sg.macro >= 0) prolong_segment<T, DIM>(a, sg);
+    }
   }
 }
 
@@ -201,29 +246,65 @@ __device__ __forceinline__ double wmax(double v) {
 // alpha = res[2] / res[4], x += alpha p, r -= alpha q, partials of r . r and
 // max |r|.  Sums count each unique DoF once (owner bits); each block leaves
 // one partial, its four waves summed in a fixed order.
+constexpr int kPcgU = 4;
+
 template <int KIND, typename TE>
 __global__ __launch_bounds__(256) void pcg_lin_kernel(const Launch<PcgArgs> L) {
   PcgArgs a;
   const int blk = resolve(L, (int)blockIdx.x, a);
   const int64_t stride = (int64_t)a.nblk * 256;
   double ss = 0.0, mx = 0.0;
+  // kPcgU elements per thread and step, all loads issued before any use (the
+  // owner-bit test selects instead of branching around the load), so each
+  // thread keeps kPcgU independent loads in flight; the elements are still
+  // taken in index order, so the sums are those of a one-element loop.
+  const int64_t i0 = (int64_t)blk * 256 + threadIdx.x;
   if (KIND == kOpPcgZDot) {
     const double sc = sizeof(TE) == 4 ? a.res[1] : 1.0;
     const TE* e = (const TE*)a.e;
     const bool wz = a.z != nullptr && (const void*)a.z != a.e;
-    for (int64_t i = (int64_t)blk * 256 + threadIdx.x; i < a.n; i += stride) {
-      const double zv = sc * (double)e[i];
-      if (wz) a.z[i] = zv;
-      if ((a.own[i >> 5] >> (i & 31)) & 1u) ss = fma(a.r[i], zv, ss);
+    for (int64_t i = i0; i < a.n; i += kPcgU * stride) {
+      double zv[kPcgU], rv[kPcgU];
+      uint32_t ow[kPcgU];
+#pragma unroll
+      for (int u = 0; u < kPcgU; ++u) {
+        const int64_t j = i + u * stride, jj = j < a.n ? j : i;
+        zv[u] = sc * (double)e[jj];
+        rv[u] = a.r[jj];
+        ow[u] = a.own[jj >> 5];
+      }
+#pragma unroll
+      for (int u = 0; u < kPcgU; ++u) {
+        const int64_t j = i + u * stride;
+        if (j >= a.n) break;
+        if (wz) a.z[j] = zv[u];
+        if ((ow[u] >> (j & 31)) & 1u) ss = fma(rv[u], zv[u], ss);
+      }
     }
   } else {
     const double alpha = a.res[2] / a.res[4];
-    for (int64_t i = (int64_t)blk * 256 + threadIdx.x; i < a.n; i += stride) {
-      a.x[i] = fma(alpha, a.p[i], a.x[i]);
-      const double rn = fma(-alpha, a.q[i], a.r[i]);
-      a.r[i] = rn;
-      if ((a.own[i >> 5] >> (i & 31)) & 1u) ss = fma(rn, rn, ss);
-      mx = fmax(mx, fabs(rn));
+    for (int64_t i = i0; i < a.n; i += kPcgU * stride) {
+      double xv[kPcgU], pv[kPcgU], qv[kPcgU], rv[kPcgU];
+      uint32_t ow[kPcgU];
+#pragma unroll
+      for (int u = 0; u < kPcgU; ++u) {
+        const int64_t j = i + u * stride, jj = j < a.n ? j : i;
+        xv[u] = a.x[jj];
+        pv[u] = a.p[jj];
+        qv[u] = a.q[jj];
+        rv[u] = a.r[jj];
+        ow[u] = a.own[jj >> 5];
+      }
+#pragma unroll
+      for (int u = 0; u < kPcgU; ++u) {
+        const int64_t j = i + u * stride;
+        if (j >= a.n) break;
+        a.x[j] = fma(alpha, pv[u], xv[u]);
+        const double rn = fma(-alpha, qv[u], rv[u]);
+        a.r[j] = rn;
+        if ((ow[u] >> (j & 31)) & 1u) ss = fma(rn, rn, ss);
+        mx = fmax(mx, fabs(rn));
+      }
     }
   }
   ss = wsum(ss);
