@@ -129,7 +129,7 @@ struct Pass {
 template <typename T, class Sel>
 void stencil_pass(PlanBuilder& P, const std::vector<Member*>& ms, int dim, int dtype, int mode, double omega,
                   Sel sel) {
-  // one stencil launch per pencil depth (levels differ in it), then one exchange launch
+  // one stencil launch per tile shape (levels differ in it), then one exchange launch
   std::vector<std::pair<StencilArgs<T>, int>> sa[2];
   std::vector<std::pair<GroupArgs<T>, int>> ga;
   for (Member* M : ms) {
@@ -138,11 +138,11 @@ void stencil_pass(PlanBuilder& P, const std::vector<Member*>& ms, int dim, int d
     if (!sel(*M, p)) continue;
     const Level& L = lev(*M, p.level);
     const StencilArgs<T> a = stencil_args<T>(L, p.x, p.y, p.b, omega, p.part);
-    sa[dim == 3 && L.pen_z == kPenZSmall ? 1 : 0].push_back({a, a.nwg});
+    sa[dim == 3 && L.pen_z == kPenSeg ? 1 : 0].push_back({a, a.nwg});
     ga.push_back({exchange_args<T>(L, p.x, p.y, p.b, omega, p.part), exchange_blocks(L)});
   }
   P.add(kOpStencil, dtype, dim, mode, sa[0], kPenZ);
-  P.add(kOpStencil, dtype, dim, mode, sa[1], kPenZSmall);
+  P.add(kOpStencil, dtype, dim, mode, sa[1], kPenSeg);
   P.add(kOpExchange, dtype, dim, mode, ga);
 }
 

@@ -412,7 +412,7 @@ struct BatchOp {
   int kind, dtype, dim, mode;
   int nseg, nwg;
   int64_t args_off, wg0_off;
-  int variant;  // stencil ops: 3D pencil depth of the members' levels
+  int variant;  // stencil ops: 3D tile shape of the members' levels (kPenZ or kPenSeg)
   int pad_;
 };
 

@@ -49,7 +49,7 @@ struct LevelDev {
 struct Level {
   int level = 0;
   int N = 0;
-  int pen_z = 0;  // 3D pencil depth of the wave tiles (kPenZ or kPenZSmall)
+  int pen_z = 0;  // 3D tile shape: pencils of kPenZ slices, or runs of slice segments (kPenSeg)
   int64_t storage = 0, unique = 0;
   std::vector<int64_t> base;    // per macro storage offset
   std::vector<MacroDev> md;

@@ -459,12 +459,23 @@ static int build_level(mf_mesh* m, int level, Level& L) {
   for (size_t i = 0; i < L.xcopies.size(); ++i) L.xcpidx[i] = storage_index(L.xcopies[i]);
 
   // wave tiles over every point of every macro, natural order: macro,
-  // (slice chunk,) strip, band
+  // (slice chunk,) strip, band; on small 3D levels runs of slice segments
+  // (macro, slice, index)
   L.tiles.clear();
-  L.pen_z = N < kPenZSmallBelowN ? kPenZSmall : kPenZ;
-  L.tiles.reserve((size_t)m->nc * (macro_points(dim, N) / (kTileW * (dim == 2 ? kTileH2 : kPenR * L.pen_z)) * 2 + 64));
+  L.pen_z = dim == 3 && N <= kSegUpToN ? kPenSeg : kPenZ;
+  if (L.pen_z == kPenSeg)
+    L.tiles.reserve((size_t)m->nc * (macro_points(dim, N) / (kWave * seg_run(N)) + N + 2) + 64);
+  else
+    L.tiles.reserve((size_t)m->nc * (macro_points(dim, N) / (kTileW * (dim == 2 ? kTileH2 : kPenR * L.pen_z)) * 2 + 64));
   for (int64_t c = 0; c < m->nc; ++c) {
-    if (dim == 2) {
+    if (L.pen_z == kPenSeg) {
+      for (int z = 0; z <= N; ++z) {
+        const int64_t S = N - z, P = (S + 1) * (S + 2) / 2;
+        const int64_t run = kWave * seg_run(N);
+        for (int64_t r0 = 0; r0 < P; r0 += run)
+          L.tiles.push_back({(int32_t)c, (int32_t)r0, (int32_t)std::min<int64_t>(run, P - r0), z});
+      }
+    } else if (dim == 2) {
       for (int y0 = 0; y0 <= N; y0 += kTileH2)
         for (int x0 = 0; x0 + y0 <= N; x0 += kTileW) L.tiles.push_back({(int32_t)c, x0, y0, 0});
     } else {

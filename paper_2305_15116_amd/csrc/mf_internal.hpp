@@ -38,15 +38,24 @@ constexpr int kRingU2F = 8;
 #endif
 constexpr int kPenR = MF_PEN_R;
 constexpr int kPenZ = MF_PEN_Z;
-// Small levels use shorter pencils: a wave's walk is a chain of dependent
-// slice loads, and with few waves in flight its length sets the kernel time
-// (measured: at N = 128 pencils of 4 slices take 31 us per FP64 apply on the
-// 6-tet cube against 34 us with 8; at N = 256, 8 slices are faster).
-constexpr int kPenZSmall = 4;
-#ifndef MF_PENZ_SMALL_BELOW
-#define MF_PENZ_SMALL_BELOW 256
+// Small 3D levels: instead of pencils, a wave takes a run of up to kSegRun
+// slice segments (64 consecutive storage points of one slice each, across
+// row ends), one point per lane, and gathers each point's 15 neighbours.
+// A pencil's walk is a chain of dependent slice loads, and with few waves in
+// flight that chain sets a small level's kernel time; a run has no chain, so
+// a launch costs about one round of loads (measured on the 6-tet cube: 11-14
+// us per FP64 apply at N = 16..64 against 18 us with pencils).  From N = 256
+// on, the 15 gathered loads per point cost more than the walk (FP64 apply at
+// N = 256: 169 us against 96).  kPenSeg marks a level whose tile list holds
+// such runs.
+constexpr int kPenSeg = 1;
+#ifndef MF_SEG3D_UPTO_N
+#define MF_SEG3D_UPTO_N 128
 #endif
-constexpr int kPenZSmallBelowN = MF_PENZ_SMALL_BELOW;  // pencil depth kPenZSmall when N < this
+constexpr int kSegUpToN = MF_SEG3D_UPTO_N;  // runs of slice segments when N <= this
+constexpr int kSegRun = 4;
+// segments per run at side N: fewer on the smallest levels, for more waves
+MF_HD constexpr int seg_run(int N) { return N >= 128 ? 4 : (N >= 64 ? 2 : 1); }
 #ifndef MF_WAVES_PER_WG
 #define MF_WAVES_PER_WG 4
 #endif
@@ -57,7 +66,8 @@ constexpr int kXCD = 8;        // MI355X: 8 accelerator complex dies, workgroups
 
 // A wave tile: columns [x0, x0+62) of rows [y0, y0+H) of `macro` (2D), or of
 // rows [y0, y0+kPenR) in slices [z, z+kPenZ) (3D).  For per-point kernels the same record names a row segment
-// of 64 points starting at x0 of row y0 in slice z.  macro < 0: padding.
+// of 64 points starting at x0 of row y0 in slice z; in the tile list of a kPenSeg level, y0 points of slice z
+// from slice-local index x0 (a run of at most kSegRun segments).  macro < 0: padding.
 struct Tile {
   int32_t macro, x0, y0, z;
 };

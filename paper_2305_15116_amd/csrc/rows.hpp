@@ -199,6 +199,21 @@ __device__ __forceinline__ void restrict_point(const TransferArgs<T>& a, int mac
   }
   if (live) a.dst[C.base + lidx<DIM>(Nc, x, y, z)] = acc;
 }
+// (x, y) of slice-local index r in a 3D slice of side S <= 2048, r <
+// (S+1)(S+2)/2: y is the smaller root of y^2 - (2S + 3) y + 2r = 0 (row y
+// starts at y (2S + 3 - y) / 2), rounded down and corrected by one step
+// either way.  The FP32 discriminant is exact or within an ulp and the
+// hardware root within an ulp, far inside that correction.
+__device__ __forceinline__ void slice_xy3(int S, int r, int& x, int& y) {
+  const float b = 2.0f * (float)S + 3.0f;
+  int yy = (int)((b - __builtin_amdgcn_sqrtf(b * b - 8.0f * (float)r)) * 0.5f);
+  yy = min(max(yy, 0), S);
+  if (row_start(S, yy) > r) --yy;
+  else if (yy < S && row_start(S, yy + 1) <= r) ++yy;
+  y = yy;
+  x = r - row_start(S, yy);
+}
+
 // This lane's point of slice segment sg ({macro, first slice-local index, 0,
 // z}) in a macro of side N: the slice of side S = N - z holds (S+1)(S+2)/2
 // points, row y starting at y (2S + 3 - y) / 2, so y is the smaller root of
@@ -214,18 +229,13 @@ __device__ __forceinline__ void slice_point(const Tile& sg, int N, int& x, int& 
     y = 0;
     return;
   }
-  int yy;
   if (DIM == 3) {
-    // 3D slices have S <= 2048: the FP32 discriminant is exact or within an
-    // ulp, and the hardware root within an ulp, far inside the one-step
-    // correction below
-    const float b = 2.0f * (float)S + 3.0f;
-    yy = (int)((b - __builtin_amdgcn_sqrtf(b * b - 8.0f * (float)r)) * 0.5f);
-  } else {
-    // 2D: the discriminant reaches 2^32, exact in a double
-    const double b = 2.0 * (double)S + 3.0;
-    yy = (int)((b - sqrt(b * b - 8.0 * (double)r)) * 0.5);
+    slice_xy3(S, r, x, y);
+    return;
   }
+  // 2D: the discriminant reaches 2^32, exact in a double
+  const double b = 2.0 * (double)S + 3.0;
+  int yy = (int)((b - sqrt(b * b - 8.0 * (double)r)) * 0.5);
   yy = min(max(yy, 0), S);
   if (row_start(S, yy) > r) --yy;
   else if (yy < S && row_start(S, yy + 1) <= r) ++yy;

@@ -442,11 +442,74 @@ __device__ __forceinline__ void pencil3d(const int x0, const int y0, const int z
 
 
 
+// ------------------------------------------------------------ 3D slice runs
+// A run of t.y0 consecutive points of slice z from slice-local index t.x0,
+// one point per lane, 64 at a time.  Relative to the point's own index p in
+// slice z (side S = N - z; row y holds d = S + 1 - y points): row y + 1 of
+// the slice starts d after p's column, row y - 1 ends d + 1 before it; the
+// point (x, y, z + 1) lies T(S) - y after p and (x, y, z - 1) lies
+// T(S + 1) - y before it, T(s) = (s + 1)(s + 2) / 2 being the points of a
+// slice of side s.  The 15 neighbours are therefore seven row positions and
+// their +-1 columns.  Indices are formed relative to the first point of
+// slice z - 1 (of slice 0 at z = 0), so every offset is a non-negative
+// 32-bit value.  Lattice points outside the macro map to some index of the
+// neighbouring slices; for 1 <= z <= N - 2 every such index stays inside
+// the macro, elsewhere the indices are clamped into it.  Those values are
+// stand-ins that the boundary rows never use (point_row).
+template <typename T, int MODE>
+__device__ __forceinline__ void seg3d(const Tile& t, const MacroDev& M, WTab<T> W, const T* __restrict__ X,
+                                      T* __restrict__ Y, const T* __restrict__ B, T omega, double& ss, double& mx) {
+  constexpr int FM = full_mask(3);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int N = M.N, z = t.z, S = N - z;
+  T wi[15];
+#pragma unroll
+  for (int o = 0; o < 15; ++o) wi[o] = Prec<T>::w(M, FM, o);
+  T bid[3] = {T(0), T(0), T(0)};
+  if (MODE == kJacobi) {
+    constexpr int c = stencil_table(3).centre;
+    bid[0] = T(1) / W[RowMasks<3>::L][c];
+    bid[1] = T(1) / W[RowMasks<3>::F][c];
+    bid[2] = T(1) / W[RowMasks<3>::LF][c];
+  }
+  const int za = max(z - 1, 0);
+  const int64_t ab = M.base + slice_base(N, za);
+  const T* Xa = X + ab;
+  const int Ts = (S + 1) * (S + 2) / 2;                 // points of slice z
+  const int Tb = z > 0 ? (S + 2) * (S + 3) / 2 : 0;     // points of slice z - 1: offset of slice z
+  const bool safe = z >= 1 && z + 2 <= N;
+  // highest index of the three slices around z, inside the macro
+  const int hi = (int)min(tet_count_small(N + 1) - slice_base(N, za) - 1, (int64_t)Tb + 2 * (int64_t)Ts);
+  auto ld = [&](int i) -> T {
+    if (!safe) i = min(max(i, 0), hi);
+    return *(const T*)((const char*)Xa + (unsigned)i * (unsigned)sizeof(T));
+  };
+#pragma unroll
+  for (int k = 0; k < kSegRun; ++k) {
+    if (k * kWave >= t.y0) break;  // wave-uniform
+    int r = t.x0 + k * kWave + lane;
+    const bool live = k * kWave + lane < t.y0;
+    if (!live) r = 0;
+    int x, y;
+    slice_xy3(S, r, x, y);
+    const int d = S + 1 - y;
+    const int p = Tb + r;
+    const int pu = p + Ts - y;
+    const int pd = r + y;
+    const T v[15] = {ld(pd),         ld(pd + 1),     ld(pd + d + 1), ld(pd + d), ld(p - d - 1),
+                     ld(p - d),      ld(p - 1),      ld(p),          ld(p + 1),  ld(p + d - 1),
+                     ld(p + d),      ld(pu - d),     ld(pu - d + 1), ld(pu - 1), ld(pu)};
+    const T bv = MODE != kApply ? B[ab + p] : T(0);
+    point_row<T, 3, MODE>(M, W, wi, live, N, x, y, z, v, v[7], bv, omega, Y + ab + p, ss, mx, true, true, bid);
+  }
+}
+
 // Whether a wave tile has output points on its macro's boundary (x = 0,
 // y = 0, z = 0 or the far face x + y + z = N).
 template <typename T, int DIM, int PZ>
 __device__ __forceinline__ bool tile_on_boundary(const Tile& t, int N) {
   if (DIM == 2) return t.x0 == 0 || t.y0 == 0 || t.x0 + t.y0 + (kTileW - 1) + (Tile2<T>::H - 1) >= N;
+  if (PZ == kPenSeg) return true;  // a run of 64 points or more reaches a row end
   return t.x0 == 0 || t.y0 == 0 || t.z == 0 || t.x0 + t.y0 + t.z + (kTileW - 1) + (kPenR - 1) + (PZ - 1) >= N;
 }
 
@@ -491,6 +554,8 @@ __global__ __launch_bounds__(kWG) void stencil_kernel(const Launch<StencilArgs<T
       tile2d_fast<T, MODE>(t.x0, t.y0, M, a.X, a.Y, a.B, a.omega, ss, mx);
     else if (DIM == 2)
       tile2d<T, MODE>(t.x0, t.y0, M, W, a.X, a.Y, a.B, a.omega, ss, mx);
+    else if (PZ == kPenSeg)
+      seg3d<T, MODE>(t, M, W, a.X, a.Y, a.B, a.omega, ss, mx);
     else
       pencil3d<T, MODE, PZ>(t.x0, t.y0, t.z, M, W, a.X, a.Y, a.B, a.omega, ss, mx);
   }
@@ -648,10 +713,10 @@ void run_stencil(const Level& L, const void* x, void* y, const void* b, double o
                  hipStream_t s) {
   const StencilArgs<T> a = stencil_args<T>(L, x, y, b, omega, part);
   if (a.nwg > 0) {
-    // the pencil depth is a 3D notion: 2D uses one instance
-    if (DIM == 3 && L.pen_z == kPenZSmall) {
+    // the tile shape is a 3D notion: 2D uses one instance
+    if (DIM == 3 && L.pen_z == kPenSeg) {
       if constexpr (DIM == 3)
-        hipLaunchKernelGGL((stencil_kernel<T, DIM, MODE, kPenZSmall>), dim3(stencil_grid(a.nwg)), dim3(kWG), 0, s,
+        hipLaunchKernelGGL((stencil_kernel<T, DIM, MODE, kPenSeg>), dim3(stencil_grid(a.nwg)), dim3(kWG), 0, s,
                            single(a, a.nwg));
     } else {
       hipLaunchKernelGGL((stencil_kernel<T, DIM, MODE, kPenZ>), dim3(stencil_grid(a.nwg)), dim3(kWG), 0, s,
@@ -701,9 +766,9 @@ int launch(const mf_mesh* m, const Level& L, int dtype, int mode, const void* x,
 // ---------------------------------------------------------------- batched
 template <typename T, int DIM, int MODE>
 void batch_stencil(const BatchOp& op, const char* table, hipStream_t s) {
-  if (op.kind == kOpStencil && DIM == 3 && op.variant == kPenZSmall) {
+  if (op.kind == kOpStencil && DIM == 3 && op.variant == kPenSeg) {
     if constexpr (DIM == 3)
-      hipLaunchKernelGGL((stencil_kernel<T, DIM, MODE, kPenZSmall>), dim3(stencil_grid(op.nwg)), dim3(kWG), 0, s,
+      hipLaunchKernelGGL((stencil_kernel<T, DIM, MODE, kPenSeg>), dim3(stencil_grid(op.nwg)), dim3(kWG), 0, s,
                          batched<StencilArgs<T>>(op, table));
   } else if (op.kind == kOpStencil)
     hipLaunchKernelGGL((stencil_kernel<T, DIM, MODE, kPenZ>), dim3(stencil_grid(op.nwg)), dim3(kWG), 0, s,

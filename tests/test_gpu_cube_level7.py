@@ -1,15 +1,16 @@
 """Parity of the 3D kernels that the cube benchmarks run, against the oracle.
 
-From N = 256 (level 8) on, 3D stencil launches use pencils of 8 slices
-instead of 4, a separate kernel instance with its own slice ring and
+3D stencil launches use two kernel instances: up to N = 128 (level 7) waves
+take runs of slice segments and gather each point's neighbours; from
+N = 256 (level 8) on they walk pencils of 8 slices with a slice ring and a
 right-hand-side double buffer.  These tests compare every storage DoF with
 the oracle's CSR: the apply, three Jacobi sweeps and the residual with its
 norm, in FP64 (1e-12 relative, max norm) and FP32 (the rounding bound of the
 parity tests), on the 6-tet unit cube at level 7 in both vertex orders (the
 canonical Kuhn order and a seeded random order per tet; 2,146,689 unique
-DoFs, pencils of 4 slices) and on two face-sharing tets with shuffled vertex
-orders at level 8 (5,691,265 unique DoFs, pencils of 8 slices, the shared
-face completed by the exchange).  The CG solver's fused apply + dot mode is
+DoFs, slice runs) and on two face-sharing tets with shuffled vertex orders
+at level 8 (5,691,265 unique DoFs, pencils, the shared face completed by the
+exchange).  The CG solver's fused apply + dot mode is
 checked through solves whose residual the oracle recomputes, the batched
 launches through members that must equal their solve alone, and the
 mixed-precision solve of the benchmark (cube level 8) against the
@@ -159,7 +160,7 @@ def test_cg_level7_residual_by_oracle(order, mode):
 @pytest.mark.parametrize("mode", [1, 3])
 def test_batch_level7_member_equals_alone(mode):
     """A level-7 cube member and a level-8 two-tet member in a batch with
-    small 2D and 3D members: the batched launches of both pencil depths give
+    small 2D and 3D members: the batched launches of both 3D tile shapes give
     bitwise their solves alone."""
     co, ce, m7, om, s2u, A, _ = _cube("random")
     b7, _ = _rhs(m7, om, s2u, 75)

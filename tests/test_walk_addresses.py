@@ -13,8 +13,10 @@ element offset against the macro's point count.
 
 The replay follows the kernels' loops: the tile lists are the ones the mesh
 set-up builds (2D: bands of H rows, 62-column tiles; 3D: pencils of 4 rows x
-PZ slices), the rows and slices each tile loads are those of tile2d,
-tile2d_fast and pencil3d, and the clamps are ldrow's.
+8 slices), the rows and slices each tile loads are those of tile2d,
+tile2d_fast and pencil3d, and the clamps are ldrow's.  Small 3D levels use
+runs of slice segments instead (seg3d), whose per-lane neighbour indices are
+replayed at the end of this file.
 """
 import numpy as np
 import pytest
@@ -174,9 +176,10 @@ def test_2d_walk_apex_and_hypotenuse_tiles_large_levels(L, H, U):
 
 @pytest.mark.parametrize("L", range(0, 9))
 def test_3d_walk_every_pencil_small_levels(L):
+    """Pencils of 4 rows x 8 slices (the library uses them from N = 256 on;
+    the index arithmetic is replayed at every level up to that one)."""
     N = 1 << L
-    PZ = 4 if N < 256 else 8
-    check_3d(N, 4, PZ, pencils(N, 4, PZ))
+    check_3d(N, 4, 8, pencils(N, 4, 8))
 
 
 def test_3d_walk_apex_and_far_face_pencils_level_11():
@@ -202,3 +205,99 @@ def test_replay_catches_an_unclamped_apex_row():
     col = np.minimum(xc, N - rr)  # negative bound: N - rr = -1
     offsets = rs32(N, rr) + (col.astype(np.int64) & 0xFFFFFFFF)  # the column offset is unsigned
     assert (offsets >= tri_points(N)).any()
+
+
+# ---------------------------------------------------------------- slice runs
+# The 3D run kernel (seg3d, levels up to N = 128): a wave takes up to 4 x 64
+# consecutive points of one slice; each lane decodes its (x, y) and forms its
+# 15 neighbour indices from its own index, relative to the first point of
+# slice z - 1 (slice 0 at z = 0), clamped into the three slices around z
+# unless 1 <= z <= N - 2.
+OFF3 = [(0, 0, -1), (1, 0, -1), (0, 1, -1), (-1, 1, -1), (0, -1, 0), (1, -1, 0), (-1, 0, 0), (0, 0, 0),
+        (1, 0, 0), (-1, 1, 0), (0, 1, 0), (0, -1, 1), (1, -1, 1), (-1, 0, 1), (0, 0, 1)]
+
+
+def seg_xy(S, r, ulp=0):
+    """The kernel's decode, in FP32.  numpy's float32 root is correctly
+    rounded; the hardware root may be one ulp off, which ulp = -1 / +1
+    replays."""
+    b = np.float32(2 * S + 3)
+    disc = (b * b - np.float32(8) * r.astype(np.float32)).astype(np.float32)
+    root = np.sqrt(disc)
+    if ulp:
+        root = np.nextafter(root, np.float32(np.inf if ulp > 0 else -np.inf)).astype(np.float32)
+    yy = ((b - root) * np.float32(0.5)).astype(np.int64)
+    yy = np.clip(yy, 0, S)
+    yy = np.where(rs32(S, yy) > r, yy - 1, yy)
+    up = (yy < S) & (rs32(S, np.minimum(yy + 1, S)) <= r)
+    yy = np.where(up, yy + 1, yy)
+    return r - rs32(S, yy), yy
+
+
+def seg_indices(N, z, r):
+    """Neighbour indices (relative to the anchor slice) of slice-local points r."""
+    S = N - z
+    Ts = (S + 1) * (S + 2) // 2
+    Tb = (S + 2) * (S + 3) // 2 if z > 0 else 0
+    za = max(z - 1, 0)
+    hi = min(tet_count(N + 1) - slice_base(N, za) - 1, Tb + 2 * Ts)
+    x, y = seg_xy(S, r)
+    d = S + 1 - y
+    p = Tb + r
+    pu = p + Ts - y
+    pd = r + y
+    idx = np.stack([pd, pd + 1, pd + d + 1, pd + d, p - d - 1, p - d, p - 1, p, p + 1, p + d - 1, p + d,
+                    pu - d, pu - d + 1, pu - 1, pu])
+    if not (1 <= z <= N - 2):
+        idx = np.clip(idx, 0, hi)
+    return x, y, idx, slice_base(N, za)
+
+
+def check_runs(N):
+    P = tet_count(N + 1)
+    for z in range(N + 1):
+        S = N - z
+        Ts = (S + 1) * (S + 2) // 2
+        r = np.arange(Ts, dtype=np.int64)
+        x, y, idx, a = seg_indices(N, z, r)
+        assert (x >= 0).all() and (x + y <= S).all()
+        assert np.array_equal(rs32(S, y) + x, r), (N, z)  # the decode is exact
+        for u in (-1, 1):
+            xu, yu = seg_xy(S, r, u)
+            assert np.array_equal(xu, x) and np.array_equal(yu, y), (N, z, u)
+        absidx = a + idx
+        assert (absidx >= 0).all() and (absidx < P).all(), (N, z)
+        assert (idx >= 0).all() and (idx.astype(np.int64) * 8 < 2 ** 32).all()  # unsigned 32-bit byte offsets
+        for o, (dx, dy, dz) in enumerate(OFF3):
+            nx, ny, nz = x + dx, y + dy, z + dz
+            ins = (nx >= 0) & (ny >= 0) & (nz >= 0) & (nx + ny + nz <= N)
+            want = slice_base(N, nz) + rs32(N - nz, ny[ins]) + nx[ins] if nz <= N else None
+            if ins.any():
+                assert np.array_equal(absidx[o][ins], want), (N, z, o)
+    return True
+
+
+@pytest.mark.parametrize("L", range(1, 9))
+def test_3d_runs_every_point_small_levels(L):
+    """Every point of every slice: the decode is exact, every neighbour
+    inside the macro gets its storage index, every index stays inside the
+    macro's storage, byte offsets fit 32 bits."""
+    assert check_runs(1 << L)
+
+
+def test_3d_runs_level_11_edge_slices():
+    """Level 11 (N = 2048, the largest supported 3D level): the slices where
+    the clamps act and a few in between, every point."""
+    N = 1 << 11
+    P = tet_count(N + 1)
+    for z in [0, 1, 2, 3, 1024, N - 3, N - 2, N - 1, N]:
+        S = N - z
+        Ts = (S + 1) * (S + 2) // 2
+        r = np.arange(Ts, dtype=np.int64)
+        x, y, idx, a = seg_indices(N, z, r)
+        assert np.array_equal(rs32(S, y) + x, r)
+        for u in (-1, 1):
+            xu, yu = seg_xy(S, r, u)
+            assert np.array_equal(xu, x) and np.array_equal(yu, y), (z, u)
+        assert ((a + idx) >= 0).all() and ((a + idx) < P).all()
+        assert (idx >= 0).all() and (idx * 8 < 2 ** 32).all()
