@@ -173,6 +173,21 @@ __device__ __forceinline__ MacroC load_macro(const MacroDev* md, int m) {
 #endif
 }
 
+// Storage offsets of the 15 stencil neighbours of a 3D point (x, y, z),
+// relative to the point, in stencil-table order; exact for neighbours inside
+// the macro.  Slice z has side S = N - z and row y of it d = S + 1 - y
+// points: rows y +- 1 start d after / end d + 1 before the point's column,
+// and (x, y, z + 1) / (x, y, z - 1) lie T(S) - y after / T(S + 1) - y
+// before it (T(s) = (s + 1)(s + 2) / 2 points in a slice of side s).
+__device__ __forceinline__ void nbr_offsets3(int N, int y, int z, int (&o)[15]) {
+  const int S = N - z, d = S + 1 - y;
+  const int up = (S + 1) * (S + 2) / 2 - y;
+  const int dn = y - (S + 2) * (S + 3) / 2;
+  const int t[15] = {dn, dn + 1, dn + d + 1, dn + d, -d - 1, -d, -1, 0, 1, d - 1, d, up - d, up - d + 1, up - 1, up};
+#pragma unroll
+  for (int k = 0; k < 15; ++k) o[k] = t[k];
+}
+
 template <typename T, int DIM>
 __device__ __forceinline__ void restrict_point(const TransferArgs<T>& a, int macro, int x, int y, int z) {
   constexpr StencilTable ST = stencil_table(DIM);
@@ -181,6 +196,13 @@ __device__ __forceinline__ void restrict_point(const TransferArgs<T>& a, int mac
   const MacroC F = load_macro(a.mdf, macro);
   const int Nc = C.N, Nf = F.N;
   const bool live = x + y + z <= Nc;
+  // 3D: the fine neighbours' indices as offsets from that of 2P
+  int off[15];
+  int64_t fc = 0;
+  if constexpr (DIM == 3) {
+    nbr_offsets3(Nf, live ? 2 * y : 0, 2 * z, off);
+    fc = live ? lidx<3>(Nf, 2 * x, 2 * y, 2 * z) : 0;
+  }
   // branch-free: every lane takes all offsets; fine points outside the macro
   // read the centre instead and contribute nothing
   T acc = T(0);
@@ -192,7 +214,7 @@ __device__ __forceinline__ void restrict_point(const TransferArgs<T>& a, int mac
     const bool owned = mask == full || ((F.own_mask >> mask) & 1);
     const bool dir = mask != full && ((F.dir_mask >> mask) & 1);
     const bool use = in && owned && !dir;
-    const int64_t i = in ? lidx<DIM>(Nf, fx, fy, fz) : 0;
+    const int64_t i = in ? (DIM == 3 ? fc + off[s] : lidx<DIM>(Nf, fx, fy, fz)) : 0;
     const T r = a.src[F.base + i];
     const T w = s == ST.centre ? T(1) : T(0.5);
     acc += use ? w * r : T(0);

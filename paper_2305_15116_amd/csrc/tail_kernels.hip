@@ -60,12 +60,17 @@ __device__ __forceinline__ void for_points(int N, int nmac, Fn&& fn) {
         ++z;
       }
     }
-    int y = 0;
-    for (int len = S + 1; r >= len; --len) {  // row y of the slice holds S + 1 - y points
-      r -= len;
-      ++y;
+    int x, y = 0;
+    if (DIM == 3) {
+      slice_xy3(S, r, x, y);
+    } else {
+      for (int len = S + 1; r >= len; --len) {  // row y of the slice holds S + 1 - y points
+        r -= len;
+        ++y;
+      }
+      x = r;
     }
-    fn(m, r, y, z);
+    fn(m, x, y, z);
   }
 }
 
@@ -78,6 +83,8 @@ __device__ __forceinline__ void tail_stencil(const TailLevel<T>& F, const T* X, 
     const MacroDev& M = F.md[m];
     const int N = F.N;
     const int64_t i = M.base + lidx<DIM>(N, x, y, z);
+    int off[15];
+    if constexpr (DIM == 3) nbr_offsets3(N, y, z, off);
     T v[ST.n];
 #pragma unroll
     for (int o = 0; o < ST.n; ++o) {
@@ -85,7 +92,7 @@ __device__ __forceinline__ void tail_stencil(const TailLevel<T>& F, const T* X, 
       const bool in = nx >= 0 && ny >= 0 && nz >= 0 && nx + ny + nz <= N;
       // neighbours outside the macro read the point itself (a valid index);
       // partial_sum drops them
-      v[o] = X[in ? M.base + lidx<DIM>(N, nx, ny, nz) : i];
+      v[o] = X[in ? (DIM == 3 ? i + off[o] : M.base + lidx<DIM>(N, nx, ny, nz)) : i];
     }
     const int mask = support_mask(DIM, N, x, y, z);
     const WTab<T> W = wtab_of<T>(M);

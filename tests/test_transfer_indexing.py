@@ -168,3 +168,31 @@ def test_replay_catches_a_wrong_slice_offset():
     c = tb + rs(S, 2 * y) + 2 * x
     dn_wrong = c - tb + 2 * y - 1
     assert not np.array_equal(slice_base(Nf, 2 * z - 1) + dn_wrong, idx3(Nf, 2 * x, 2 * y, 2 * z - 1))
+
+
+def nbr_offsets3(N, y, z):
+    """nbr_offsets3 (rows.hpp): the 15 neighbours' storage offsets relative
+    to the point, used by the V-cycle tail's stencil rows and the point
+    form of the restriction."""
+    S = N - z
+    d = S + 1 - y
+    up = (S + 1) * (S + 2) // 2 - y
+    dn = y - (S + 2) * (S + 3) // 2
+    return [dn, dn + 1, dn + d + 1, dn + d, -d - 1, -d, -1, 0 * d, 1 + 0 * d, d - 1, d, up - d, up - d + 1, up - 1,
+            up]
+
+
+@pytest.mark.parametrize("L", range(0, 7))
+def test_3d_neighbour_offsets_every_point(L):
+    N = 1 << L
+    for z in range(N + 1):
+        S = N - z
+        r = np.arange((S + 1) * (S + 2) // 2, dtype=np.int64)
+        x, y = decode(S, r)
+        i = idx3(N, x, y, z)
+        off = nbr_offsets3(N, y, z)
+        for o, (dx, dy, dz) in enumerate(OFF3):
+            nx, ny, nz = x + dx, y + dy, z + dz
+            k = (nx >= 0) & (ny >= 0) & (nz >= 0) & (nx + ny + nz <= N)
+            if k.any():
+                assert np.array_equal((i + off[o])[k], idx3(N, nx[k], ny[k], np.full(k.sum(), nz))), (N, z, o)
