@@ -139,7 +139,7 @@ void stencil_pass(PlanBuilder& P, const std::vector<Member*>& ms, int dim, int d
     const Level& L = lev(*M, p.level);
     const StencilArgs<T> a = stencil_args<T>(L, p.x, p.y, p.b, omega, p.part);
     sa[dim == 3 && L.pen_z == kPenSeg ? 1 : 0].push_back({a, a.nwg});
-    ga.push_back({exchange_args<T>(L, p.x, p.y, p.b, omega, p.part), exchange_blocks(L)});
+    if (!exchange_in_launch(L)) ga.push_back({exchange_args<T>(L, p.x, p.y, p.b, omega, p.part), exchange_blocks(L)});
   }
   P.add(kOpStencil, dtype, dim, mode, sa[0], kPenZ);
   P.add(kOpStencil, dtype, dim, mode, sa[1], kPenSeg);

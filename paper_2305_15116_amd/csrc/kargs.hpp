@@ -49,6 +49,12 @@ struct StencilArgs {
   T omega;
   double* part;  // sums at [0, np), maxima at [np, 2 np)
   int np;
+  // exchange list, read by group tiles (levels whose launch finishes shared DoFs)
+  const int32_t* xptr;
+  const Copy* xcopies;
+  const int64_t* xcidx;
+  const double* xinv;
+  const float* xinvf;
 };
 
 // exchange_kernel / iface_kernel: groups of copies of macro-boundary DoFs.
@@ -238,6 +244,11 @@ StencilArgs<T> stencil_args(const Level& L, const void* x, void* y, const void* 
   a.omega = (T)omega;
   a.part = part;
   a.np = (int)L.n_partials(dt);
+  a.xptr = L.dev.xgrp_ptr;
+  a.xcopies = L.dev.xcopies;
+  a.xcidx = L.dev.xcpidx;
+  a.xinv = L.dev.xgrp_invdiag;
+  a.xinvf = L.dev.xgrp_invdiagf;
   return a;
 }
 
@@ -261,6 +272,8 @@ GroupArgs<T> exchange_args(const Level& L, const void* x, void* y, const void* b
   return g;
 }
 inline int exchange_blocks(const Level& L) { return (int)L.xgroup_blocks(); }
+// stencil passes of levels whose launch finishes shared DoFs need no exchange launch
+inline bool exchange_in_launch(const Level& L) { return L.pen_z == kPenSeg; }
 
 template <typename T>
 GroupArgs<T> iface_args(const Level& L, const void* x, void* y, const void* b) {

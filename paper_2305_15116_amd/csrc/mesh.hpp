@@ -77,7 +77,10 @@ struct Level {
     return dtype == MF_F32 && !tiles_f32.empty() ? tiles_f32 : tiles;
   }
   // norm / dot partials of one stencil pass: one per workgroup of tiles, then one per exchange block
-  int64_t n_partials(int dtype) const { return (int64_t)tiles_for(dtype).size() / kWavesPerWG + xgroup_blocks(); }
+  // (3D levels of slice runs finish shared DoFs in the stencil launch: no exchange partials)
+  int64_t n_partials(int dtype) const {
+    return (int64_t)tiles_for(dtype).size() / kWavesPerWG + (pen_z == kPenSeg ? 0 : xgroup_blocks());
+  }
   int64_t n_partials() const { return std::max(n_partials(MF_F64), n_partials(MF_F32)); }  // buffer sizes
   // blocks of the linear (grid-stride) vector kernels with partials
   int64_t lin_blocks() const { return std::min<int64_t>(2048, std::max<int64_t>(1, (storage + 1023) / 1024)); }

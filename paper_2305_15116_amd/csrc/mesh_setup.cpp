@@ -485,6 +485,27 @@ static int build_level(mf_mesh* m, int level, Level& L) {
     }
   }
   while (L.tiles.size() % kWavesPerWG) L.tiles.push_back({-1, 0, 0, 0});
+  if (L.pen_z == kPenSeg) {
+    // group tiles: the shared DoFs, finished in the same launch.  Their
+    // workgroups are spread evenly among the runs' (each XCD takes a
+    // contiguous chunk of workgroups, so appended ones would all land on one)
+    std::vector<Tile> grp;
+    const int64_t ng = L.nxgroups();
+    for (int64_t g0 = 0; g0 < ng; g0 += kWave)
+      grp.push_back({kGroupTile, (int32_t)g0, (int32_t)std::min<int64_t>(kWave, ng - g0), 0});
+    while (grp.size() % kWavesPerWG) grp.push_back({-1, 0, 0, 0});
+    const size_t nr = L.tiles.size() / kWavesPerWG, ngw = grp.size() / kWavesPerWG;
+    std::vector<Tile> all;
+    all.reserve(L.tiles.size() + grp.size());
+    size_t ir = 0, ig = 0;
+    while (ir < nr || ig < ngw) {
+      // next: a group workgroup while the groups lag the runs proportionally
+      const bool take_g = ig < ngw && (ir == nr || ig * nr <= ir * ngw);
+      const Tile* src = take_g ? &grp[ig++ * kWavesPerWG] : &L.tiles[ir++ * kWavesPerWG];
+      all.insert(all.end(), src, src + kWavesPerWG);
+    }
+    L.tiles.swap(all);
+  }
   L.tiles_f32.clear();
   if (dim == 2) {
     for (int64_t c = 0; c < m->nc; ++c)

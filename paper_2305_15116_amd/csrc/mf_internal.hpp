@@ -56,6 +56,12 @@ constexpr int kSegUpToN = MF_SEG3D_UPTO_N;  // runs of slice segments when N <= 
 constexpr int kSegRun = 4;
 // segments per run at side N: fewer on the smallest levels, for more waves
 MF_HD constexpr int seg_run(int N) { return N >= 128 ? 4 : (N >= 64 ? 2 : 1); }
+// On such levels the stencil launch also finishes the shared DoFs: after the
+// runs, the tile list holds group tiles (macro = kGroupTile, x0 = first
+// exchange group, y0 = groups, at most 64), whose lanes compute each shared
+// DoF's whole row from its copies' partial stencils, so no exchange launch
+// follows.
+constexpr int kGroupTile = -2;
 #ifndef MF_WAVES_PER_WG
 #define MF_WAVES_PER_WG 4
 #endif
@@ -67,7 +73,8 @@ constexpr int kXCD = 8;        // MI355X: 8 accelerator complex dies, workgroups
 // A wave tile: columns [x0, x0+62) of rows [y0, y0+H) of `macro` (2D), or of
 // rows [y0, y0+kPenR) in slices [z, z+kPenZ) (3D).  For per-point kernels the same record names a row segment
 // of 64 points starting at x0 of row y0 in slice z; in the tile list of a kPenSeg level, y0 points of slice z
-// from slice-local index x0 (a run of at most kSegRun segments).  macro < 0: padding.
+// from slice-local index x0 (a run of at most kSegRun segments), then group tiles (kGroupTile).  macro = -1:
+// padding.
 struct Tile {
   int32_t macro, x0, y0, z;
 };

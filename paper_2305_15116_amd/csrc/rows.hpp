@@ -75,9 +75,11 @@ __device__ __forceinline__ void accum(double& ss, double& mx, T out, T xc) {
 // Finish the row of one point.  acc is its (partial) stencil value, xc and bv
 // its x and b entries.  Interior points, Dirichlet points (identity rows) and
 // points no other macro shares are finished here; shared non-Dirichlet points
-// get their partial row for the exchange.  Norm partials count each unique
-// DoF once (Dirichlet DoFs on shared primitives only in their owner).
-template <typename T, int DIM, int MODE>
+// get their partial row for the exchange (KEEP_SHARED), or nothing where the
+// same launch computes their whole rows (group_rows3).  Norm partials count
+// each unique DoF once (Dirichlet DoFs on shared primitives only in their
+// owner).
+template <typename T, int DIM, int MODE, bool KEEP_SHARED = true>
 __device__ __forceinline__ void finish(const MacroDev& M, const WTab<T> W, int mask, T acc, T xc, T bv, T omega,
                                        T* yp, double& ss, double& mx) {
   constexpr int FM = full_mask(DIM);
@@ -97,7 +99,7 @@ __device__ __forceinline__ void finish(const MacroDev& M, const WTab<T> W, int m
     else out = bv;
     if (MODE != kNormB) st(yp, out);
     accum<T, MODE>(ss, mx, out, xc);
-  } else if (MODE != kNormB) {
+  } else if (MODE != kNormB && KEEP_SHARED) {
     st(yp, acc);
   }
 }

@@ -127,7 +127,7 @@ __device__ __forceinline__ T group_sum(const WTab<T> W, const T* v) {
 // their x = 0 lane (only in tiles starting at x0 = 0, tile_left) and their
 // far-face lane branch-free, with the uniform partial stencils above;
 // Jacobi needs bid = 1 / centre weight of the L, F and LF masks.
-template <typename T, int DIM, int MODE>
+template <typename T, int DIM, int MODE, bool KEEP_SHARED = true>
 __device__ __forceinline__ void point_row(const MacroDev& M, const WTab<T> W, const T* wi, bool inside, int N, int x,
                                           int y, int z, const T* v, T xc, T bv, T omega, T* yp, double& ss,
                                           double& mx, bool may_face, bool tile_left, const T* bid) {
@@ -142,7 +142,7 @@ __device__ __forceinline__ void point_row(const MacroDev& M, const WTab<T> W, co
     if (__builtin_amdgcn_ballot_w64(inside)) {
       const int mask = support_mask(DIM, N, x, y, z);
       acc = partial_sum<T, DIM>(W, inside ? mask : FM, N, x, y, z, v);
-      if (inside) finish<T, DIM, MODE>(M, W, mask, acc, xc, bv, omega, yp, ss, mx);
+      if (inside) finish<T, DIM, MODE, KEEP_SHARED>(M, W, mask, acc, xc, bv, omega, yp, ss, mx);
     }
     return;
   }
@@ -184,7 +184,7 @@ __device__ __forceinline__ void point_row(const MacroDev& M, const WTab<T> W, co
     out = bv;
   }
   if (inside) {
-    if (MODE != kNormB) st(yp, out);
+    if (MODE != kNormB && (KEEP_SHARED || !shared)) st(yp, out);
     if (dir ? own : !shared) accum<T, MODE>(ss, mx, out, xc);
   }
 }
@@ -500,8 +500,55 @@ __device__ __forceinline__ void seg3d(const Tile& t, const MacroDev& M, WTab<T> 
                      ld(p - d),      ld(p - 1),      ld(p),          ld(p + 1),  ld(p + d - 1),
                      ld(p + d),      ld(pu - d),     ld(pu - d + 1), ld(pu - 1), ld(pu)};
     const T bv = MODE != kApply ? B[ab + p] : T(0);
-    point_row<T, 3, MODE>(M, W, wi, live, N, x, y, z, v, v[7], bv, omega, Y + ab + p, ss, mx, true, true, bid);
+    point_row<T, 3, MODE, false>(M, W, wi, live, N, x, y, z, v, v[7], bv, omega, Y + ab + p, ss, mx, true, true, bid);
   }
+}
+
+// A group tile of a slice-run level: lane i finishes shared DoF t.x0 + i of
+// the exchange list.  Each copy's partial row is formed as the walk forms it
+// at a boundary point (the partial stencil of the copy's support mask in its
+// own macro, neighbours outside that macro dropped, table order), the copies
+// are summed in the list's fixed macro order and the row is finished as the
+// exchange kernel finishes it, so the values are those of the run and
+// exchange launches; the runs leave these DoFs alone (point_row with
+// KEEP_SHARED = false).
+template <typename T, int MODE>
+__device__ __forceinline__ void group_rows3(const StencilArgs<T>& a, const Tile& t, double& ss, double& mx) {
+  constexpr StencilTable ST = stencil_table(3);
+  const int lane = threadIdx.x & (kWave - 1);
+  if (lane >= t.y0) return;
+  const int g = t.x0 + lane;
+  const int c0 = a.xptr[g], c1 = a.xptr[g + 1];
+  const int64_t i0 = a.xcidx[c0];
+  T out;
+  if (MODE == kNormB) {
+    out = a.B[i0];
+  } else {
+    T acc = T(0);
+    for (int c = c0; c < c1; ++c) {
+      const Copy k = a.xcopies[c];
+      const MacroDev& M = a.md[k.macro];
+      const int N = M.N;
+      const int64_t i = a.xcidx[c];
+      int off[15];
+      nbr_offsets3(N, k.y, k.z, off);
+      const int mask = support_mask(3, N, k.x, k.y, k.z);
+      T p = T(0);
+#pragma unroll
+      for (int o = 0; o < ST.n; ++o) {
+        const int nx = k.x + ST.off[o][0], ny = k.y + ST.off[o][1], nz = k.z + ST.off[o][2];
+        const bool in = nx >= 0 && ny >= 0 && nz >= 0 && nx + ny + nz <= N;
+        const T v = a.X[in ? i + off[o] : i];
+        p = fma(Prec<T>::w(M, mask, o), in ? v : T(0), p);
+      }
+      acc += p;
+    }
+    if (MODE == kApply || MODE == kApplyDot) out = acc;
+    else if (MODE == kJacobi) out = fma(a.omega * Prec<T>::ginv(a.xinv, a.xinvf, g), a.B[i0] - acc, a.X[i0]);
+    else out = a.B[i0] - acc;
+    for (int c = c0; c < c1; ++c) a.Y[a.xcidx[c]] = out;
+  }
+  accum<T, MODE>(ss, mx, out, MODE == kApplyDot ? a.X[i0] : T(0));
 }
 
 // Whether a wave tile has output points on its macro's boundary (x = 0,
@@ -558,6 +605,8 @@ __global__ __launch_bounds__(kWG) void stencil_kernel(const Launch<StencilArgs<T
       seg3d<T, MODE>(t, M, W, a.X, a.Y, a.B, a.omega, ss, mx);
     else
       pencil3d<T, MODE, PZ>(t.x0, t.y0, t.z, M, W, a.X, a.Y, a.B, a.omega, ss, mx);
+  } else if (DIM == 3 && PZ == kPenSeg && t.macro == kGroupTile) {
+    group_rows3<T, MODE>(a, t, ss, mx);
   }
   if (kPart && a.part != nullptr) {
     // one partial per workgroup: its four waves summed in a fixed order
@@ -723,7 +772,7 @@ void run_stencil(const Level& L, const void* x, void* y, const void* b, double o
                          single(a, a.nwg));
     }
   }
-  const int nblk = exchange_blocks(L);
+  const int nblk = exchange_in_launch(L) ? 0 : exchange_blocks(L);
   if (nblk == 0) return;
   hipLaunchKernelGGL((exchange_kernel<T, DIM, MODE>), dim3(nblk), dim3(kIfaceWG), 0, s,
                      single(exchange_args<T>(L, x, y, b, omega, part), nblk));
