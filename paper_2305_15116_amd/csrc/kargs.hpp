@@ -273,7 +273,7 @@ GroupArgs<T> exchange_args(const Level& L, const void* x, void* y, const void* b
 }
 inline int exchange_blocks(const Level& L) { return (int)L.xgroup_blocks(); }
 // stencil passes of levels whose launch finishes shared DoFs need no exchange launch
-inline bool exchange_in_launch(const Level& L) { return L.pen_z == kPenSeg; }
+inline bool exchange_in_launch(const Level& L) { return L.xfused; }
 
 template <typename T>
 GroupArgs<T> iface_args(const Level& L, const void* x, void* y, const void* b) {

@@ -50,6 +50,7 @@ struct Level {
   int level = 0;
   int N = 0;
   int pen_z = 0;  // 3D tile shape: pencils of kPenZ slices, or runs of slice segments (kPenSeg)
+  bool xfused = false;  // the stencil launch finishes shared DoFs (group tiles; slice-run levels): no exchange launch
   int64_t storage = 0, unique = 0;
   std::vector<int64_t> base;    // per macro storage offset
   std::vector<MacroDev> md;
@@ -77,9 +78,9 @@ struct Level {
     return dtype == MF_F32 && !tiles_f32.empty() ? tiles_f32 : tiles;
   }
   // norm / dot partials of one stencil pass: one per workgroup of tiles, then one per exchange block
-  // (3D levels of slice runs finish shared DoFs in the stencil launch: no exchange partials)
+  // (levels whose stencil launch finishes shared DoFs have no exchange partials)
   int64_t n_partials(int dtype) const {
-    return (int64_t)tiles_for(dtype).size() / kWavesPerWG + (pen_z == kPenSeg ? 0 : xgroup_blocks());
+    return (int64_t)tiles_for(dtype).size() / kWavesPerWG + (xfused ? 0 : xgroup_blocks());
   }
   int64_t n_partials() const { return std::max(n_partials(MF_F64), n_partials(MF_F32)); }  // buffer sizes
   // blocks of the linear (grid-stride) vector kernels with partials

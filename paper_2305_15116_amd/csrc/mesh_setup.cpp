@@ -485,7 +485,10 @@ static int build_level(mf_mesh* m, int level, Level& L) {
     }
   }
   while (L.tiles.size() % kWavesPerWG) L.tiles.push_back({-1, 0, 0, 0});
-  if (L.pen_z == kPenSeg) {
+  // (measured: on pencil levels the group work lengthens the launch more than
+  // the exchange launch costs, cube level 8 FP64 apply 96 -> 109 us)
+  L.xfused = L.pen_z == kPenSeg && dim == 3;
+  if (L.xfused) {
     // group tiles: the shared DoFs, finished in the same launch.  Their
     // workgroups are spread evenly among the runs' (each XCD takes a
     // contiguous chunk of workgroups, so appended ones would all land on one)

@@ -56,11 +56,11 @@ constexpr int kSegUpToN = MF_SEG3D_UPTO_N;  // runs of slice segments when N <= 
 constexpr int kSegRun = 4;
 // segments per run at side N: fewer on the smallest levels, for more waves
 MF_HD constexpr int seg_run(int N) { return N >= 128 ? 4 : (N >= 64 ? 2 : 1); }
-// On such levels the stencil launch also finishes the shared DoFs: after the
-// runs, the tile list holds group tiles (macro = kGroupTile, x0 = first
-// exchange group, y0 = groups, at most 64), whose lanes compute each shared
-// DoF's whole row from its copies' partial stencils, so no exchange launch
-// follows.
+// On slice-run levels the stencil launch also finishes the shared DoFs: among
+// the runs, the tile list holds group tiles (macro = kGroupTile,
+// x0 = first exchange group, y0 = groups, at most 64), whose lanes compute
+// each shared DoF's whole row from its copies' partial stencils, so no
+// exchange launch follows.
 constexpr int kGroupTile = -2;
 #ifndef MF_WAVES_PER_WG
 #define MF_WAVES_PER_WG 4
