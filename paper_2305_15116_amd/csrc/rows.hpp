@@ -67,8 +67,7 @@ __device__ __forceinline__ void accum(double& ss, double& mx, T out, T xc) {
     ss += (double)out * (double)out;
     mx = fmax(mx, fabs((double)out));
   } else if (MODE == kApplyDot) {
-    ss += (double)xc * (double)out;
-    mx = fmax(mx, fabs((double)out));
+    ss += (double)xc * (double)out;  // (no maximum: only the dot product is used)
   }
 }
 
