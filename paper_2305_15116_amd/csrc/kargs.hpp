@@ -127,7 +127,7 @@ struct Jacobi0Args {
   T* Y;
   T omega;
 };
-constexpr int kJ0Points = 2048;  // points per block of the streaming pass
+constexpr int kJ0Points = 2048;  // points per block of the streaming pass (a multiple of the block size)
 
 // vcycle_tail_kernel: the bottom of a V-cycle — the coarse solve and up to
 // kTailLevels - 1 levels above it, each of at most kTailMaxPoints storage

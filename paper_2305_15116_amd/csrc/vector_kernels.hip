@@ -160,7 +160,19 @@ __global__ __launch_bounds__(kWG) void jacobi0_stream_kernel(const Launch<Jacobi
   const T c = a.omega * Prec<T>::invd(M);
   const T* __restrict__ B = a.B + M.base;
   T* __restrict__ Y = a.Y + M.base;
-  for (int64_t i = begin + threadIdx.x; i < end; i += kWG) Y[i] = fma(c, B[i], T(0));
+  // all of a thread's loads first, then the stores
+  constexpr int kPer = kJ0Points / kWG;
+  T v[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int64_t i = begin + threadIdx.x + (int64_t)k * kWG;
+    v[k] = i < end ? B[i] : T(0);
+  }
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int64_t i = begin + threadIdx.x + (int64_t)k * kWG;
+    if (i < end) Y[i] = fma(c, v[k], T(0));
+  }
 }
 
 // Pass 2: the macro-boundary DoFs, as jacobi0_point and jacobi0_group finish
