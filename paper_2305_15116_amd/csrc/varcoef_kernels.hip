@@ -215,30 +215,33 @@ __device__ __forceinline__ void vc3_point(const MacroDev& M, const T* __restrict
   constexpr ElemTable E = elem_table(3);
   const int N = M.N;
   const int S = N - z;
-  // slice bases of z - 1, z, z + 1 (clamped into the macro; only read for
-  // neighbours inside it)
-  const int64_t bz = slice_base(N, z);
-  const int64_t bm = z > 0 ? slice_base(N, z - 1) : bz;
-  const int64_t bp = z < N ? slice_base(N, z + 1) : bz;
-  const int64_t ic = M.base + bz + row_start(S, y) + x;
+  // neighbours by offsets from the point's index, all taken relative to the
+  // first point of slice z - 1 (slice 0 at z = 0) as 32-bit offsets
+  const int za = z > 0 ? z - 1 : 0;
+  const int64_t ab = M.base + slice_base(N, za);
+  const int c = (z > 0 ? (S + 2) * (S + 3) / 2 : 0) + row_start(S, y) + x;
+  int off[15];
+  nbr_offsets3(N, y, z, off);
+  const T* __restrict__ Ka = K + ab;
+  const T* __restrict__ Xa = X + ab;
   T kv[ST.n], xv[ST.n];
 #pragma unroll
   for (int o = 0; o < ST.n; ++o) {
     const int nx = x + ST.off[o][0], ny = y + ST.off[o][1], nz = z + ST.off[o][2];
     const bool in = nx >= 0 && ny >= 0 && nz >= 0 && nx + ny + nz <= N;
-    const int dz = ST.off[o][2];
-    const int64_t sb = dz < 0 ? bm : (dz > 0 ? bp : bz);
-    const int Sn = S - dz;
     // neighbours outside the macro read the point itself; no tet uses them
-    const int64_t i = in ? M.base + sb + row_start(Sn, ny) + nx : ic;
-    kv[o] = K[i];
-    xv[o] = X[i];
+    const unsigned byte = (unsigned)(in ? c + off[o] : c) * (unsigned)sizeof(T);
+    kv[o] = *(const T*)((const char*)Ka + byte);
+    xv[o] = *(const T*)((const char*)Xa + byte);
   }
   const int mask = support_mask(3, N, x, y, z);
   if (mask != full_mask(3) && ((M.dir_mask >> mask) & 1)) {
-    Y[ic] = xv[ST.centre];  // identity row
+    Y[ab + c] = xv[ST.centre];  // identity row
     return;
   }
+  // the sums of the four vertex coefficients are used unscaled and the row
+  // scaled by 1/4 once at the end: scaling by powers of two is exact, so this
+  // equals summing mean_T(k) times the element rows
   T acc = T(0);
 #pragma unroll
   for (int t = 0; t < E.ntypes; ++t) {
@@ -247,18 +250,18 @@ __device__ __forceinline__ void vc3_point(const MacroDev& M, const T* __restrict
       const int ax = x - E.off[t][v][0], ay = y - E.off[t][v][1], az = z - E.off[t][v][2];
       const bool exists = ax >= 0 && ay >= 0 && az >= 0 && ax + ay + az <= N - E.slack[t];
       const int s0 = tet_slot(t, v, 0), s1 = tet_slot(t, v, 1), s2 = tet_slot(t, v, 2), s3 = tet_slot(t, v, 3);
-      const T km = (kv[s0] + kv[s1] + kv[s2] + kv[s3]) * T(0.25);
+      const T ks = kv[s0] + kv[s1] + kv[s2] + kv[s3];
       const double* Kt = M.K[t] + 4 * v;
       T r = T(Kt[0]) * xv[s0];
       r = fma(T(Kt[1]), xv[s1], r);
       r = fma(T(Kt[2]), xv[s2], r);
       r = fma(T(Kt[3]), xv[s3], r);
-      acc = exists ? fma(km, r, acc) : acc;
+      acc = exists ? fma(ks, r, acc) : acc;
     }
   }
   // interior, unshared and shared points alike store their (partial) row;
   // the exchange kernel completes shared DoFs
-  Y[ic] = acc;
+  Y[ab + c] = acc * T(0.25);
 }
 
 template <typename T>
