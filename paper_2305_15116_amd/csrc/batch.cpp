@@ -256,11 +256,13 @@ void coarse_op(PlanBuilder& P, const std::vector<Member*>& ms, int dim, int dtyp
 template <typename T>
 void tail_op(PlanBuilder& P, const std::vector<Member*>& ms, int dim, const mf_solve_opts& o) {
   std::vector<std::pair<TailArgs<T>, int>> ta;
+  int lds = 0;  // dynamic LDS of the launch: the largest member's
   for (Member* M : ms) {
     if (M->m->dim != dim || M->tail == 0) continue;
     ta.push_back({tail_args<T>(M->m, M->lc, M->tail, o.pre, o.post, o.omega, M->w.b, M->w.x, M->w.t), 1});
+    lds = std::max(lds, ta.back().first.lds);
   }
-  P.add(kOpTail, dtype_of<T>(), dim, 0, ta);
+  P.add(kOpTail, dtype_of<T>(), dim, 0, ta, lds);
 }
 
 void reduce_op(PlanBuilder& P, const std::vector<std::pair<ReduceArgs, int>>& ra) { P.add(kOpReduce, MF_F64, 0, 0, ra); }

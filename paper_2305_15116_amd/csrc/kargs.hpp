@@ -175,7 +175,13 @@ struct TailArgs {
   T omega;
   CoarseArgs<T> coarse;
   TailLevel<T> lv[kTailLevels];
+  int lds;  // bytes of LDS holding the levels' b, x and t (0: they stay in global memory)
 };
+
+// The tail keeps its levels' vectors in LDS when they fit in kTailLdsMax
+// bytes: three per level (b, x, t), each rounded up to 16 bytes.
+constexpr int kTailLdsMax = 64 * 1024;
+MF_HD constexpr int64_t tail_lds_vec(int64_t storage, int elem) { return (storage * elem + 15) / 16 * 16; }
 
 // Plain vector kernels (fill, copy, axpy and the FP32 <-> FP64 pair of the
 // mixed solver, whose scale comes from a device norm result).
@@ -425,7 +431,7 @@ struct BatchOp {
   int kind, dtype, dim, mode;
   int nseg, nwg;
   int64_t args_off, wg0_off;
-  int variant;  // stencil ops: 3D tile shape of the members' levels (kPenZ or kPenSeg)
+  int variant;  // stencil ops: 3D tile shape of the members' levels (kPenZ or kPenSeg); tail ops: dynamic LDS bytes
   int pad_;
 };
 

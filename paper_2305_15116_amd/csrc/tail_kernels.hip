@@ -195,15 +195,37 @@ __device__ __forceinline__ auto resolve_ref(const Launch<A>& L, int g) {
 
 template <typename T, int DIM>
 __global__ __launch_bounds__(kTailWG) void vcycle_tail_kernel(const Launch<TailArgs<T>> L) {
+  extern __shared__ __align__(16) unsigned char tail_lds[];
   const auto* a = resolve_ref(L, (int)blockIdx.x);
   const int nlev = a->nlev, pre = a->pre, post = a->post;
   const T omega = a->omega;
   const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   const int lane = (int)threadIdx.x & (kWave - 1);
+  // Level k's record; with a->lds its b, x and t live in LDS (the kernel's
+  // steps are chains of dependent loads, so their latency sets its time):
+  // only the top level's b comes in from global memory and its x goes out.
+  const bool lds = a->lds > 0;
+  auto lvl = [&](int k) {
+    TailLevel<T> v = a->lv[k];
+    if (lds) {
+      int64_t off = 0;
+      for (int j = 0; j < k; ++j) off += 3 * tail_lds_vec(a->lv[j].storage, (int)sizeof(T));
+      const int64_t sz = tail_lds_vec(v.storage, (int)sizeof(T));
+      v.b = (T*)(tail_lds + off);
+      v.x = (T*)(tail_lds + off + sz);
+      v.t = (T*)(tail_lds + off + 2 * sz);
+    }
+    return v;
+  };
+  if (lds) {
+    const TailLevel<T> G = a->lv[nlev - 1], S = lvl(nlev - 1);
+    for (int64_t i = threadIdx.x; i < G.storage; i += kTailWG) S.b[i] = G.b[i];
+    __syncthreads();
+  }
   // descent: levels lc + nlev - 1 .. lc + 1 (restriction: one coarse point per thread)
   for (int k = nlev - 1; k >= 1; --k) {
-    const TailLevel<T> F = a->lv[k];
-    const TailLevel<T> C = a->lv[k - 1];
+    const TailLevel<T> F = lvl(k);
+    const TailLevel<T> C = lvl(k - 1);
     tail_jacobi<T, DIM>(F, pre, omega, true);
     tail_pass<T, DIM, kResidual>(F, F.x, F.t, T(0));
     const TransferArgs<T> ta{nullptr, 0, 0, C.md, F.md, F.t, C.b};  // points come from for_points
@@ -223,7 +245,12 @@ __global__ __launch_bounds__(kTailWG) void vcycle_tail_kernel(const Launch<TailA
   }
   // coarse level: x = 0, then the dense solve on its unknowns (a wave each)
   {
-    const CoarseArgs<T> cs = a->coarse;
+    CoarseArgs<T> cs = a->coarse;
+    if (lds) {
+      const TailLevel<T> C0 = lvl(0);
+      cs.B = C0.b;
+      cs.X = C0.x;
+    }
     tail_fill(cs.X, a->lv[0].storage);
     __syncthreads();
     for (int i = wave; i < cs.n; i += kTailWaves) coarse_row<T>(cs, i, lane);
@@ -231,19 +258,23 @@ __global__ __launch_bounds__(kTailWG) void vcycle_tail_kernel(const Launch<TailA
   }
   // ascent: levels lc + 1 .. lc + nlev - 1
   for (int k = 1; k < nlev; ++k) {
-    const TailLevel<T> F = a->lv[k];
-    const TailLevel<T> C = a->lv[k - 1];
+    const TailLevel<T> F = lvl(k);
+    const TailLevel<T> C = lvl(k - 1);
     const TransferArgs<T> ta{nullptr, 0, 0, C.md, F.md, C.x, F.x};
     for_points<DIM>(F.N, F.nmac, [&](int m, int x, int y, int z) { prolong_point<T, DIM>(ta, m, x, y, z); });
     __syncthreads();
     tail_jacobi<T, DIM>(F, post, omega, false);
   }
+  if (lds) {
+    const TailLevel<T> G = a->lv[nlev - 1], S = lvl(nlev - 1);
+    for (int64_t i = threadIdx.x; i < G.storage; i += kTailWG) G.x[i] = S.x[i];
+  }
 }
 
 template <typename T>
-void run_tail(int dim, const Launch<TailArgs<T>>& l, hipStream_t s) {
-  if (dim == 2) hipLaunchKernelGGL((vcycle_tail_kernel<T, 2>), dim3(l.nwg), dim3(kTailWG), 0, s, l);
-  else hipLaunchKernelGGL((vcycle_tail_kernel<T, 3>), dim3(l.nwg), dim3(kTailWG), 0, s, l);
+void run_tail(int dim, const Launch<TailArgs<T>>& l, int lds, hipStream_t s) {
+  if (dim == 2) hipLaunchKernelGGL((vcycle_tail_kernel<T, 2>), dim3(l.nwg), dim3(kTailWG), lds, s, l);
+  else hipLaunchKernelGGL((vcycle_tail_kernel<T, 3>), dim3(l.nwg), dim3(kTailWG), lds, s, l);
 }
 
 template <class A>
@@ -277,6 +308,9 @@ TailArgs<T> tail_args(const mf_mesh* m, int lc, int nlev, int pre, int post, dou
   a.omega = (T)omega;
   a.coarse = coarse_args<T>(m->levels[lc], b[lc], x[lc]);
   for (int k = 0; k < nlev; ++k) a.lv[k] = tail_level<T>(m->levels[lc + k], b[lc + k], x[lc + k], t[lc + k]);
+  int64_t lds = 0;
+  for (int k = 0; k < nlev; ++k) lds += 3 * tail_lds_vec(a.lv[k].storage, (int)sizeof(T));
+  a.lds = lds <= kTailLdsMax ? (int)lds : 0;
   return a;
 }
 template TailArgs<double> tail_args<double>(const mf_mesh*, int, int, int, int, double, const std::vector<void*>&,
@@ -288,15 +322,21 @@ int launch_vcycle_tail(const mf_mesh* m, int lc, int nlev, int dtype, int pre, i
                        const std::vector<void*>& b, const std::vector<void*>& x, const std::vector<void*>& t,
                        hipStream_t s) {
   if (nlev < 1 || nlev > kTailLevels) return set_error(MF_EINVAL, "tail levels out of range");
-  if (dtype == MF_F64) run_tail<double>(m->dim, single(tail_args<double>(m, lc, nlev, pre, post, omega, b, x, t), 1), s);
-  else run_tail<float>(m->dim, single(tail_args<float>(m, lc, nlev, pre, post, omega, b, x, t), 1), s);
+  if (dtype == MF_F64) {
+    const TailArgs<double> a = tail_args<double>(m, lc, nlev, pre, post, omega, b, x, t);
+    run_tail<double>(m->dim, single(a, 1), a.lds, s);
+  } else {
+    const TailArgs<float> a = tail_args<float>(m, lc, nlev, pre, post, omega, b, x, t);
+    run_tail<float>(m->dim, single(a, 1), a.lds, s);
+  }
   return check_launch();
 }
 
 int launch_tail_batch(const BatchOp& op, const char* table, hipStream_t s) {
   if (op.nwg <= 0) return MF_OK;
-  if (op.dtype == MF_F64) run_tail<double>(op.dim, batched<TailArgs<double>>(op, table), s);
-  else run_tail<float>(op.dim, batched<TailArgs<float>>(op, table), s);
+  // op.variant: the largest LDS size of the members (each member's own record says whether it uses LDS)
+  if (op.dtype == MF_F64) run_tail<double>(op.dim, batched<TailArgs<double>>(op, table), op.variant, s);
+  else run_tail<float>(op.dim, batched<TailArgs<float>>(op, table), op.variant, s);
   return check_launch();
 }
 
