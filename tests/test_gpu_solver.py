@@ -101,6 +101,38 @@ def test_random_mesh_against_oracle_solve(mode):
     assert np.abs(xu - uo).max() <= kappa_bound * 1e-10 * max(1.0, np.abs(uo).max())
 
 
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+def test_tail_levels_in_lds_and_in_global_memory(mode):
+    """16 triangles at level 5: the one-workgroup bottom of the cycle takes
+    levels 2-4 (240, 720 and 2,448 storage points), whose b, x and t need
+    81,792 bytes in FP64 cycles (more than the 64 KiB the kernel keeps in LDS:
+    they stay in global memory, modes 0 and 2) and 40,896 bytes in FP32 cycles
+    (held in LDS, modes 1 and 3).  Both forms must solve to the tolerance on
+    the oracle's matrix."""
+    co, ce = W.strip_2d(16)
+    J, t = W.random_affine(2, 12)
+    co = W.apply_affine(co, J, t)
+    L = 5
+    m = P.create_macro_mesh(co, ce, L)
+    assert [P.mesh_num_dofs(m, k)[0] for k in (2, 3, 4, 5)] == [240, 720, 2448, 8976]
+    om = OracleMesh(co, ce, L)
+    s2u = harness.storage_to_unique(P.mesh_dof_keys(m, L), om.keys())
+    s, _ = P.mesh_num_dofs(m, L)
+    b = torch.empty(s, dtype=torch.float64, device="cuda")
+    P.mesh_fill_random(m, L, 33, b)
+    x = torch.zeros_like(b)
+    ws = torch.empty(P.mesh_workspace_bytes(m, L, mode), dtype=torch.uint8, device="cuda")
+    rc, it, rel, sec = P.vcycle_solve(m, L, b, x, ws, mode=mode, rtol=1e-10, max_iter=2000)
+    torch.cuda.synchronize()
+    assert rc == P.MF_OK, (it, rel)
+    bo = om.keyed_random(33)
+    xu = np.zeros(om.n)
+    xu[s2u] = x.cpu().numpy()
+    res = np.linalg.norm(bo - om.spmv(xu)) / np.linalg.norm(bo)
+    assert res <= 1.01e-10
+    assert abs(rel - res) <= 1e-2 * res, (rel, res)
+
+
 # refinement (modes 0, 1) takes any sweep counts; conjugate gradients (modes
 # 2, 3) needs a symmetric preconditioner, so equal pre- and post-sweeps
 CYCLES = [("strip2d", 6, 0, 2, None, 1), ("strip2d", 6, 1, 1, 1, 0), ("strip2d", 6, 3, 3, None, 3),
