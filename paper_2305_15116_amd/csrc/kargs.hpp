@@ -311,12 +311,16 @@ inline int transfer_blocks(int nseg) {
 template <typename T>
 TransferArgs<T> restrict_args(const Level& F, const Level& C, const void* rf, void* bc) {
   const int n = (int)C.psegs.size();
-  return TransferArgs<T>{C.dev.psegs, n, transfer_blocks(n), C.dev.md, F.dev.md, (const T*)rf, (T*)bc, C.dev.sbase, F.dev.sbase};
+  return TransferArgs<T>{C.dev.psegs, n, transfer_blocks(n), C.dev.md, F.dev.md, (const T*)rf, (T*)bc,
+                         C.dev.sbase, F.dev.sbase};
 }
 template <typename T>
 TransferArgs<T> prolong_args(const Level& F, const Level& C, const void* ec, void* xf) {
-  const int n = (int)F.psegs.size();
-  return TransferArgs<T>{F.dev.psegs, n, transfer_blocks(n), C.dev.md, F.dev.md, (const T*)ec, (T*)xf, C.dev.sbase, F.dev.sbase};
+  // 3D prolongations walk runs of slice segments, 2D single segments
+  const bool runs = !F.pruns.empty();
+  const int n = (int)(runs ? F.pruns.size() : F.psegs.size());
+  return TransferArgs<T>{runs ? F.dev.pruns : F.dev.psegs, n, transfer_blocks(n), C.dev.md, F.dev.md,
+                         (const T*)ec, (T*)xf, C.dev.sbase, F.dev.sbase};
 }
 
 template <typename T>

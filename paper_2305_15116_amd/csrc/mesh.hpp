@@ -24,6 +24,7 @@ struct LevelDev {
   Tile* segs = nullptr;        // row segments of 64 points covering every storage point
   Tile* psegs = nullptr;       // slice segments: 64 consecutive storage points of one slice
   int32_t* sbase = nullptr;    // first macro-local index of each slice z = 0 .. N + 1 (3D)
+  Tile* pruns = nullptr;       // 3D: runs of up to kTransferRun slice segments (prolongation)
   int32_t* grp_ptr = nullptr;  // ngroups + 1
   Copy* copies = nullptr;
   uint8_t* grp_flag = nullptr;  // bit0: Dirichlet
@@ -62,6 +63,7 @@ struct Level {
   // are cut into 64-point pieces across row ends (full lanes where rows are short)
   std::vector<Tile> psegs;
   std::vector<int32_t> sbase;  // slice bases, z = 0 .. N + 1 (3D; fits 32 bits up to N = 2048)
+  std::vector<Tile> pruns;     // 3D: {macro, first slice-local index, points (<= kTransferRun * 64), z}
   std::vector<int32_t> grp_ptr;
   std::vector<Copy> copies;
   std::vector<uint8_t> grp_flag;

@@ -538,6 +538,19 @@ static int build_level(mf_mesh* m, int level, Level& L) {
     }
   }
   while (L.psegs.size() % kWavesPerWG) L.psegs.push_back({-1, 0, 0, 0});
+  // runs of slice segments for the 3D prolongation: kTransferRun segments
+  // from N = 256 on, single ones below (more waves in flight for the
+  // smaller levels, measured faster there)
+  L.pruns.clear();
+  if (dim == 3) {
+    for (int64_t c = 0; c < m->nc; ++c)
+      for (int z = 0; z <= N; ++z) {
+        const int64_t S = N - z, P = (S + 1) * (S + 2) / 2, run = kWave * (N >= 256 ? kTransferRun : 1);
+        for (int64_t r0 = 0; r0 < P; r0 += run)
+          L.pruns.push_back({(int32_t)c, (int32_t)r0, (int32_t)std::min<int64_t>(run, P - r0), z});
+      }
+    while (L.pruns.size() % kWavesPerWG) L.pruns.push_back({-1, 0, 0, 0});
+  }
   L.sbase.assign(dim == 3 ? N + 2 : 1, 0);
   if (dim == 3)
     for (int z = 0; z <= N + 1; ++z) L.sbase[z] = (int32_t)slice_base(N, z);
@@ -553,6 +566,7 @@ int upload_level(mf_mesh* m, Level& L) {
   if ((rc = dev_upload(&D.segs, L.segs))) return rc;
   if ((rc = dev_upload(&D.psegs, L.psegs))) return rc;
   if ((rc = dev_upload(&D.sbase, L.sbase))) return rc;
+  if ((rc = dev_upload(&D.pruns, L.pruns))) return rc;
   if ((rc = dev_upload(&D.grp_ptr, L.grp_ptr))) return rc;
   if ((rc = dev_upload(&D.copies, L.copies))) return rc;
   if ((rc = dev_upload(&D.grp_flag, L.grp_flag))) return rc;
@@ -730,7 +744,7 @@ int build_mesh(mf_mesh* m) {
 void free_device(mf_mesh* m) {
   for (auto& L : m->levels) {
     LevelDev& D = L.dev;
-    void* ptrs[] = {D.md, D.tiles, D.tiles_f32, D.segs, D.psegs, D.sbase, D.grp_ptr, D.copies, D.grp_flag, D.xgrp_ptr, D.xcopies, D.cpidx, D.xcpidx, D.xgrp_invdiag,
+    void* ptrs[] = {D.md, D.tiles, D.tiles_f32, D.segs, D.psegs, D.sbase, D.pruns, D.grp_ptr, D.copies, D.grp_flag, D.xgrp_ptr, D.xcopies, D.cpidx, D.xcpidx, D.xgrp_invdiag,
                     D.xgrp_invdiagf,
                     D.part, D.result, D.cinv, D.cinvf, D.cfirst, D.cptr, D.cidx, D.own_bits, D.p2_tiles};
     for (void* p : ptrs)

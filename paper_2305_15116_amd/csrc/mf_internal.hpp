@@ -62,6 +62,9 @@ MF_HD constexpr int seg_run(int N) { return N >= 128 ? 4 : (N >= 64 ? 2 : 1); }
 // each shared DoF's whole row from its copies' partial stencils, so no
 // exchange launch follows.
 constexpr int kGroupTile = -2;
+// 3D prolongations walk runs of up to kTransferRun 64-point slice segments
+// (single segments below N = 256).
+constexpr int kTransferRun = 4;
 #ifndef MF_WAVES_PER_WG
 #define MF_WAVES_PER_WG 4
 #endif

@@ -277,15 +277,19 @@ __device__ __forceinline__ void slice_point(const Tile& sg, int N, int& x, int& 
 // in the macro, and its support mask, follow from P's position:
 // 2x + dx = 0 only for x = 0 and dx = 0, and Nf - |2P + d| =
 // 2 (Nc - |P|) - |d| vanishes only on P's far face with |d| = 0.
+// The lane's coarse point is slice-local index r of slice sg.z (in_run:
+// inside its run of points).
 template <typename T>
-__device__ __forceinline__ T restrict_seg3(const TransferArgs<T>& a, const Tile sg, int64_t& di, bool& wr) {
+__device__ __forceinline__ T restrict_seg3(const TransferArgs<T>& a, const Tile sg, int r, bool in_run, int64_t& di,
+                                           bool& wr) {
   constexpr StencilTable ST = stencil_table(3);
   constexpr int full = 15;
   const MacroC C = load_macro(a.mdc, sg.macro);
   const MacroC F = load_macro(a.mdf, sg.macro);
   const int Nc = C.N, Nf = F.N;
-  int x, y, z;
-  slice_point<3>(sg, Nc, x, y, z);
+  const int z = sg.z;
+  int x = Nc - z + 1, y = 0;  // lanes past the run or the slice: no point
+  if (in_run && r < (Nc - z + 1) * (Nc - z + 2) / 2) slice_xy3(Nc - z, r, x, y);
   const bool live = x + y + z <= Nc;
   const bool x0 = x == 0, y0 = y == 0, z0 = z == 0, far = x + y + z == Nc;
   const int zf = 2 * z, S = Nf - zf, yf = live ? 2 * y : 0, xf = live ? 2 * x : 0;
@@ -313,23 +317,17 @@ __device__ __forceinline__ T restrict_seg3(const TransferArgs<T>& a, const Tile 
     const T w = s == ST.centre ? T(1) : T(0.5);
     acc += use ? w * r : T(0);
   }
-  di = C.base + as_const(a.sbc)[z] + sg.x0 + (int)(threadIdx.x & (kWave - 1));
+  di = C.base + as_const(a.sbc)[z] + r;
   wr = live;
   return acc;
 }
 
+// 2D: one 64-point segment of coarse points.
 template <typename T, int DIM>
 __device__ __forceinline__ void restrict_segment(const TransferArgs<T>& a, const Tile sg) {
-  if constexpr (DIM == 3) {
-    int64_t di;
-    bool wr;
-    const T acc = restrict_seg3<T>(a, sg, di, wr);
-    if (wr) a.dst[di] = acc;
-  } else {
-    int x, y, z;
-    slice_point<DIM>(sg, load_macro(a.mdc, sg.macro).N, x, y, z);
-    restrict_point<T, DIM>(a, sg.macro, x, y, z);
-  }
+  int x, y, z;
+  slice_point<DIM>(sg, load_macro(a.mdc, sg.macro).N, x, y, z);
+  restrict_point<T, DIM>(a, sg.macro, x, y, z);
 }
 
 // x_f += P e_c: even fine points take the coarse value, the others the mean
@@ -365,15 +363,18 @@ __device__ __forceinline__ void prolong_point(const TransferArgs<T>& a, int macr
 // points addressed by 32-bit offsets from the first point of coarse slice
 // z / 2 (the other coarse slice, (z + 1) / 2, follows it), the fine point by
 // its slice-local index.
+// The lane's fine point is slice-local index r of slice sg.z (in_run: inside
+// its run of points).
 template <typename T>
-__device__ __forceinline__ void prolong_seg3(const TransferArgs<T>& a, const Tile sg, int64_t& di, T& u, T& v,
-                                             bool& wr) {
+__device__ __forceinline__ void prolong_seg3(const TransferArgs<T>& a, const Tile sg, int r, bool in_run,
+                                             int64_t& di, T& u, T& v, bool& wr) {
   constexpr int full = 15;
   const MacroC C = load_macro(a.mdc, sg.macro);
   const MacroC F = load_macro(a.mdf, sg.macro);
   const int Nc = C.N, Nf = F.N;
-  int x, y, z;
-  slice_point<3>(sg, Nf, x, y, z);
+  const int z = sg.z;
+  int x = Nf - z + 1, y = 0;  // lanes past the run or the slice: no point
+  if (in_run && r < (Nf - z + 1) * (Nf - z + 2) / 2) slice_xy3(Nf - z, r, x, y);
   const bool live = x + y + z <= Nf;
   const int mask = support_mask(3, Nf, x, y, z);
   const bool dir = mask != full && ((F.dir_mask >> mask) & 1);
@@ -391,23 +392,16 @@ __device__ __forceinline__ void prolong_seg3(const TransferArgs<T>& a, const Til
   u = Cl[(unsigned)((sz < 0 ? dh : 0) + row_start(Nc - zu, (yl - sy) >> 1) + ((xl - sx) >> 1))];
   v = Cl[(unsigned)((sz > 0 ? dh : 0) + row_start(Nc - zv, (yl + sy) >> 1) + ((xl + sx) >> 1))];
   // dead lanes name the macro's first point (a valid address, never written)
-  di = F.base + (live ? as_const(a.sbf)[z] + sg.x0 + (int)(threadIdx.x & (kWave - 1)) : 0);
+  di = F.base + (live ? as_const(a.sbf)[z] + r : 0);
   wr = live && !dir;
 }
 
+// 2D: one 64-point segment of fine points.
 template <typename T, int DIM>
 __device__ __forceinline__ void prolong_segment(const TransferArgs<T>& a, const Tile sg) {
-  if constexpr (DIM == 3) {
-    int64_t di;
-    T u, v;
-    bool wr;
-    prolong_seg3<T>(a, sg, di, u, v, wr);
-    if (wr) a.dst[di] += T(0.5) * (u + v);
-  } else {
-    int x, y, z;
-    slice_point<DIM>(sg, load_macro(a.mdf, sg.macro).N, x, y, z);
-    prolong_point<T, DIM>(a, sg.macro, x, y, z);
-  }
+  int x, y, z;
+  slice_point<DIM>(sg, load_macro(a.mdf, sg.macro).N, x, y, z);
+  prolong_point<T, DIM>(a, sg.macro, x, y, z);
 }
 
 // First Jacobi sweep of a V-cycle level.  The iterate is zero there, so

@@ -74,10 +74,11 @@ __global__ __launch_bounds__(kWG) void fill_random_kernel(const Tile* __restrict
 
 
 
-// Each wave walks several segments.  In 3D a wave takes kTransferU of them at
-// a time and issues all their loads before any store: a segment's work is a
-// short chain of dependent loads (segment record, macro records, values),
-// so independent segments in flight hide that latency.
+// Each wave walks several tiles.  In 3D all loads of a step are issued
+// before any store: the restriction's step takes kTransferU strided 64-point
+// segments of coarse points, the prolongation's a run of slice segments of
+// fine points (up to kTransferRun of one slice: one record, macro and
+// slice-base lookup for all of them).  2D walks single segments.
 constexpr int kTransferU = 4;
 
 template <typename T, int DIM>
@@ -87,6 +88,7 @@ __global__ __launch_bounds__(kWG) void restrict_kernel(const Launch<TransferArgs
   const int stride = a.nblk * kWavesPerWG;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if constexpr (DIM == 3) {
+    const int lane = threadIdx.x & (kWave - 1);
     for (int si = blk * kWavesPerWG + w; si < a.nseg; si += kTransferU * stride) {
       T acc[kTransferU];
       int64_t di[kTransferU];
@@ -96,7 +98,7 @@ __global__ __launch_bounds__(kWG) void restrict_kernel(const Launch<TransferArgs
         const int sk = si + k * stride;
         const Tile sg = sk < a.nseg ? load_seg(a.segs, sk) : Tile{-1, 0, 0, 0};
         wr[k] = false;
-        if (sg.macro >= 0) acc[k] = restrict_seg3<T>(a, sg, di[k], wr[k]);
+        if (sg.macro >= 0) acc[k] = restrict_seg3<T>(a, sg, sg.x0 + lane, true, di[k], wr[k]);
       }
 #pragma unroll
       for (int k = 0; k < kTransferU; ++k)
@@ -119,22 +121,24 @@ __global__ __launch_bounds__(kWG) void prolong_add_kernel(const Launch<TransferA
   const int stride = a.nblk * kWavesPerWG;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if constexpr (DIM == 3) {
-    for (int si = blk * kWavesPerWG + w; si < a.nseg; si += kTransferU * stride) {
-      T u[kTransferU], v[kTransferU], xo[kTransferU];
-      int64_t di[kTransferU];
-      bool wr[kTransferU];
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int si = blk * kWavesPerWG + w; si < a.nseg; si += stride) {
+      const Tile run = load_seg(a.segs, si);
+      if (run.macro < 0) continue;
+      T u[kTransferRun], v[kTransferRun], xo[kTransferRun];
+      int64_t di[kTransferRun];
+      bool wr[kTransferRun];
 #pragma unroll
-      for (int k = 0; k < kTransferU; ++k) {
-        const int sk = si + k * stride;
-        const Tile sg = sk < a.nseg ? load_seg(a.segs, sk) : Tile{-1, 0, 0, 0};
+      for (int k = 0; k < kTransferRun; ++k) {
+        const int q = k * kWave + lane;
         wr[k] = false;
-        if (sg.macro >= 0) prolong_seg3<T>(a, sg, di[k], u[k], v[k], wr[k]);
+        if (k * kWave < run.y0) prolong_seg3<T>(a, run, run.x0 + q, q < run.y0, di[k], u[k], v[k], wr[k]);
       }
 #pragma unroll
-      for (int k = 0; k < kTransferU; ++k)
+      for (int k = 0; k < kTransferRun; ++k)
         if (wr[k]) xo[k] = a.dst[di[k]];
 #pragma unroll
-      for (int k = 0; k < kTransferU; ++k)
+      for (int k = 0; k < kTransferRun; ++k)
         if (wr[k]) a.dst[di[k]] = xo[k] + T(0.5) * (u[k] + v[k]);
     }
   } else {
