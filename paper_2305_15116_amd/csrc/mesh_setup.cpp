@@ -415,48 +415,59 @@ static int build_level(mf_mesh* m, int level, Level& L) {
   // owner bits: bit i set iff storage DoF i is the copy that counts its
   // unique DoF in norms and dot products (interior points, and boundary
   // points whose primitive this macro owns)
-  L.own_bits.assign((size_t)((L.storage + 31) / 32), 0u);
+  // (slices of every macro on several threads: a word whose bits come from
+  // two rows is or-ed atomically, words inside one row are stored)
+  std::vector<std::atomic<uint32_t>> bits((size_t)((L.storage + 31) / 32));
+  for (auto& w : bits) w.store(0u, std::memory_order_relaxed);
   auto set_range = [&](int64_t lo, int64_t hi) {  // bits [lo, hi)
     for (int64_t i = lo; i < hi;) {
       if ((i & 31) == 0 && i + 32 <= hi) {
-        L.own_bits[i >> 5] = 0xffffffffu;
+        bits[i >> 5].store(0xffffffffu, std::memory_order_relaxed);
         i += 32;
       } else {
-        L.own_bits[i >> 5] |= 1u << (i & 31);
+        bits[i >> 5].fetch_or(1u << (i & 31), std::memory_order_relaxed);
         ++i;
       }
     }
   };
-  for (int64_t c = 0; c < m->nc; ++c) {
+  const int nz = dim == 3 ? N + 1 : 1;
+  parallel_for((size_t)(m->nc * nz), L.storage, [&](size_t job) {
+    const int64_t c = (int64_t)job / nz;
+    const int z = (int)((int64_t)job % nz);
     const uint16_t om = m->own_mask[c];
-    const int zmax = dim == 3 ? N : 0;
-    for (int z = 0; z <= zmax; ++z) {
-      const int S = N - z;
-      for (int y = 0; y <= S; ++y) {
-        const int64_t r0 = L.base[c] + (dim == 2 ? idx2(N, 0, y) : idx3(N, 0, y, z));
-        const int len = S - y + 1;
-        if (y >= 1 && z >= 1 - (dim == 2 ? 1 : 0) && len >= 3) {
-          set_range(r0 + 1, r0 + len - 1);
-          for (int x : {0, len - 1})
-            if ((om >> support_mask(dim, N, x, y, z)) & 1) set_range(r0 + x, r0 + x + 1);
-        } else {
-          for (int x = 0; x < len; ++x) {
-            const int mk = support_mask(dim, N, x, y, z);
-            if (mk == full_mask(dim) || ((om >> mk) & 1)) set_range(r0 + x, r0 + x + 1);
-          }
+    const int S = N - z;
+    for (int y = 0; y <= S; ++y) {
+      const int64_t r0 = L.base[c] + (dim == 2 ? idx2(N, 0, y) : idx3(N, 0, y, z));
+      const int len = S - y + 1;
+      if (y >= 1 && z >= 1 - (dim == 2 ? 1 : 0) && len >= 3) {
+        set_range(r0 + 1, r0 + len - 1);
+        for (int x : {0, len - 1})
+          if ((om >> support_mask(dim, N, x, y, z)) & 1) set_range(r0 + x, r0 + x + 1);
+      } else {
+        for (int x = 0; x < len; ++x) {
+          const int mk = support_mask(dim, N, x, y, z);
+          if (mk == full_mask(dim) || ((om >> mk) & 1)) set_range(r0 + x, r0 + x + 1);
         }
       }
     }
-  }
+  });
+  L.own_bits.resize(bits.size());
+  for (size_t i = 0; i < bits.size(); ++i) L.own_bits[i] = bits[i].load(std::memory_order_relaxed);
 
   // storage indices of the copies, so that exchange kernels index directly
   auto storage_index = [&](const Copy& c) {
     return L.md[c.macro].base + (dim == 2 ? idx2(N, c.x, c.y) : idx3(N, c.x, c.y, c.z));
   };
   L.cpidx.resize(L.copies.size());
-  for (size_t i = 0; i < L.copies.size(); ++i) L.cpidx[i] = storage_index(L.copies[i]);
   L.xcpidx.resize(L.xcopies.size());
-  for (size_t i = 0; i < L.xcopies.size(); ++i) L.xcpidx[i] = storage_index(L.xcopies[i]);
+  constexpr size_t kChunk = 1 << 16;
+  parallel_for((L.copies.size() + kChunk - 1) / kChunk, (int64_t)L.copies.size(), [&](size_t k) {
+    for (size_t i = k * kChunk; i < std::min(L.copies.size(), (k + 1) * kChunk); ++i) L.cpidx[i] = storage_index(L.copies[i]);
+  });
+  parallel_for((L.xcopies.size() + kChunk - 1) / kChunk, (int64_t)L.xcopies.size(), [&](size_t k) {
+    for (size_t i = k * kChunk; i < std::min(L.xcopies.size(), (k + 1) * kChunk); ++i)
+      L.xcpidx[i] = storage_index(L.xcopies[i]);
+  });
 
   // wave tiles over every point of every macro, natural order: macro,
   // (slice chunk,) strip, band; on small 3D levels runs of slice segments
@@ -530,6 +541,7 @@ static int build_level(mf_mesh* m, int level, Level& L) {
   }
   while (L.segs.size() % kWavesPerWG) L.segs.push_back({-1, 0, 0, 0});
   L.psegs.clear();
+  L.psegs.reserve((size_t)m->nc * (macro_points(dim, N) / kWave + (dim == 3 ? N + 2 : 2)) + 64);
   for (int64_t c = 0; c < m->nc; ++c) {
     const int zmax = dim == 3 ? N : 0;
     for (int z = 0; z <= zmax; ++z) {

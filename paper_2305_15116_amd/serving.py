@@ -77,6 +77,9 @@ class Server:
     whose footprint alone exceeds it is rejected (its future raises MFError
     with MF_ENOMEM).  batched: continuous batching with the mixed solver
     (default), else plain one-at-a-time FIFO with the all-FP64 solver.
+    Requests are admitted in arrival order and prepared (mesh set-up, device
+    vectors) by `preparers` threads, so both servers solve them in the order
+    their preparation ends.
     submit() returns a Future of (x, info): x the solution (torch, storage
     layout), info a dict with status, iters, rel_res and the arrival, admission
     and completion times (time.perf_counter()).
@@ -84,7 +87,7 @@ class Server:
 
     def __init__(self, budget_bytes: int, batched: bool = True, max_batch: int = 64, max_iter: int = 100,
                  keep_solutions: bool = True, mode: int | None = None, lanes: int | None = None,
-                 split_dofs: int = 4_000_000):
+                 split_dofs: int = 4_000_000, preparers: int = 3):
         import torch
         self.torch = torch
         self.budget = int(budget_bytes)
@@ -115,10 +118,15 @@ class Server:
         self._dev = torch.cuda.current_device()
         self._next = 0
         self._live: dict[int, Request] = {}  # submitted, not finished
-        self._prep = threading.Thread(target=self._prep_loop, name="mf-prep", daemon=True)
+        # mesh set-up on the host takes as long as a solve or longer (3D level 8:
+        # about 35 ms against a 20 ms mixed CG solve), so several threads
+        # prepare requests; ctypes releases the GIL during the library calls
+        self._prep = [threading.Thread(target=self._prep_loop, name=f"mf-prep{k}", daemon=True)
+                      for k in range(max(1, preparers))]
         self._work = [threading.Thread(target=self._work_loop, args=(k,), name=f"mf-work{k}", daemon=True)
                       for k in range(self.lanes)]
-        self._prep.start()
+        for t in self._prep:
+            t.start()
         for t in self._work:
             t.start()
 
@@ -151,7 +159,8 @@ class Server:
             self._stop = True
             self._cv.notify_all()
         if wait:
-            self._prep.join()
+            for t in self._prep:
+                t.join()
             for t in self._work:
                 t.join()
         if self._error is not None:
