@@ -5,7 +5,9 @@ the P1 interpolant of nodal values) within 1e-12 relative in the max norm;
 FP32 within 1e-5.  At the full size of the benchmark (level 14) the oracle
 cannot be assembled, so the output is checked by properties that hold at any
 size: a constant k = c gives c times the constant-coefficient apply, and for
-any k the constant vector gives zero rows off the Dirichlet boundary.  The 3D
+any k the constant vector gives zero rows off the Dirichlet boundary; with a
+seeded k, sampled rows are recomputed one by one by the oracle's row
+evaluator.  The 3D
 apply is compared with the assembled matrix at every row up to level 6 and,
 on the 6-tet cube at level 8, on sampled rows recomputed one by one by the
 oracle's row evaluator.
@@ -181,6 +183,42 @@ def test_varcoef_fp32_full_size():
     wc = float(np.abs(P.mesh_stencil(m, L, 0)).sum())
     err = (y[inner].double() - 2.0 * y1[inner].double()).abs().max().item()
     assert err <= 256 * 2.0 ** -24 * 2.0 * wc, err
+
+
+def test_varcoef_2d_level14_sampled_rows():
+    """The benchmark's 2D workload (the affine triangle at level 14,
+    134,242,305 DoFs) with a seeded coefficient k in [0.5, 2.5): about 3,000
+    sampled rows (random, tile edges, the apex and the three sides) against
+    the oracle's row evaluator within 1e-12."""
+    co, ce = W.affine_triangle(2)
+    L = 14
+    N = 1 << L
+    m = P.create_macro_mesh(co, ce, L)
+    s, _ = P.mesh_num_dofs(m, L)
+    x = torch.empty(s, dtype=torch.float64, device="cuda")
+    k = torch.empty_like(x)
+    P.mesh_fill_random(m, L, 41, x)
+    P.mesh_fill_random(m, L, 42, k)
+    k += 1.5
+    y = torch.full_like(x, float("nan"))
+    P.apply_varcoef(m, L, k, x, y)
+    torch.cuda.synchronize()
+    assert torch.isfinite(y).all()
+    rng = np.random.default_rng(11)
+    pts = []
+    for _ in range(2500):
+        yy = int(rng.integers(0, N + 1))
+        pts.append((0, int(rng.integers(0, N + 1 - yy)), yy))
+    for yy in (0, 1, 2, 7, 8, 9, N // 2, N - 62, N - 2, N - 1, N):
+        for xx in (0, 1, 61, 62, 63, 124, N - yy - 1, N - yy):
+            if 0 <= xx and xx + yy <= N:
+                pts.append((0, xx, yy))
+    pts = np.array(pts, dtype=np.int64)  # (macro, x, y)
+    idx = P.mesh_dof_index(m, L, pts)
+    got = y[torch.as_tensor(idx, device="cuda")].cpu().numpy()
+    yo, bnd = sample_rows_varcoef(co, ce, L, 41, 42, 1.5, pts[:, 0], pts[:, 1:3])
+    assert bnd.any() and (~bnd).sum() > 2000
+    assert np.abs(got - yo).max() <= 1e-12 * np.abs(yo).max()
 
 
 @pytest.mark.parametrize("order", ["canonical", "random"])
