@@ -92,13 +92,8 @@ __device__ __forceinline__ void finish_interior(const MacroDev& M, T acc, T xc, 
   accum<T, MODE>(ss, mx, out, xc);
 }
 
-// Rows off the y = 0 (and, in 3D, z = 0) faces: a boundary lane is the row's
-// first point (x = 0), its last (on the far face x + y + z = N), or both, so
-// it has one of three support masks known at compile time.  Their partial
-// stencils are uniform (one weight per offset for all lanes), and the
-// neighbours outside the macro are known at compile time — x - 1 for x = 0,
-// the offsets of coordinate sum +1 on the far face — so those terms are left
-// out.
+// Support masks of the boundary lanes of rows off the y = 0 (and, in 3D,
+// z = 0) faces: the row's first point (x = 0), its last (far face) or both.
 template <int DIM>
 struct RowMasks {
   static constexpr int L = full_mask(DIM) & ~2;   // x = 0
@@ -106,42 +101,34 @@ struct RowMasks {
   static constexpr int LF = full_mask(DIM) & ~3;  // both
 };
 
-template <typename T, int DIM, int MASK>
-__device__ __forceinline__ T group_sum(const WTab<T> W, const T* v) {
-  constexpr StencilTable ST = stencil_table(DIM);
-  constexpr bool left = !(MASK & 2), far = !(MASK & 1);
-  T acc = T(0);
-#pragma unroll
-  for (int o = 0; o < ST.n; ++o) {
-    const int osum = ST.off[o][0] + ST.off[o][1] + ST.off[o][2];
-    if ((left && ST.off[o][0] < 0) || (far && osum > 0)) continue;
-    acc = fma(W[MASK][o], v[o], acc);
-  }
-  return acc;
-}
-
 // Row of one point from its neighbour values v (xc = its x, bv = its b).
-// Every lane first takes the interior stencil.  may_face (a compile-time
-// constant after unrolling) marks the rows that can lie on the y = 0 / z = 0
-// faces: those go through the general per-lane path.  Other rows fix up
-// their x = 0 lane (only in tiles starting at x0 = 0, tile_left) and their
-// far-face lane branch-free, with the uniform partial stencils above;
-// Jacobi needs bid = 1 / centre weight of the L, F and LF masks.
+// may_face (a compile-time constant after unrolling) marks the rows that can
+// lie on the y = 0 / z = 0 faces: those go through the general per-lane
+// path.  In other rows a boundary lane is the row's first point (x = 0, only
+// in tiles starting at x0 = 0, tile_left), its last (on the far face
+// x + y + z = N), or both.  A row without such a lane takes the interior
+// stencil from scalar registers, and so does a row whose boundary lanes are
+// all Dirichlet points (they copy x).  Any other row takes, in every lane,
+// the partial stencil of the lane's own support mask from the LDS table
+// (interior lanes read the full stencil there, the same weights); the
+// neighbours such a lane lacks (x - 1 for x = 0, the offsets of coordinate
+// sum +1 on the far face) have weight 0 in its table row, and their
+// stand-in values are replaced by 0 so that those terms add exactly nothing.
+// The terms are summed in table order in every case, so a boundary row is
+// the sum over the neighbours it has, in that order.  Jacobi needs bid =
+// 1 / centre weight of the L, F and LF masks.
 template <typename T, int DIM, int MODE, bool KEEP_SHARED = true>
 __device__ __forceinline__ void point_row(const MacroDev& M, const WTab<T> W, const T* wi, bool inside, int N, int x,
                                           int y, int z, const T* v, T xc, T bv, T omega, T* yp, double& ss,
                                           double& mx, bool may_face, bool tile_left, const T* bid) {
-  using RM = RowMasks<DIM>;
+  constexpr StencilTable ST = stencil_table(DIM);
   constexpr int FM = full_mask(DIM);
-  constexpr int NO = DIM == 2 ? 7 : 15;
-  T acc = wi[0] * v[0];
-#pragma unroll
-  for (int o = 1; o < NO; ++o) acc = fma(wi[o], v[o], acc);
+  constexpr int NO = ST.n;
   if (may_face && (y == 0 || (DIM == 3 && z == 0))) {
     // a row on the y = 0 or z = 0 face: every lane is a boundary point
     if (__builtin_amdgcn_ballot_w64(inside)) {
       const int mask = support_mask(DIM, N, x, y, z);
-      acc = partial_sum<T, DIM>(W, inside ? mask : FM, N, x, y, z, v);
+      const T acc = partial_sum<T, DIM>(W, inside ? mask : FM, N, x, y, z, v);
       if (inside) finish<T, DIM, MODE, KEEP_SHARED>(M, W, mask, acc, xc, bv, omega, yp, ss, mx);
     }
     return;
@@ -149,34 +136,39 @@ __device__ __forceinline__ void point_row(const MacroDev& M, const WTab<T> W, co
   const bool far = inside && x + y + z == N;
   const bool left = tile_left && inside && x == 0;
   if (!__builtin_amdgcn_ballot_w64(far || left)) {
+    T acc = wi[0] * v[0];
+#pragma unroll
+    for (int o = 1; o < NO; ++o) acc = fma(wi[o], v[o], acc);
     if (inside) finish_interior<T, MODE>(M, acc, xc, bv, omega, yp, ss, mx);
     return;
   }
-  // a group on the Dirichlet boundary only copies x (or b - x): no partial sum
-  T ab = acc;
-  if (!((M.dir_mask >> RM::F) & 1)) ab = group_sum<T, DIM, RM::F>(W, v);
-  int bm = RM::F;
-  T bd = MODE == kJacobi ? bid[1] : T(0);
-  if (tile_left) {
-    T al = acc, alf = acc;
-    if (!((M.dir_mask >> RM::L) & 1)) al = group_sum<T, DIM, RM::L>(W, v);
-    if (!((M.dir_mask >> RM::LF) & 1)) alf = group_sum<T, DIM, RM::LF>(W, v);
-    if (left) {
-      ab = far ? alf : al;
-      bm = far ? RM::LF : RM::L;
-      if (MODE == kJacobi) bd = far ? bid[2] : bid[0];
+  const bool bnd = far || left;
+  const int bm = FM & ~(far ? 1 : 0) & ~(left ? 2 : 0);
+  const bool dir = bnd && ((M.dir_mask >> bm) & 1);
+  T a = T(0);
+  if (!__builtin_amdgcn_ballot_w64(bnd && !dir)) {
+    // the row's boundary lanes are all Dirichlet (they copy x): the others
+    // take the interior stencil
+    a = wi[0] * v[0];
+#pragma unroll
+    for (int o = 1; o < NO; ++o) a = fma(wi[o], v[o], a);
+  } else {
+    const T* wr = W[bm];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) {
+      T vo = v[o];
+      if (ST.off[o][0] + ST.off[o][1] + ST.off[o][2] > 0) vo = far ? T(0) : vo;
+      if (ST.off[o][0] < 0) vo = left ? T(0) : vo;
+      a = o == 0 ? wr[0] * vo : fma(wr[o], vo, a);
     }
   }
-  const bool bnd = far || left;
-  const T a = bnd ? ab : acc;
-  const bool dir = bnd && ((M.dir_mask >> bm) & 1);
   const bool shared = bnd && !dir && ((M.shared_mask >> bm) & 1);
   const bool own = !bnd || ((M.own_mask >> bm) & 1);
   T out;
   if (MODE == kApply || MODE == kApplyDot) {
     out = dir ? xc : a;
   } else if (MODE == kJacobi) {
-    const T id = bnd ? bd : Prec<T>::invd(M);
+    const T id = !bnd ? Prec<T>::invd(M) : far ? (left ? bid[2] : bid[1]) : bid[0];
     out = dir ? xc : (shared ? a : fma(omega * id, bv - a, xc));
   } else if (MODE == kResidual) {
     out = dir ? bv - xc : (shared ? a : bv - a);
