@@ -227,18 +227,25 @@ def solve_bytes(P, m, L, mode, iters, lc=2):
     prolongation e S_{l-1}/S_l + 2e, two post-sweeps 6e.  Outer step per fine
     DoF: refinement x += e and r = b - A x (FP64 48, mixed 56 with the
     scaled cast); CG r.z, direction, A p with p.Ap, x/r update (FP64 104,
-    mixed 108 with the cast).  Set-up: norm of b and the first residual (32),
-    plus one recomputed residual (24) at CG termination."""
+    mixed 108 with the cast); MINRES A z with z.Az 16, the Lanczos
+    recurrence 32, v.z 16 (mixed: the scaled cast 12 and z formed in FP64,
+    20), the direction recurrence 32 and x += c eta w 24 (FP64 120, mixed
+    136).  Set-up: norm of b and the first residual (32), plus one
+    recomputed residual (24) at Krylov termination; MINRES also clears three
+    vectors (24) and applies the preconditioner once before its first
+    iteration (one cycle and v.z)."""
     S = [P.mesh_num_dofs(m, l)[0] for l in range(L + 1)]
     e = 4 if mode & 1 else 8
     cycle = sum((17 * e + 2 * e * S[l - 1] / S[l]) * S[l] for l in range(lc + 1, L + 1))
-    outer = {0: 48, 1: 56, 2: 104, 3: 108}[mode] * S[L]
-    setup = (32 + (24 if mode & 2 else 0)) * S[L]
+    outer = {0: 48, 1: 56, 2: 104, 3: 108, 4: 120, 5: 136}[mode] * S[L]
+    setup = (32 + (24 if mode & 6 else 0)) * S[L]
+    if mode & 4:
+        setup += cycle + (24 + (32 if mode & 1 else 16)) * S[L]
     return {"per_iteration": cycle + outer, "per_iteration_B_per_dof": (cycle + outer) / S[L],
             "per_solve": setup + iters * (cycle + outer)}
 
 
-def solve_bench(P, torch, W, L=8, repeats=10, modes=(0, 1, 2, 3)):
+def solve_bench(P, torch, W, L=8, repeats=10, modes=(0, 1, 2, 3, 4, 5)):
     co, ce = W.kuhn_cube()
     m = P.create_macro_mesh(co, ce, L)
     s, _ = P.mesh_num_dofs(m, L)
@@ -255,7 +262,7 @@ def solve_bench(P, torch, W, L=8, repeats=10, modes=(0, 1, 2, 3)):
     f = 3 * np.pi ** 2 * np.prod(np.sin(np.pi * xyz), axis=1)
     b = torch.as_tensor(h ** 3 * f, device="cuda")
     out = {}
-    names = {0: "fp64", 1: "mixed", 2: "fp64_pcg", 3: "mixed_pcg"}
+    names = {0: "fp64", 1: "mixed", 2: "fp64_pcg", 3: "mixed_pcg", 4: "fp64_minres", 5: "mixed_minres"}
     for mode in modes:
         ws = torch.empty(P.mesh_workspace_bytes(m, L, mode), dtype=torch.uint8, device="cuda")
         x = torch.zeros(s, dtype=torch.float64, device="cuda")
@@ -366,7 +373,7 @@ def main():
     ap.add_argument("--serve-n", type=int, default=None, help="requests of the serving run")
     ap.add_argument("--serve-servers", choices=["both", "plain", "batched"], default="both",
                     help="which servers the serving run measures")
-    ap.add_argument("--solve-only", type=int, choices=[0, 1, 2, 3], default=None,
+    ap.add_argument("--solve-only", type=int, choices=[0, 1, 2, 3, 4, 5], default=None,
                     help="only run the cube level-8 solve of this mode three times (for kernel traces)")
     ap.add_argument("--cpu-cube", action="store_true",
                     help="also time the oracle on the 3D benchmark mesh (cube level 8, 100 products; assembly takes minutes)")

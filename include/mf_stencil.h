@@ -105,7 +105,7 @@ int mesh_dof_index(const mf_mesh* mesh, int level, int64_t n, const int64_t* mac
 int mesh_stencil(const mf_mesh* mesh, int level, int64_t macro, double* weights);
 
 /* Bytes of device workspace vcycle_solve needs at `level` for a solver mode
- * (mf_solve_opts.mode, 0..3). */
+ * (mf_solve_opts.mode, 0..5). */
 int mesh_workspace_bytes(const mf_mesh* mesh, int level, int mode, int64_t* bytes);
 
 /* Fill a storage vector with x = 2u - 1, u uniform in [0,1) from SplitMix64
@@ -211,8 +211,10 @@ int prolong_add(const mf_mesh* mesh, int level, int dtype, const void* ec_dev, v
 typedef struct {
   int mode;         /* 0: FP64 V-cycles in iterative refinement; 1: FP32 V-cycles in FP64 iterative
                        refinement; 2: conjugate gradients preconditioned by one FP64 V-cycle per
-                       iteration; 3: the same with an FP32 V-cycle (FP64 recurrences) */
-  int pre, post;    /* smoothing sweeps (default 2, 2); modes 2, 3 need pre == post (a symmetric
+                       iteration; 3: the same with an FP32 V-cycle (FP64 recurrences); 4: MINRES
+                       preconditioned by one FP64 V-cycle per iteration; 5: the same with an FP32
+                       V-cycle (FP64 recurrences) */
+  int pre, post;    /* smoothing sweeps (default 2, 2); modes 2 to 5 need pre == post (a symmetric
                        preconditioner), else MF_EINVAL */
   int coarse_level; /* solved directly (default min(2, level)) */
   int max_iter;     /* outer iterations (default 50) */
@@ -228,18 +230,24 @@ typedef struct {
 
 /* Solve A x = b with V(pre,post)-cycles of geometric multigrid (levels are
  * the refinement hierarchy, Intro) as the correction of iterative refinement
- * (modes 0, 1) or as the preconditioner of conjugate gradients (modes 2, 3;
- * every CG scalar stays on the device).  x_dev holds the initial guess (its
- * Dirichlet entries are set to b's); workspace_dev must hold
- * mesh_workspace_bytes(level, opts->mode) bytes.  The stopping test uses the
- * true FP64 residual b - A x over unique DoFs: recomputed each iteration in
- * modes 0, 1; in modes 2, 3 the CG recurrence's residual decides when to
- * recompute it, and MF_OK is returned only if the recomputed one meets rtol
- * (otherwise CG goes on).  info->rel_res is that true relative residual
- * (modes 2, 3 after a miss that ends at max_iter: the last recomputed one).
- * Returns MF_OK, MF_NOT_CONVERGED (x = last iterate) or an error.
- * Synchronous; one device-to-host copy of two doubles per iteration, plus
- * one per recomputed residual in modes 2, 3. */
+ * (modes 0, 1), as the preconditioner of conjugate gradients (modes 2, 3;
+ * every CG scalar stays on the device) or as the preconditioner of MINRES
+ * (modes 4, 5: the Krylov method of the paper's plume application, section
+ * Plume in Rectangular Domain; its scalars are formed on the host).  x_dev
+ * holds the initial guess (its Dirichlet entries are set to b's);
+ * workspace_dev must hold mesh_workspace_bytes(level, opts->mode) bytes.
+ * The stopping test uses the true FP64 residual b - A x over unique DoFs:
+ * recomputed each iteration in modes 0, 1; in modes 2 to 5 the Krylov
+ * recurrence's residual (CG: its 2-norm; MINRES: sqrt(r . M r), M the
+ * V-cycle, against its first value) decides when to recompute it,
+ * and MF_OK is returned only if the recomputed one meets rtol (otherwise the
+ * recurrence goes on).  info->rel_res is that true relative residual (modes 2
+ * to 5 after a miss that ends at max_iter: the last recomputed one; MINRES
+ * recomputes it at max_iter).  Returns MF_OK, MF_NOT_CONVERGED (x = last
+ * iterate) or an error (MF_ENUMERIC if MINRES meets a preconditioner that is
+ * not positive definite).  Synchronous; one device-to-host copy of two
+ * doubles per iteration (MINRES: two), plus one per recomputed residual in
+ * modes 2 to 5. */
 int vcycle_solve(const mf_mesh* mesh, int level, const double* b_dev, double* x_dev, void* workspace_dev,
                  const mf_solve_opts* opts, mf_solve_info* info, void* stream);
 
@@ -266,9 +274,10 @@ int device_copy(void* dst_dev, const void* src_dev, int64_t n_bytes, void* strea
  * latency rather than by memory bandwidth. */
 typedef struct mf_batch mf_batch;
 
-/* opts: as for vcycle_solve (mode, pre, post, max_iter, omega; rtol is per
- * member; coarse_level < 0 or above a member's level selects min(2, level)).
- * NULL = mode 1, V(2,2), 50 iterations, omega 2/3.  capacity: maximum members
+/* opts: as for vcycle_solve (mode 0..3 only: MINRES is not batched; pre,
+ * post, max_iter, omega; rtol is per member; coarse_level < 0 or above a
+ * member's level selects min(2, level)).  NULL = mode 1, V(2,2), 50
+ * iterations, omega 2/3; another mode is MF_EINVAL.  capacity: maximum members
  * (1..4096).  Allocates a small device table and pinned staging. */
 int batch_create(const mf_solve_opts* opts, int capacity, mf_batch** out);
 int batch_destroy(mf_batch* batch);

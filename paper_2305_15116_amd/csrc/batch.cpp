@@ -502,7 +502,7 @@ int batch_create(const mf_solve_opts* opts, int capacity, mf_batch** out) {
   if (capacity < 1 || capacity > 4096) return set_error(MF_EINVAL, "capacity must be in [1, 4096]");
   mf_solve_opts o = {1, 2, 2, -1, 50, 2.0 / 3.0, 1e-8};
   if (opts) o = *opts;
-  if (o.mode < 0 || o.mode > 3) return set_error(MF_EINVAL, "mode must be 0, 1, 2 or 3");
+  if (o.mode < 0 || o.mode > 3) return set_error(MF_EINVAL, "batched solves take mode 0, 1, 2 or 3");
   if (mode_pcg(o.mode) && o.pre != o.post)
     return set_error(MF_EINVAL, "conjugate gradients need a symmetric V-cycle (pre == post)");
   if (o.pre < 0 || o.post < 0 || o.max_iter < 0) return set_error(MF_EINVAL, "bad solver options");

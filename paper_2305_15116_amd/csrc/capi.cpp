@@ -8,7 +8,8 @@
 // experiment description).  smooth and residual reuse the same kernels in
 // their fused Jacobi and residual modes; vcycle_solve runs geometric
 // multigrid over the refinement levels (Intro: the levels are a natural
-// multigrid hierarchy) inside iterative refinement.
+// multigrid hierarchy) inside iterative refinement, conjugate gradients or
+// MINRES.
 
 #include <hip/hip_runtime.h>
 
@@ -135,6 +136,137 @@ int vcycle(const mf_mesh* m, int l, int lc, int tail, int dtype, const Workspace
   return rc;
 }
 
+// z = M v: one V-cycle on v from the zero iterate, then partials of v . z
+// (unique DoFs) reduced into result[2].  FP32 cycles take v scaled by
+// 1 / result[1] (its max |.|, already on the device) and z = result[1] e is
+// formed in FP64; FP64 cycles read v and write z in place of b and x of the
+// top level.
+int precondition(const mf_mesh* m, int level, int lc, int tail, bool f32, Workspace& w, const mf_solve_opts& o,
+                 const double* v, double* z, hipStream_t s) {
+  const Level& L = m->levels[level];
+  int rc;
+  if (f32) {
+    rc = launch_scale_to_f32(v, (float*)w.b[level], w.result, L.storage, s);
+    if (!rc) rc = vcycle(m, level, lc, tail, MF_F32, w, o, s);
+    if (!rc) rc = launch_pcg_zdot(m, L, MF_F32, v, w.x[level], z, w.result, w.part, s);
+  } else {
+    w.b[level] = (void*)v;
+    w.x[level] = z;
+    rc = vcycle(m, level, lc, tail, MF_F64, w, o, s);
+    if (!rc) rc = launch_pcg_zdot(m, L, MF_F64, v, z, z, w.result, w.part, s);
+  }
+  if (!rc) rc = launch_reduce(w.part, L.lin_blocks(), w.result + 2, s);
+  return rc;
+}
+
+// Preconditioned MINRES (the outer solver of the paper's plume application,
+// there around a block preconditioner; here around the symmetric V-cycle M,
+// which is positive definite for this operator).  Lanczos in the inner
+// product induced by M: the vectors v_j are kept unnormalised (gamma_j =
+// sqrt(v_j . M v_j), z_j = M v_j / gamma_j), the tridiagonal is reduced by
+// Givens rotations (c, s), and the directions w_j give x_j = x_{j-1} +
+// c_{j+1} eta w_{j+1}; |eta| = sqrt(r . M r) for the current residual r,
+// the norm MINRES minimises.  When |eta| falls to `trigger`
+// times its first value (rtol at first) the FP64 residual b - A x is
+// computed; the solve ends when it meets rtol, otherwise the trigger is
+// tightened and the recurrence goes on.  On entry r64 holds b - A x and
+// result[1] its max |.|.
+int minres_iterate(const mf_mesh* m, int level, int lc, int tail, const double* b, double* x, Workspace& w,
+                   const mf_solve_opts& o, double bnorm, double rel0, hipStream_t s, int* iters, double* rel_out,
+                   bool* converged) {
+  const Level& L = m->levels[level];
+  const int64_t n = L.storage;
+  const bool f32 = mode_f32(o.mode);
+  const int nlin = (int)L.lin_blocks();
+  double* v = w.r64;
+  double* vo = w.v2;
+  double* z = w.z64;
+  double* zn = w.z2;
+  double* wc = w.w1;
+  double* wo = w.w2;
+  int rc = launch_fill(MF_F64, vo, 0.0, n, s);
+  if (!rc) rc = launch_fill(MF_F64, wc, 0.0, n, s);
+  if (!rc) rc = launch_fill(MF_F64, wo, 0.0, n, s);
+  if (!rc) rc = precondition(m, level, lc, tail, f32, w, o, v, z, s);
+  double out[2] = {0.0, 0.0};
+  if (!rc) rc = sync_result(w.result + 2, out, s);
+  if (rc) return rc;
+  auto true_rel = [&](double* rel) {
+    double ts = 0.0, tm = 0.0;
+    const int r = residual_norm(m, L, MF_F64, b, x, w.q64, w.part, w.result + 6, &ts, &tm, s);
+    *rel = bnorm > 0.0 ? std::sqrt(ts) / bnorm : std::sqrt(ts);
+    return r;
+  };
+  if (!std::isfinite(out[0]) || out[0] < 0.0)
+    return set_error(MF_ENUMERIC, "preconditioner is not positive definite (v . M v < 0 or not finite)");
+  double gamma = std::sqrt(out[0]), gamma_o = 1.0;
+  double eta = gamma;
+  const double eta0 = gamma;
+  double c = 1.0, c_o = 1.0, sn = 0.0, sn_o = 0.0;
+  double trigger = o.rtol, rel = rel0;
+  int it = 0;
+  *converged = false;
+  for (;;) {
+    if (gamma == 0.0 || std::fabs(eta) <= trigger * eta0) {
+      // the M^-1-norm says converged (or v = 0): check the FP64 residual
+      if (it > 0) {
+        rc = true_rel(&rel);
+        if (rc) return rc;
+      }
+      if (rel <= o.rtol || gamma == 0.0) {
+        *converged = rel <= o.rtol;
+        break;
+      }
+      trigger *= std::min(0.5, o.rtol / rel);
+    }
+    if (it >= o.max_iter) {
+      if (it > 0) rc = true_rel(&rel);
+      break;
+    }
+    // q = A z_u (z_u = gamma z_j) and z_u . q
+    rc = launch_stencil(m, L, MF_F64, kApplyDot, z, w.q64, nullptr, 0.0, w.part, s);
+    if (!rc) rc = launch_reduce(w.part, stencil_partials(L, MF_F64), w.result + 4, s);
+    if (!rc) rc = sync_result(w.result + 4, out, s);
+    if (rc) return rc;
+    const double delta = out[0] / (gamma * gamma);  // z_j . A z_j
+    // v_{j+1} = A z_j - (delta / gamma_j) v_j - (gamma_j / gamma_{j-1}) v_{j-1}, over v_{j-1}
+    rc = launch_lin3(vo, w.q64, v, -gamma / gamma_o, 1.0 / gamma, -delta / gamma, n, f32 ? w.part : nullptr, nlin, s);
+    if (!rc && f32) rc = launch_reduce(w.part, nlin, w.result, s);  // max |v_{j+1}| for the FP32 scaling
+    std::swap(v, vo);
+    if (!rc) rc = precondition(m, level, lc, tail, f32, w, o, v, zn, s);
+    if (!rc) rc = sync_result(w.result + 2, out, s);
+    if (rc) return rc;
+    if (!std::isfinite(out[0]) || out[0] < 0.0)
+      return set_error(MF_ENUMERIC, "preconditioner is not positive definite (v . M v < 0 or not finite)");
+    const double gamma_n = std::sqrt(out[0]);
+    // the new column of the tridiagonal, rotated by the last two rotations,
+    // and the rotation that annihilates gamma_{j+1}
+    const double a0 = c * delta - c_o * sn * gamma;
+    const double a1 = std::hypot(a0, gamma_n);
+    const double a2 = sn * delta + c_o * c * gamma;
+    const double a3 = sn_o * gamma;
+    if (!(a1 > 0.0) || !std::isfinite(a1)) return set_error(MF_ENUMERIC, "MINRES breakdown (zero rotation norm)");
+    const double c_n = a0 / a1, sn_n = gamma_n / a1;
+    // w_{j+1} = (z_j - a3 w_{j-1} - a2 w_j) / a1, over w_{j-1}; x += c_{j+1} eta w_{j+1}
+    rc = launch_lin3(wo, z, wc, -a3 / a1, 1.0 / (a1 * gamma), -a2 / a1, n, nullptr, nlin, s);
+    std::swap(wc, wo);
+    if (!rc) rc = launch_axpy(MF_F64, x, wc, c_n * eta, n, s);
+    if (rc) return rc;
+    eta = -sn_n * eta;
+    c_o = c;
+    c = c_n;
+    sn_o = sn;
+    sn = sn_n;
+    gamma_o = gamma;
+    gamma = gamma_n;
+    std::swap(z, zn);
+    ++it;
+  }
+  *iters = it;
+  *rel_out = rel;
+  return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -238,7 +370,7 @@ int mesh_stencil(const mf_mesh* m, int level, int64_t macro, double* w) {
 int mesh_workspace_bytes(const mf_mesh* m, int level, int mode, int64_t* bytes) {
   int rc = check_mesh(m, level, false);
   if (rc) return rc;
-  if (mode < 0 || mode > 3) return set_error(MF_EINVAL, "mode must be 0, 1, 2 or 3");
+  if (mode < 0 || mode >= kNumModes) return set_error(MF_EINVAL, "mode must be in 0..5");
   if (!bytes) return set_error(MF_EINVAL, "NULL output");
   *bytes = carve(m, level, mode, 0, nullptr).bytes;
   return MF_OK;
@@ -357,9 +489,9 @@ int vcycle_solve(const mf_mesh* m, int level, const double* b, double* x, void* 
   if (!b || !x || !workspace) return set_error(MF_EINVAL, "NULL vector or workspace");
   mf_solve_opts o = {0, 2, 2, default_coarse(level), 50, 2.0 / 3.0, 1e-10};
   if (opts) o = *opts;
-  if (o.mode < 0 || o.mode > 3) return set_error(MF_EINVAL, "mode must be 0, 1, 2 or 3");
-  if (mode_pcg(o.mode) && o.pre != o.post)
-    return set_error(MF_EINVAL, "conjugate gradients need a symmetric V-cycle (pre == post)");
+  if (o.mode < 0 || o.mode >= kNumModes) return set_error(MF_EINVAL, "mode must be in 0..5");
+  if (mode_krylov(o.mode) && o.pre != o.post)
+    return set_error(MF_EINVAL, "conjugate gradients and MINRES need a symmetric V-cycle (pre == post)");
   if (o.pre < 0 || o.post < 0 || o.max_iter < 0 || !(o.rtol >= 0.0))
     return set_error(MF_EINVAL, "bad solver options");
   if (o.coarse_level < 0 || o.coarse_level > level) return set_error(MF_EINVAL, "coarse_level outside [0, level]");
@@ -373,7 +505,7 @@ int vcycle_solve(const mf_mesh* m, int level, const double* b, double* x, void* 
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t s = (hipStream_t)stream;
   const Level& L = m->levels[level];
-  const Workspace w = carve(m, level, o.mode, 0, (char*)workspace);
+  Workspace w = carve(m, level, o.mode, 0, (char*)workspace);
   const bool f32 = mode_f32(o.mode), pcg = mode_pcg(o.mode);
   const int vdt = f32 ? MF_F32 : MF_F64;
   // Dirichlet entries of x take b's values; the correction never changes them.
@@ -387,6 +519,23 @@ int vcycle_solve(const mf_mesh* m, int level, const double* b, double* x, void* 
   rc = residual_norm(m, L, MF_F64, b, x, w.r64, w.part, w.result, &ss, &mx, s);
   if (!rc && pcg) rc = launch_fill(MF_F64, w.result + 2, 0.0, 6, s);
   if (rc) return rc;
+  if (mode_minres(o.mode)) {
+    int it = 0;
+    double rel = bnorm > 0.0 ? std::sqrt(ss) / bnorm : std::sqrt(ss);
+    bool converged = false;
+    if (rel <= o.rtol || mx == 0.0) {
+      converged = true;
+    } else {
+      rc = minres_iterate(m, level, lc, tail, b, x, w, o, bnorm, rel, s, &it, &rel, &converged);
+      if (rc) return rc;
+    }
+    if (info) {
+      info->iters = it;
+      info->rel_res = rel;
+      info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return converged ? MF_OK : MF_NOT_CONVERGED;
+  }
   const int64_t nlin = L.lin_blocks();
   int it = 0;
   double rel = 0.0;

@@ -180,7 +180,10 @@ struct TailArgs {
 
 // The tail keeps its levels' vectors in LDS when they fit in kTailLdsMax
 // bytes: three per level (b, x, t), each rounded up to 16 bytes.
-constexpr int kTailLdsMax = 64 * 1024;
+#ifndef MF_TAIL_LDS_MAX
+#define MF_TAIL_LDS_MAX (64 * 1024)
+#endif
+constexpr int kTailLdsMax = MF_TAIL_LDS_MAX;
 MF_HD constexpr int64_t tail_lds_vec(int64_t storage, int elem) { return (storage * elem + 15) / 16 * 16; }
 
 // Plain vector kernels (fill, copy, axpy and the FP32 <-> FP64 pair of the

@@ -90,6 +90,11 @@ int launch_pcg_update(const mf_mesh* m, const Level& L, double* x, double* r, do
 // p = z + beta p; zdtype MF_F32: z is given as the FP32 V-cycle output e and
 // formed as res[1] e (as launch_pcg_zdot forms it).
 int launch_pcg_dir(double* p, const void* z, const double* res, int64_t n, hipStream_t s, int zdtype = MF_F64);
+// y = a y + b x1 + c x2 (x2 nullable) over n entries in nblk blocks of 256
+// threads; part (nullable, 2 nblk doubles) receives zero sums and per-block
+// maxima of |y| for launch_reduce.
+int launch_lin3(double* y, const double* x1, const double* x2, double a, double b, double c, int64_t n, double* part,
+                int nblk, hipStream_t s);
 // result (2 doubles) = (sum, previous result[0]) of part[0, np)
 int launch_reduce_shift(const double* part, int64_t np, double* result, hipStream_t s);
 

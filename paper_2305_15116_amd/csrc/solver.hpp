@@ -12,10 +12,15 @@ namespace mf {
 constexpr int64_t kAlign = 256;
 inline int64_t align_up(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-// Solver modes: bit 0 = FP32 V-cycles (else FP64); bit 1 = preconditioned
-// conjugate gradients around the V-cycle (else iterative refinement).
+// Solver modes 0..5: bit 0 = FP32 V-cycles (else FP64); bit 1 = preconditioned
+// conjugate gradients around the V-cycle; bit 2 = preconditioned MINRES
+// around it (modes 4, 5); neither = iterative refinement.
+constexpr int kNumModes = 6;
 inline bool mode_f32(int mode) { return (mode & 1) != 0; }
 inline bool mode_pcg(int mode) { return (mode & 2) != 0; }
+inline bool mode_minres(int mode) { return (mode & 4) != 0; }
+// Krylov modes need a symmetric (pre == post) V-cycle as the preconditioner.
+inline bool mode_krylov(int mode) { return mode_pcg(mode) || mode_minres(mode); }
 
 struct Workspace {
   std::vector<void*> b, x, t;  // per level
@@ -25,7 +30,13 @@ struct Workspace {
   double* z64 = nullptr;  // PCG: preconditioned residual (== e64 in FP64 mode; in FP32 mode never
                           // stored: z = res[1] e is formed where it is read)
   double* p64 = nullptr;  // PCG: search direction
-  double* q64 = nullptr;  // PCG: A p
+  double* q64 = nullptr;  // PCG: A p; MINRES: A z
+  // MINRES: r64 and v2 hold the last two Lanczos vectors v, z64 and z2 the
+  // preconditioned ones (FP64 z64 == e64), w1 and w2 the last two directions.
+  double* v2 = nullptr;
+  double* z2 = nullptr;
+  double* w1 = nullptr;
+  double* w2 = nullptr;
   double* part = nullptr;
   double* result = nullptr;  // 8 doubles: r.r, max|r|, r.z, previous r.z, p.Ap
   int64_t bytes = 0;
@@ -73,8 +84,16 @@ inline Workspace carve(const mf_mesh* m, int level, int mode, int lc, char* base
     w.p64 = (double*)take(8 * SL);
     w.q64 = (double*)take(8 * SL);
   }
+  if (mode_minres(mode)) {
+    w.z64 = mode_f32(mode) ? (double*)take(8 * SL) : w.e64;
+    w.q64 = (double*)take(8 * SL);
+    w.v2 = (double*)take(8 * SL);
+    w.z2 = (double*)take(8 * SL);
+    w.w1 = (double*)take(8 * SL);
+    w.w2 = (double*)take(8 * SL);
+  }
   const Level& L = m->levels[level];
-  const int64_t np = std::max<int64_t>(L.n_partials(), mode_pcg(mode) ? L.lin_blocks() : 0);
+  const int64_t np = std::max<int64_t>(L.n_partials(), mode_krylov(mode) ? L.lin_blocks() : 0);
   w.part = (double*)take(8 * 2 * (np + 1));
   w.result = (double*)take(8 * 8);
   w.bytes = off;

@@ -525,6 +525,52 @@ int launch_pcg_update(const mf_mesh* m, const Level& L, double* x, double* r, do
   return check_launch();
 }
 
+namespace {
+// MINRES's three-term recurrences: y = a y + b x1 + c x2 (x2 may be null),
+// grid-stride; with part, each block leaves the maximum of |y| over its
+// entries at part[nblk + block] and 0 at part[block] (the layout
+// launch_reduce takes).
+struct Lin3Args {
+  double* y;
+  const double* x1;
+  const double* x2;
+  double a, b, c;
+  int64_t n;
+  double* part;
+  int nblk;
+};
+
+__global__ __launch_bounds__(256) void lin3_kernel(const Lin3Args a) {
+  const int64_t stride = (int64_t)a.nblk * 256;
+  double mx = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < a.n; i += stride) {
+    double v = a.b * a.x1[i];
+    if (a.x2) v = fma(a.c, a.x2[i], v);
+    v = fma(a.a, a.y[i], v);
+    a.y[i] = v;
+    mx = fmax(mx, fabs(v));
+  }
+  if (!a.part) return;
+  mx = wmax(mx);
+  __shared__ double s_mx[4];
+  if ((threadIdx.x & (kWave - 1)) == 0) s_mx[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a.part[blockIdx.x] = 0.0;
+    a.part[a.nblk + blockIdx.x] = fmax(fmax(s_mx[0], s_mx[1]), fmax(s_mx[2], s_mx[3]));
+  }
+}
+}  // namespace
+
+int launch_lin3(double* y, const double* x1, const double* x2, double a, double b, double c, int64_t n, double* part,
+                int nblk, hipStream_t s) {
+  if (n <= 0) return MF_OK;
+  if (nblk < 1) return set_error(MF_EINVAL, "lin3: no blocks");
+  const Lin3Args la{y, x1, x2, a, b, c, n, part, nblk};
+  hipLaunchKernelGGL(lin3_kernel, dim3(nblk), dim3(256), 0, s, la);
+  return check_launch();
+}
+
 int launch_pcg_dir(double* p, const void* z, const double* res, int64_t n, hipStream_t s, int zdtype) {
   if (n <= 0) return MF_OK;
   const VecArgs a = vec_args(p, z, res, n, 0.0);

@@ -40,7 +40,8 @@ def _manufactured(co, ce, L):
 
 @pytest.mark.parametrize("mesh,L,mode", [("cube", 4, 0), ("cube", 4, 1), ("cube", 5, 1), ("square", 6, 0),
                                          ("square", 6, 1), ("cube", 4, 2), ("cube", 5, 3), ("square", 6, 2),
-                                         ("square", 6, 3)])
+                                         ("square", 6, 3), ("cube", 4, 4), ("cube", 5, 5), ("square", 6, 4),
+                                         ("square", 6, 5)])
 def test_manufactured_solution(mesh, L, mode):
     co, ce = W.kuhn_cube() if mesh == "cube" else W.two_triangle_square()
     m, om, s2u, bu, us = _manufactured(co, ce, L)
@@ -67,7 +68,7 @@ def test_manufactured_solution(mesh, L, mode):
     assert np.abs(xu - uh).max() <= 2 * kappa * 1e-10 * np.abs(uh).max()
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3, 4, 5])
 def test_random_mesh_against_oracle_solve(mode):
     co, ce = W.kuhn_cube("random", 5)
     J, t = W.random_affine(3, 8)
@@ -101,7 +102,7 @@ def test_random_mesh_against_oracle_solve(mode):
     assert np.abs(xu - uo).max() <= kappa_bound * 1e-10 * max(1.0, np.abs(uo).max())
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3, 4, 5])
 def test_tail_levels_in_lds_and_in_global_memory(mode):
     """16 triangles at level 5: the one-workgroup bottom of the cycle takes
     levels 2-4 (240, 720 and 2,448 storage points), whose b, x and t need
@@ -200,12 +201,17 @@ def test_cg_rejects_a_non_symmetric_cycle():
     b = torch.ones(s, dtype=torch.float64, device="cuda")
     x = torch.zeros_like(b)
     ws = torch.empty(P.mesh_workspace_bytes(m, 3, 2), dtype=torch.uint8, device="cuda")
-    for mode in (2, 3):
+    for mode in (2, 3, 4, 5):
         with pytest.raises(P.MFError) as e:
             P.vcycle_solve(m, 3, b, x, ws, mode=mode, pre=2, post=1)
         assert e.value.code == P.MF_EINVAL
         with pytest.raises(P.MFError) as e:
             P.batch_create(1, mode=mode, pre=1, post=2)
+        assert e.value.code == P.MF_EINVAL
+    # MINRES is not batched
+    for mode in (4, 5):
+        with pytest.raises(P.MFError) as e:
+            P.batch_create(1, mode=mode)
         assert e.value.code == P.MF_EINVAL
     # refinement takes any sweep counts
     rc, it, rel, _ = P.vcycle_solve(m, 3, b, x, ws, mode=0, pre=2, post=1, rtol=1e-8)
@@ -272,3 +278,51 @@ def test_pcg_needs_fewer_iterations_on_a_stretched_mesh(mode):
         assert rc == P.MF_OK and rel <= 1e-8
         its[md] = it
     assert its[mode] < its[mode - 2]
+
+
+@pytest.mark.parametrize("mode", [4, 5])
+def test_minres_stopped_early_reports_the_true_residual(mode):
+    """MINRES cut off after a few iterations: MF_NOT_CONVERGED, and rel_res
+    is the FP64 residual of the returned x as the oracle's matrix gives it;
+    more iterations give a smaller residual (MINRES minimises sqrt(r . M r),
+    M the V-cycle, over a growing Krylov space)."""
+    co, ce = W.kuhn_cube("random", 7)
+    L = 4
+    m = P.create_macro_mesh(co, ce, L)
+    om = OracleMesh(co, ce, L)
+    s2u = harness.storage_to_unique(P.mesh_dof_keys(m, L), om.keys())
+    s, _ = P.mesh_num_dofs(m, L)
+    b = torch.empty(s, dtype=torch.float64, device="cuda")
+    P.mesh_fill_random(m, L, 35, b)
+    bo = om.keyed_random(35)
+    ws = torch.empty(P.mesh_workspace_bytes(m, L, mode), dtype=torch.uint8, device="cuda")
+    rels = []
+    for k in (2, 4, 8):
+        x = torch.zeros_like(b)
+        rc, it, rel, _ = P.vcycle_solve(m, L, b, x, ws, mode=mode, rtol=1e-14, max_iter=k)
+        torch.cuda.synchronize()
+        assert rc == P.MF_NOT_CONVERGED and it == k
+        xu = np.zeros(om.n)
+        xu[s2u] = x.cpu().numpy()
+        res = np.linalg.norm(bo - om.spmv(xu)) / np.linalg.norm(bo)
+        assert abs(rel - res) <= 1e-6 * res, (k, rel, res)
+        rels.append(res)
+    assert rels[0] > rels[1] > rels[2], rels
+
+
+def test_minres_and_cg_take_similar_iterations():
+    """On this symmetric positive definite operator MINRES with the V-cycle
+    needs about as many iterations as CG with it (both minimise over the same
+    Krylov space, in different norms)."""
+    co, ce = W.kuhn_cube()
+    m, om, s2u, bu, us = _manufactured(co, ce, 5)
+    b = torch.as_tensor(bu[s2u], device="cuda")
+    its = {}
+    for mode in (2, 4, 3, 5):
+        x = torch.zeros_like(b)
+        ws = torch.empty(P.mesh_workspace_bytes(m, 5, mode), dtype=torch.uint8, device="cuda")
+        rc, it, rel, _ = P.vcycle_solve(m, 5, b, x, ws, mode=mode, rtol=1e-10)
+        torch.cuda.synchronize()
+        assert rc == P.MF_OK and rel <= 1e-10
+        its[mode] = it
+    assert abs(its[4] - its[2]) <= 3 and abs(its[5] - its[3]) <= 3, its

@@ -154,3 +154,17 @@ def test_workspace_bytes_account_for_hierarchy():
     b1 = P.mesh_workspace_bytes(m, 5, 1)
     assert b0 >= 8 * 3 * s5 * 8 / 7 * 0.95
     assert b1 < b0
+
+
+def test_workspace_bytes_of_the_krylov_modes():
+    """CG adds two FP64 vectors (p, q); MINRES six (two Lanczos vectors, two
+    preconditioned ones, two directions, A z; one of them is the FP64
+    cycle's output); mode 6 does not exist."""
+    m = P.create_macro_mesh(*W.kuhn_cube(), 5, HOST)
+    s5, _ = P.mesh_num_dofs(m, 5)
+    by = [P.mesh_workspace_bytes(m, 5, k) for k in range(6)]
+    assert by[2] - by[0] >= 2 * 8 * s5 and by[3] - by[1] >= 2 * 8 * s5
+    assert by[4] - by[0] >= 5 * 8 * s5 and by[5] - by[1] >= 6 * 8 * s5
+    with pytest.raises(P.MFError) as e:
+        P.mesh_workspace_bytes(m, 5, 6)
+    assert e.value.code == P.MF_EINVAL
