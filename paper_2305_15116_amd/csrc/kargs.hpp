@@ -135,7 +135,8 @@ constexpr int kJ0Points = 2048;  // points per block of the streaming pass (a mu
 // steps, instead of about a dozen launches per level whose time is latency.
 // The point limit is where one CU stops beating the whole chip: measured on
 // cube and triangle solves, 3D levels of 990 points gain and of 5,814 points
-// lose (the single CU's load bandwidth), 2D levels of 2,145 points gain.
+// lose (the single CU's load bandwidth; also with the level's FP32 vectors
+// in LDS), 2D levels of 2,145 points gain.
 #ifndef MF_TAIL_LEVELS
 #define MF_TAIL_LEVELS 4
 #endif
