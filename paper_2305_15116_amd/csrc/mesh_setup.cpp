@@ -296,7 +296,10 @@ static int build_level(mf_mesh* m, int level, Level& L) {
       double K[4][4];
       if (!metric_stiffness(dim, E, K)) return set_error(MF_EINVAL, "degenerate macro " + std::to_string(c));
       for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 4; ++j) M.K[t][i * 4 + j] = K[i][j];
+        for (int j = 0; j < 4; ++j) {
+          M.K[t][i * 4 + j] = K[i][j];
+          M.Kf[t][i * 4 + j] = (float)K[i][j];
+        }
     }
     // Partial stencil of every support mask: sum, over the (type, local vertex v)
     // incidences of the micro-elements inside the macro that contain a point

@@ -106,7 +106,8 @@ struct MacroDev {
   double inv_diag;      // 1 / interior centre weight
   double wm[16][16];
   float wmf[16][16];
-  double K[6][16];
+  double K[6][16];      // element matrix of each micro-element type (row-major 4 x 4)
+  float Kf[6][16];      // the same in FP32 (FP32 kernels read it without conversions)
 };
 
 // ---------------------------------------------------------------- layout

@@ -18,6 +18,7 @@ struct Prec<double> {
   static __device__ __forceinline__ double w(const MacroDev& M, int mask, int i) { return M.wm[mask][i]; }
   static __device__ __forceinline__ double invd(const MacroDev& M) { return M.inv_diag; }
   static __device__ __forceinline__ double ginv(const double* d, const float*, int g) { return d[g]; }
+  static __device__ __forceinline__ const double* K(const MacroDev& M, int t) { return M.K[t]; }
 };
 
 template <>
@@ -25,6 +26,7 @@ struct Prec<float> {
   static __device__ __forceinline__ float w(const MacroDev& M, int mask, int i) { return M.wmf[mask][i]; }
   static __device__ __forceinline__ float invd(const MacroDev& M) { return M.inv_diagf; }
   static __device__ __forceinline__ float ginv(const double*, const float* f, int g) { return f[g]; }
+  static __device__ __forceinline__ const float* K(const MacroDev& M, int t) { return M.Kf[t]; }
 };
 
 // Ordinary (write-back) stores: partial lines at wave boundaries merge in L2.

@@ -241,7 +241,8 @@ __device__ __forceinline__ void vc3_point(const MacroDev& M, const T* __restrict
   }
   // the sums of the four vertex coefficients are used unscaled and the row
   // scaled by 1/4 once at the end: scaling by powers of two is exact, so this
-  // equals summing mean_T(k) times the element rows
+  // equals summing mean_T(k) times the element rows.  The element matrices
+  // are read in the kernel's precision (FP32 kernels: the macro's FP32 copy).
   T acc = T(0);
 #pragma unroll
   for (int t = 0; t < E.ntypes; ++t) {
@@ -251,11 +252,11 @@ __device__ __forceinline__ void vc3_point(const MacroDev& M, const T* __restrict
       const bool exists = ax >= 0 && ay >= 0 && az >= 0 && ax + ay + az <= N - E.slack[t];
       const int s0 = tet_slot(t, v, 0), s1 = tet_slot(t, v, 1), s2 = tet_slot(t, v, 2), s3 = tet_slot(t, v, 3);
       const T ks = kv[s0] + kv[s1] + kv[s2] + kv[s3];
-      const double* Kt = M.K[t] + 4 * v;
-      T r = T(Kt[0]) * xv[s0];
-      r = fma(T(Kt[1]), xv[s1], r);
-      r = fma(T(Kt[2]), xv[s2], r);
-      r = fma(T(Kt[3]), xv[s3], r);
+      const T* Kt = Prec<T>::K(M, t) + 4 * v;
+      T r = Kt[0] * xv[s0];
+      r = fma(Kt[1], xv[s1], r);
+      r = fma(Kt[2], xv[s2], r);
+      r = fma(Kt[3], xv[s3], r);
       acc = exists ? fma(ks, r, acc) : acc;
     }
   }

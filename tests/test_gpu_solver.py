@@ -326,3 +326,39 @@ def test_minres_and_cg_take_similar_iterations():
         assert rc == P.MF_OK and rel <= 1e-10
         its[mode] = it
     assert abs(its[4] - its[2]) <= 3 and abs(its[5] - its[3]) <= 3, its
+
+
+@pytest.mark.parametrize("mode", [4, 5])
+def test_minres_from_a_nonzero_guess_is_deterministic(mode):
+    """MINRES from a random initial guess on a randomly mapped 2D strip: the
+    oracle's matrix gives a residual within the tolerance, the Dirichlet
+    entries are b's, and a second solve from the same guess is bitwise the
+    same (every reduction has a fixed order)."""
+    co, ce = W.strip_2d(6)
+    J, t = W.random_affine(2, 21)
+    co = W.apply_affine(co, J, t)
+    L = 6
+    m = P.create_macro_mesh(co, ce, L)
+    om = OracleMesh(co, ce, L)
+    s2u = harness.storage_to_unique(P.mesh_dof_keys(m, L), om.keys())
+    s, _ = P.mesh_num_dofs(m, L)
+    b = torch.empty(s, dtype=torch.float64, device="cuda")
+    P.mesh_fill_random(m, L, 37, b)
+    x0 = torch.empty_like(b)
+    P.mesh_fill_random(m, L, 38, x0)
+    ws = torch.empty(P.mesh_workspace_bytes(m, L, mode), dtype=torch.uint8, device="cuda")
+    xs = []
+    for _ in range(2):
+        x = x0.clone()
+        rc, it, rel, _ = P.vcycle_solve(m, L, b, x, ws, mode=mode, rtol=1e-10, max_iter=500)
+        torch.cuda.synchronize()
+        assert rc == P.MF_OK, (it, rel)
+        xs.append(x)
+    assert torch.equal(xs[0], xs[1])
+    bo = om.keyed_random(37)
+    xu = np.zeros(om.n)
+    xu[s2u] = xs[0].cpu().numpy()
+    res = np.linalg.norm(bo - om.spmv(xu)) / np.linalg.norm(bo)
+    assert res <= 1.01e-10
+    bnd = om.boundary()
+    assert np.array_equal(xu[bnd], bo[bnd])
