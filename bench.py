@@ -227,7 +227,10 @@ def solve_bytes(P, m, L, mode, iters, lc=2):
     prolongation e S_{l-1}/S_l + 2e, two post-sweeps 6e.  Outer step per fine
     DoF: refinement x += e and r = b - A x (FP64 48, mixed 56 with the
     scaled cast); CG r.z, direction, A p with p.Ap, x/r update (FP64 104,
-    mixed 108 with the cast); MINRES A z with z.Az 16, the Lanczos
+    mixed 100: r.z and the direction read the FP32 cycle output, 4 bytes
+    less each, and the update also writes the next FP32 preconditioner
+    input, 4; the first input's cast, 12, is set-up);
+    MINRES A z with z.Az 16, the Lanczos
     recurrence 32, v.z 16 (mixed: the scaled cast 12 and z formed in FP64,
     20), the direction recurrence 32 and x += c eta w 24 (FP64 120, mixed
     136).  Set-up: norm of b and the first residual (32), plus one
@@ -237,8 +240,8 @@ def solve_bytes(P, m, L, mode, iters, lc=2):
     S = [P.mesh_num_dofs(m, l)[0] for l in range(L + 1)]
     e = 4 if mode & 1 else 8
     cycle = sum((17 * e + 2 * e * S[l - 1] / S[l]) * S[l] for l in range(lc + 1, L + 1))
-    outer = {0: 48, 1: 56, 2: 104, 3: 108, 4: 120, 5: 136}[mode] * S[L]
-    setup = (32 + (24 if mode & 6 else 0)) * S[L]
+    outer = {0: 48, 1: 56, 2: 104, 3: 100, 4: 120, 5: 136}[mode] * S[L]
+    setup = (32 + (24 if mode & 6 else 0) + (12 if mode == 3 else 0)) * S[L]
     if mode & 4:
         setup += cycle + (24 + (32 if mode & 1 else 16)) * S[L]
     return {"per_iteration": cycle + outer, "per_iteration_B_per_dof": (cycle + outer) / S[L],

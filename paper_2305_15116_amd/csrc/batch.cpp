@@ -294,7 +294,7 @@ void build_plan(mf_batch* B) {
         dmax = std::max(dmax, M->level - M->lc);
       }
     if (!any) continue;
-    if (f32) {
+    if (f32 && !pcg) {
       vector_op(P, corr, dim, kOpScaleF32, MF_F64, [](const Member& M, VecArgs& a) {
         a = vec_args(M.w.b[M.level], M.w.r64, M.w.result, lev(M, M.level).storage, 0.0);
         return true;
@@ -367,8 +367,10 @@ void build_plan(mf_batch* B) {
       reduce_op(P, ra);
     };
     pcg_op(kOpPcgZDot, vdt, [](const Member& M) {
-      return pcg_args(lev(M, M.level), nullptr, M.w.r64, nullptr, nullptr, M.w.x[M.level], M.w.z64, M.w.result,
-                      M.w.part);
+      PcgArgs a = pcg_args(lev(M, M.level), nullptr, M.w.r64, nullptr, nullptr, M.w.x[M.level], M.w.z64, M.w.result,
+                           M.w.part);
+      a.sslot = kSlotScale;
+      return a;
     });
     reduce_corr([](const Member& M) {
       return ReduceArgs{M.w.part, lev(M, M.level).lin_blocks(), M.w.result + 2, nullptr, 1, 0};
@@ -376,6 +378,7 @@ void build_plan(mf_batch* B) {
     for (int dim = 2; dim <= 3; ++dim)
       vector_op(P, corr, dim, kOpPcgDir, vdt, [f32](const Member& M, VecArgs& a) {
         a = vec_args(M.w.p64, f32 ? M.w.x[M.level] : (const void*)M.w.z64, M.w.result, lev(M, M.level).storage, 0.0);
+        a.sslot = kSlotScale;
         return true;
       });
     for (int dim = 2; dim <= 3; ++dim)
@@ -390,8 +393,14 @@ void build_plan(mf_batch* B) {
     reduce_corr([](const Member& M) {
       return ReduceArgs{M.w.part, stencil_partials(lev(M, M.level), MF_F64), M.w.result + 4, nullptr, 0, 0};
     });
-    pcg_op(kOpPcgUpdate, MF_F64, [](const Member& M) {
-      return pcg_args(lev(M, M.level), M.x, M.w.r64, M.w.p64, M.w.q64, nullptr, nullptr, M.w.result, M.w.part);
+    pcg_op(kOpPcgUpdate, MF_F64, [f32](const Member& M) {
+      PcgArgs a = pcg_args(lev(M, M.level), M.x, M.w.r64, M.w.p64, M.w.q64, nullptr, nullptr, M.w.result, M.w.part);
+      if (f32) {
+        // the next FP32 preconditioner input, as vcycle_solve forms it
+        a.r32 = (float*)M.w.b[M.level];
+        a.sout = M.w.result + kSlotScale;
+      }
+      return a;
     });
     reduce_corr([&](const Member& M) {
       return ReduceArgs{M.w.part, lev(M, M.level).lin_blocks(), M.w.result, slot(M), 0, 0};
@@ -443,6 +452,20 @@ void build_plan(mf_batch* B) {
     for (Member* M : resid)
       ra.push_back({ReduceArgs{M->w.part, stencil_partials(lev(*M, M->level), MF_F64), M->w.result, slot(*M), 0, 0}, 1});
     reduce_op(P, ra);
+  }
+  // ---- mixed CG: the first FP32 preconditioner input of the new members and
+  // its scale (the CG update forms the later ones)
+  if (pcg && f32) {
+    for (int dim = 2; dim <= 3; ++dim) {
+      vector_op(P, fresh, dim, kOpScaleF32, MF_F64, [](const Member& M, VecArgs& a) {
+        a = vec_args(M.w.b[M.level], M.w.r64, M.w.result, lev(M, M.level).storage, 0.0);
+        return true;
+      });
+      vector_op(P, fresh, dim, kOpCopy, MF_F64, [](const Member& M, VecArgs& a) {
+        a = vec_args(M.w.result + kSlotScale, M.w.result + 1, nullptr, 1, 0.0);
+        return true;
+      });
+    }
   }
   // ---- CG members whose recurrence met rtol: the true residual, as vcycle_solve
   // recomputes it (into q and result[6..7], which no recurrence reads)

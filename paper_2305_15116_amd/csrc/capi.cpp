@@ -518,6 +518,11 @@ int vcycle_solve(const mf_mesh* m, int level, const double* b, double* x, void* 
   // r = b - A x; PCG scalars start at zero (first direction p = z)
   rc = residual_norm(m, L, MF_F64, b, x, w.r64, w.part, w.result, &ss, &mx, s);
   if (!rc && pcg) rc = launch_fill(MF_F64, w.result + 2, 0.0, 6, s);
+  if (!rc && pcg && f32) {
+    // the first FP32 preconditioner input; the CG update forms the later ones
+    rc = launch_scale_to_f32(w.r64, (float*)w.b[level], w.result, L.storage, s);
+    if (!rc) rc = launch_copy(MF_F64, w.result + kSlotScale, w.result + 1, 1, s);
+  }
   if (rc) return rc;
   if (mode_minres(o.mode)) {
     int it = 0;
@@ -560,7 +565,7 @@ int vcycle_solve(const mf_mesh* m, int level, const double* b, double* x, void* 
     }
     if (it >= o.max_iter) break;
     // preconditioner / correction: one V-cycle on r from zero
-    if (f32) {
+    if (f32 && !pcg) {
       // scale r by its max norm before the cast so FP32 keeps its relative precision
       rc = launch_scale_to_f32(w.r64, (float*)w.b[level], w.result, L.storage, s);
     }
@@ -573,13 +578,18 @@ int vcycle_solve(const mf_mesh* m, int level, const double* b, double* x, void* 
       if (!rc) rc = residual_norm(m, L, MF_F64, b, x, w.r64, w.part, w.result, &ss, &mx, s);
     } else {
       // conjugate gradients preconditioned by the V-cycle; scalars stay on the device
-      rc = launch_pcg_zdot(m, L, vdt, w.r64, w.x[level], w.z64, w.result, w.part, s);
+      // FP32 cycles: z = s e with s = the scale the input was formed with
+      rc = launch_pcg_zdot(m, L, vdt, w.r64, w.x[level], w.z64, w.result, w.part, s, kSlotScale);
       if (!rc) rc = launch_reduce_shift(w.part, nlin, w.result + 2, s);                // r.z, previous r.z
       if (!rc)
-        rc = launch_pcg_dir(w.p64, f32 ? w.x[level] : (const void*)w.z64, w.result, L.storage, s, vdt);  // p = z + beta p
+        rc = launch_pcg_dir(w.p64, f32 ? w.x[level] : (const void*)w.z64, w.result, L.storage, s, vdt,
+                            kSlotScale);  // p = z + beta p
       if (!rc) rc = launch_stencil(m, L, MF_F64, kApplyDot, w.p64, w.q64, nullptr, 0.0, w.part, s);
       if (!rc) rc = launch_reduce(w.part, stencil_partials(L, MF_F64), w.result + 4, s);       // p.Ap
-      if (!rc) rc = launch_pcg_update(m, L, x, w.r64, w.p64, w.q64, w.result, w.part, s);
+      // x, r and, in mixed mode, the next FP32 preconditioner input
+      if (!rc)
+        rc = launch_pcg_update(m, L, x, w.r64, w.p64, w.q64, w.result, w.part, s,
+                               f32 ? (float*)w.b[level] : nullptr, f32 ? w.result + kSlotScale : nullptr);
       if (!rc) rc = launch_reduce(w.part, nlin, w.result, s);                          // r.r, max|r|
       double out[2] = {0.0, 0.0};
       if (!rc) rc = sync_result(w.result, out, s);

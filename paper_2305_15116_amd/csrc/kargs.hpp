@@ -195,7 +195,8 @@ struct VecArgs {
   const double* res;  // result pair (sum of squares, max |.|) of a reduction
   int64_t n;
   double a;
-  int nblk;  // grid-stride blocks of this request
+  int nblk;   // grid-stride blocks of this request
+  int sslot;  // PCG direction: res slot of the FP32 preconditioner's scale (1, or 8 in mixed CG)
 };
 
 // reduce_kernel: one block per request.
@@ -224,8 +225,10 @@ struct PcgArgs {
   double* z;            // zdot: z = s e (not written when z == e)
   const double* res;    // scalars
   double* part;         // sums at [0, nblk), maxima at [nblk, 2 nblk)
+  float* r32;           // update (nullable): the next preconditioner input, float(r / res[1])
+  double* sout;         // update with r32: receives res[1], the scale r32 was formed with
   int nblk;
-  int pad_;
+  int sslot;            // zdot: res slot of the FP32 preconditioner's scale s (1, or 8 in mixed CG)
 };
 
 inline int vec_blocks(int64_t n) {
@@ -402,12 +405,12 @@ inline int tail_levels(const mf_mesh* m, int level, int lc) {
 }
 
 inline VecArgs vec_args(void* y, const void* x, const double* res, int64_t n, double a) {
-  return VecArgs{y, x, res, n, a, vec_blocks(n)};
+  return VecArgs{y, x, res, n, a, vec_blocks(n), 1};
 }
 
 inline PcgArgs pcg_args(const Level& L, double* x, double* r, double* p, const double* q, const void* e, double* z,
                         const double* res, double* part) {
-  return PcgArgs{L.storage, L.dev.own_bits, x, r, p, q, e, z, res, part, (int)L.lin_blocks(), 0};
+  return PcgArgs{L.storage, L.dev.own_bits, x, r, p, q, e, z, res, part, nullptr, nullptr, (int)L.lin_blocks(), 1};
 }
 inline int pcg_blocks(const Level& L) { return (int)L.lin_blocks(); }
 

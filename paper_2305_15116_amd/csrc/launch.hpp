@@ -80,16 +80,18 @@ int launch_scale_to_f32(const double* r, float* b, const double* res, int64_t n,
 int launch_axpy_f32(double* x, const float* e, const double* res, int64_t n, hipStream_t s);
 
 // Preconditioned conjugate gradients (scalars in res, see PcgArgs):
-// z = s e and partials of r . z (edtype: type of e; z == e: not written);
-// x += alpha p, r -= alpha q and partials of r . r, max |r|; p = z + beta p.
-// Partials: L.lin_blocks() slots.
+// z = s e (s = res[sslot] for FP32 e) and partials of r . z (edtype: type of
+// e; z == e: not written); x += alpha p, r -= alpha q and partials of r . r,
+// max |r|, with r32 also r32 = float(r / res[1]) and *sout = res[1] (both or
+// neither); p = z + beta p.  Partials: L.lin_blocks() slots.
 int launch_pcg_zdot(const mf_mesh* m, const Level& L, int edtype, const double* r, const void* e, double* z,
-                    const double* res, double* part, hipStream_t s);
+                    const double* res, double* part, hipStream_t s, int sslot = 1);
 int launch_pcg_update(const mf_mesh* m, const Level& L, double* x, double* r, double* p, const double* q,
-                      const double* res, double* part, hipStream_t s);
+                      const double* res, double* part, hipStream_t s, float* r32 = nullptr, double* sout = nullptr);
 // p = z + beta p; zdtype MF_F32: z is given as the FP32 V-cycle output e and
-// formed as res[1] e (as launch_pcg_zdot forms it).
-int launch_pcg_dir(double* p, const void* z, const double* res, int64_t n, hipStream_t s, int zdtype = MF_F64);
+// formed as res[sslot] e (as launch_pcg_zdot forms it).
+int launch_pcg_dir(double* p, const void* z, const double* res, int64_t n, hipStream_t s, int zdtype = MF_F64,
+                   int sslot = 1);
 // y = a y + b x1 + c x2 (x2 nullable) over n entries in nblk blocks of 256
 // threads; part (nullable, 2 nblk doubles) receives zero sums and per-block
 // maxima of |y| for launch_reduce.

@@ -38,7 +38,10 @@ struct Workspace {
   double* w1 = nullptr;
   double* w2 = nullptr;
   double* part = nullptr;
-  double* result = nullptr;  // 8 doubles: r.r, max|r|, r.z, previous r.z, p.Ap
+  // 16 doubles: [0] r.r, [1] max|r|, [2] r.z, [3] previous r.z, [4] p.Ap,
+  // [6..7] a recomputed residual's pair, [8] mixed CG: the scale of the FP32
+  // preconditioner input in use (kSlotScale)
+  double* result = nullptr;
   int64_t bytes = 0;
 };
 
@@ -95,11 +98,16 @@ inline Workspace carve(const mf_mesh* m, int level, int mode, int lc, char* base
   const Level& L = m->levels[level];
   const int64_t np = std::max<int64_t>(L.n_partials(), mode_krylov(mode) ? L.lin_blocks() : 0);
   w.part = (double*)take(8 * 2 * (np + 1));
-  w.result = (double*)take(8 * 8);
+  w.result = (double*)take(8 * 16);
   w.bytes = off;
   return w;
 }
 
 inline int default_coarse(int level) { return std::min(2, level); }
+
+// Mixed CG keeps the scale of its FP32 preconditioner input here: the update
+// forms the next input as r / max|r| of the residual before it, so when the
+// preconditioner runs, result[1] already holds the next maximum.
+constexpr int kSlotScale = 8;
 
 }  // namespace mf

@@ -257,11 +257,13 @@ __device__ __forceinline__ double wmax(double v) {
 }
 
 // Grid-stride over the storage index, nblk blocks of 256 threads.  KIND
-// kOpPcgZDot: z = s e with s = res[1] for FP32 e (the preconditioner solved
-// for r / max|r|) and 1 for FP64 e, partials of r . z.  KIND kOpPcgUpdate:
+// kOpPcgZDot: z = s e with s = res[sslot] for FP32 e (the preconditioner
+// solved for r / s) and 1 for FP64 e, partials of r . z.  KIND kOpPcgUpdate:
 // alpha = res[2] / res[4], x += alpha p, r -= alpha q, partials of r . r and
-// max |r|.  Sums count each unique DoF once (owner bits); each block leaves
-// one partial, its four waves summed in a fixed order.
+// max |r|; with r32, also the next FP32 preconditioner input r / res[1]
+// (res[1] = max |r| of the residual before this update) and *sout = res[1].
+// Sums count each unique DoF once (owner bits); each block leaves one
+// partial, its four waves summed in a fixed order.
 constexpr int kPcgU = 4;
 
 template <int KIND, typename TE>
@@ -276,7 +278,7 @@ __global__ __launch_bounds__(256) void pcg_lin_kernel(const Launch<PcgArgs> L) {
   // taken in index order, so the sums are those of a one-element loop.
   const int64_t i0 = (int64_t)blk * 256 + threadIdx.x;
   if (KIND == kOpPcgZDot) {
-    const double sc = sizeof(TE) == 4 ? a.res[1] : 1.0;
+    const double sc = sizeof(TE) == 4 ? a.res[a.sslot] : 1.0;
     const TE* e = (const TE*)a.e;
     const bool wz = a.z != nullptr && (const void*)a.z != a.e;
     for (int64_t i = i0; i < a.n; i += kPcgU * stride) {
@@ -299,6 +301,8 @@ __global__ __launch_bounds__(256) void pcg_lin_kernel(const Launch<PcgArgs> L) {
     }
   } else {
     const double alpha = a.res[2] / a.res[4];
+    const double c32 = a.r32 ? 1.0 / a.res[1] : 0.0;  // as the scaled cast forms it
+    if (a.r32 && blk == 0 && threadIdx.x == 0) *a.sout = a.res[1];
     for (int64_t i = i0; i < a.n; i += kPcgU * stride) {
       double xv[kPcgU], pv[kPcgU], qv[kPcgU], rv[kPcgU];
       uint32_t ow[kPcgU];
@@ -318,6 +322,7 @@ __global__ __launch_bounds__(256) void pcg_lin_kernel(const Launch<PcgArgs> L) {
         a.x[j] = fma(alpha, pv[u], xv[u]);
         const double rn = fma(-alpha, qv[u], rv[u]);
         a.r[j] = rn;
+        if (a.r32) a.r32[j] = (float)(c32 * rn);
         if ((ow[u] >> (j & 31)) & 1u) ss = fma(rn, rn, ss);
         mx = fmax(mx, fabs(rn));
       }
@@ -349,7 +354,7 @@ __global__ __launch_bounds__(256) void pcg_dir_kernel(const Launch<VecArgs> L) {
   const int64_t stride = (int64_t)a.nblk * 256;
   double* p = (double*)a.y;
   const TZ* zs = (const TZ*)a.x;
-  const double sc = sizeof(TZ) == 4 ? a.res[1] : 1.0;
+  const double sc = sizeof(TZ) == 4 ? a.res[a.sslot] : 1.0;
   auto z = [&](int64_t i) { return sizeof(TZ) == 4 ? sc * (double)zs[i] : (double)zs[i]; };
   if (a.res[3] == 0.0) {
     // first direction: p = z (p holds no earlier direction and is never read)
@@ -510,18 +515,24 @@ void run_pcg_point(int dim, int dtype, const Launch<PcgArgs>& l, hipStream_t s) 
 }  // namespace
 
 int launch_pcg_zdot(const mf_mesh* m, const Level& L, int edtype, const double* r, const void* e, double* z,
-                    const double* res, double* part, hipStream_t s) {
+                    const double* res, double* part, hipStream_t s, int sslot) {
   const int nwg = pcg_blocks(L);
   if (nwg == 0) return MF_OK;
-  run_pcg_point<kOpPcgZDot>(m->dim, edtype, single(pcg_args(L, nullptr, (double*)r, nullptr, nullptr, e, z, res, part), nwg), s);
+  PcgArgs a = pcg_args(L, nullptr, (double*)r, nullptr, nullptr, e, z, res, part);
+  a.sslot = sslot;
+  run_pcg_point<kOpPcgZDot>(m->dim, edtype, single(a, nwg), s);
   return check_launch();
 }
 
 int launch_pcg_update(const mf_mesh* m, const Level& L, double* x, double* r, double* p, const double* q,
-                      const double* res, double* part, hipStream_t s) {
+                      const double* res, double* part, hipStream_t s, float* r32, double* sout) {
   const int nwg = pcg_blocks(L);
   if (nwg == 0) return MF_OK;
-  run_pcg_point<kOpPcgUpdate>(m->dim, MF_F64, single(pcg_args(L, x, r, p, q, nullptr, nullptr, res, part), nwg), s);
+  if ((r32 == nullptr) != (sout == nullptr)) return set_error(MF_EINVAL, "pcg update: r32 and sout go together");
+  PcgArgs a = pcg_args(L, x, r, p, q, nullptr, nullptr, res, part);
+  a.r32 = r32;
+  a.sout = sout;
+  run_pcg_point<kOpPcgUpdate>(m->dim, MF_F64, single(a, nwg), s);
   return check_launch();
 }
 
@@ -571,9 +582,10 @@ int launch_lin3(double* y, const double* x1, const double* x2, double a, double 
   return check_launch();
 }
 
-int launch_pcg_dir(double* p, const void* z, const double* res, int64_t n, hipStream_t s, int zdtype) {
+int launch_pcg_dir(double* p, const void* z, const double* res, int64_t n, hipStream_t s, int zdtype, int sslot) {
   if (n <= 0) return MF_OK;
-  const VecArgs a = vec_args(p, z, res, n, 0.0);
+  VecArgs a = vec_args(p, z, res, n, 0.0);
+  a.sslot = sslot;
   if (zdtype == MF_F32) hipLaunchKernelGGL(pcg_dir_kernel<float>, dim3(a.nblk), dim3(256), 0, s, single(a, a.nblk));
   else hipLaunchKernelGGL(pcg_dir_kernel<double>, dim3(a.nblk), dim3(256), 0, s, single(a, a.nblk));
   return check_launch();
